@@ -1,0 +1,196 @@
+"""Seeded synthetic problem definitions.
+
+This module only describes problems: mesh sizes, angular-mesh recipes,
+per-cell cross sections drawn from seeded generators, source, inflow and
+detector boxes, solver options.  It holds none of the method's arithmetic
+(no quadrature, no operators, no right-hand sides), so that both the HIP
+library and the CPU oracle consume the same inputs without sharing code.
+
+The paper's own experiments use a Gmsh cube that is not available; every
+workload here is a structured Cartesian cube or square with cross sections
+from the recipes below (the recipes are listed in the design notes).
+"""
+from dataclasses import dataclass, field, replace
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclass
+class AngularSpec:
+    """Uniform refinement to ``base_level``; optionally ``extra_levels`` more
+    inside a cone of ``cone_half_angle_deg`` around ``cone_axis`` with the
+    two-irregularity closure."""
+    base_level: int = 1
+    cone_axis: Tuple[float, float, float] = (1.0, 0.0, 0.0)
+    cone_half_angle_deg: float = 0.0
+    extra_levels: int = 0
+    closure: bool = True
+
+
+@dataclass
+class Inflow:
+    """Boundary data on face (axis, side): kind 'iso' (isotropic value) or
+    'beam' (unit current per area along ``direction``).  ``lo``/``hi`` bound
+    the cell indices on the face (the face axis itself is ignored)."""
+    kind: str = "iso"
+    axis: int = 0
+    side: int = 0
+    lo: Tuple[int, int, int] = (0, 0, 0)
+    hi: Tuple[int, int, int] = (10 ** 6, 10 ** 6, 10 ** 6)
+    value: float = 1.0
+    direction: Tuple[float, float, float] = (1.0, 0.0, 0.0)
+
+
+@dataclass
+class Problem:
+    name: str
+    dim: int
+    n: Tuple[int, int, int]
+    angular: AngularSpec
+    sigma_t: np.ndarray
+    sigma_s: np.ndarray
+    hg_g: float
+    order: int                       # outer (full) Legendre order L
+    mg_orders: List[int]             # per angular level T_0 .. T_L (coarsest first)
+    q_cell: np.ndarray               # isotropic volume source per cell (per steradian)
+    inflow: Optional[Inflow] = None
+    detector: Optional[Tuple[Tuple[int, int, int], Tuple[int, int, int]]] = None
+    restart: int = 10
+    tol: float = 1e-8
+    nu_pre: int = 1
+    nu_post: int = 1
+    nu_coarse: int = 10
+    length: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    fd_cells: Optional[np.ndarray] = None
+    extras: dict = field(default_factory=dict)
+
+    @property
+    def cells(self):
+        return int(np.prod(self.n[:self.dim]))
+
+    def moments(self, order=None):
+        """HG Legendre coefficients f_n = g^n, n <= order (plain truncation)."""
+        L = self.order if order is None else order
+        return np.array([self.hg_g ** k for k in range(L + 1)], dtype=np.float64)
+
+    def with_sigma(self, sigma_t, sigma_s):
+        return replace(self, sigma_t=np.asarray(sigma_t, float), sigma_s=np.asarray(sigma_s, float))
+
+
+def lognormal_sigma(ncells, median, log_sd, seed):
+    """sigma_t,j = median * exp(log_sd * z_j), z = standard normals from
+    ``numpy.random.default_rng(seed)`` in cell order j = ix + nx (iy + ny iz)."""
+    z = np.random.default_rng(seed).standard_normal(ncells)
+    return median * np.exp(log_sd * z)
+
+
+def checkerboard_mask(n, block):
+    """1 where the block parity (bx + by + bz) mod 2 is even, else 0."""
+    nx, ny, nz = n
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    par = (ix // block + iy // block + iz // block) % 2
+    return (par == 0).ravel().astype(np.float64)
+
+
+def box_mask(n, dim, lo, hi):
+    nx, ny, nz = (tuple(n) + (1, 1))[:3]
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = [ix.ravel(), iy.ravel(), iz.ravel()]
+    ok = np.ones(nx * ny * nz, dtype=bool)
+    for a in range(dim):
+        ok &= (c[a] >= lo[a]) & (c[a] <= hi[a])
+    return ok.astype(np.float64)
+
+
+def central_box(n):
+    """Cells [n/2-2, n/2+1] on each axis (a 4-cell-wide central box)."""
+    return tuple(k // 2 - 2 for k in n), tuple(k // 2 + 1 for k in n)
+
+
+def fd_cells(ncells, seed, count=20):
+    return np.random.default_rng(seed + 1).choice(ncells, count, replace=False)
+
+
+# ------------------------------------------------------------------ configs
+
+def config1():
+    """2-D unit square, 16x16 cells, angular level 1 (32 patches), HG g=0.9
+    at L=8, sigma_t=10, c=0.99, isotropic unit inflow on x=0, GMRES(20)."""
+    n = (16, 16, 1)
+    C = 256
+    st = np.full(C, 10.0)
+    return Problem("cfg1-2d-16x16-ang1-L8", 2, n, AngularSpec(1), st, 0.99 * st, 0.9, 8,
+                   [8, 8], np.zeros(C), Inflow("iso", 0, 0, value=1.0), restart=20)
+
+
+def config2(n=32):
+    """3-D unit cube, 32^3 cells, angular level 2 (128 patches), HG g=0.95 at
+    L=16, lognormal sigma_t (median 5, log-sd 1.0, seed 0), c=0.98, unit
+    source in the central 4^3 box, vacuum, GMRES(10)."""
+    nn = (n, n, n)
+    C = n ** 3
+    st = lognormal_sigma(C, 5.0, 1.0, 0)
+    lo, hi = central_box(nn)
+    return Problem(f"cfg2-3d-{n}^3-ang2-L16", 3, nn, AngularSpec(2), st, 0.98 * st, 0.95, 16,
+                   [16, 16, 16], box_mask(nn, 3, lo, hi), None)
+
+
+def config3(n=48):
+    """3-D cube, 48^3 cells, angular level 3 (512 patches), HG g=0.98 at
+    L=32, coarse MG levels at L=8, checkerboard of 8^3 blocks
+    (sigma_t 1 / 20, c 0.999 / 0.9), central unit source, vacuum."""
+    nn = (n, n, n)
+    m = checkerboard_mask(nn, 8)
+    st = np.where(m > 0, 1.0, 20.0)
+    c = np.where(m > 0, 0.999, 0.9)
+    lo, hi = central_box(nn)
+    return Problem(f"cfg3-3d-{n}^3-ang3-L32", 3, nn, AngularSpec(3), st, c * st, 0.98, 32,
+                   [8, 8, 8, 32], box_mask(nn, 3, lo, hi), None)
+
+
+def config4(n=32):
+    """3-D cube, 32^3, angular level 2, HG g=0.95 at L=16, lognormal sigma_t
+    (median 5, log-sd 0.5, seed 1), c=0.95, unit beam along +x on a 4x4
+    patch of x=0, detector box of 4^3 cells at the far side."""
+    nn = (n, n, n)
+    C = n ** 3
+    st = lognormal_sigma(C, 5.0, 0.5, 1)
+    lo = (0, n // 2 - 2, n // 2 - 2)
+    hi = (0, n // 2 + 1, n // 2 + 1)
+    det = ((n - 4, n // 2 - 2, n // 2 - 2), (n - 1, n // 2 + 1, n // 2 + 1))
+    return Problem(f"cfg4-3d-{n}^3-ang2-L16-beam", 3, nn, AngularSpec(2), st, 0.95 * st, 0.95, 16,
+                   [16, 16, 16], np.zeros(C), Inflow("beam", 0, 0, lo, hi, 1.0, (1.0, 0.0, 0.0)),
+                   detector=det, fd_cells=fd_cells(C, 1))
+
+
+def config5(n=32):
+    """3-D cube, 32^3, angular level 2 plus 3 levels in a 15-degree cone
+    around +x (two-irregular), HG g=0.99 at L=64, MG orders 16 then 4,
+    lognormal sigma_t (median 10, log-sd 0.7, seed 2), c=0.99, beam as in
+    the differentiation config, detector at the far side."""
+    nn = (n, n, n)
+    C = n ** 3
+    st = lognormal_sigma(C, 10.0, 0.7, 2)
+    lo = (0, n // 2 - 2, n // 2 - 2)
+    hi = (0, n // 2 + 1, n // 2 + 1)
+    det = ((n - 4, n // 2 - 2, n // 2 - 2), (n - 1, n // 2 + 1, n // 2 + 1))
+    return Problem(f"cfg5-3d-{n}^3-cone-L64", 3, nn, AngularSpec(2, (1.0, 0.0, 0.0), 15.0, 3, True),
+                   st, 0.99 * st, 0.99, 64, [4, 4, 4, 16, 16, 16], np.zeros(C),
+                   Inflow("beam", 0, 0, lo, hi, 1.0, (1.0, 0.0, 0.0)), detector=det,
+                   fd_cells=fd_cells(C, 2))
+
+
+def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=True, source=True,
+                  mg_orders=None, restart=10):
+    """Small random heterogeneous problem for parity tests."""
+    nn = (n, n, n if dim == 3 else 1)
+    C = int(np.prod(nn[:dim]))
+    rng = np.random.default_rng(seed)
+    st = rng.uniform(0.5, 4.0, C)
+    ss = c * st * rng.uniform(0.8, 1.0, C)
+    q = rng.uniform(0.0, 1.0, C) if source else np.zeros(C)
+    mg = mg_orders if mg_orders is not None else [order] * (level + 1)
+    return Problem(f"small-{dim}d-{n}-ang{level}-L{order}-s{seed}", dim, nn, AngularSpec(level),
+                   st, ss, g, order, mg, q, Inflow("iso", 0, 0, value=1.0) if inflow else None,
+                   restart=restart)

@@ -1,0 +1,120 @@
+"""Pins of the oracle's multigrid preconditioner and GMRES."""
+import numpy as np
+import pytest
+
+from oracle import angular as ang
+from oracle import spatial as sp
+from oracle import multigrid as mgm
+from oracle import krylov
+from paper_2010_04559_amd import inputs
+from oracle_problem import OracleProblem
+
+
+def test_gmres_on_dense_system():
+    rng = np.random.default_rng(0)
+    n = 60
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3
+    b = rng.standard_normal(n)
+    ref = np.linalg.solve(A, b)
+    for M in (lambda r: r, lambda r: r / np.diag(A)):
+        res = krylov.gmres(lambda x: A @ x, M, b, 1e-12, 7, 500)
+        assert res.converged
+        assert np.abs(res.x - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def _small_mg(dim=2, n=3, level=1, order=6, g=0.9, seed=0, nu_coarse=10):
+    grid = sp.Grid(dim, (n,) * dim)
+    rng = np.random.default_rng(seed)
+    st = rng.uniform(0.5, 3.0, grid.C)
+    ss = 0.9 * st
+    mesh = ang.AngularMesh.uniform(level)
+    return mgm.AngularMG(grid, mesh, st, ss, ang.hg_moments(g, order), [order] * (level + 1),
+                         nu_coarse=nu_coarse)
+
+
+def test_coarse_gauss_seidel_converges_to_coarse_solve():
+    mg = _small_mg()
+    lv0 = mg.levels[0]
+    f = np.random.default_rng(2).standard_normal(lv0.A * lv0.grid.S)
+    ref = np.linalg.solve(lv0.dense(lv0.apply_A), f)
+    x = mg.coarse_gs(f, 40)
+    assert np.abs(x - ref).max() < 1e-11 * np.abs(ref).max()
+    xa = mg.coarse_gs(f, 40, adjoint=True)
+    refa = np.linalg.solve(lv0.dense(lv0.apply_AT), f)
+    assert np.abs(xa - refa).max() < 1e-11 * np.abs(refa).max()
+
+
+def test_one_gauss_seidel_sweep_is_block_lower_solve():
+    """One sweep from zero solves the block-lower-triangular part of A_0 in
+    visiting order: check against an explicit forward substitution built
+    from the dense matrix and the visiting order."""
+    mg = _small_mg(n=2, level=0)
+    lv0 = mg.levels[0]
+    g = lv0.grid
+    A = lv0.dense(lv0.apply_A)
+    order = []
+    for o in range(8):
+        for J in g.sweep_planes(ang.octant_signs(o)):
+            for j in J:
+                order.append([(3 * o + m) * g.S + j * g.ns + i for m in range(3) for i in range(g.ns)])
+    f = np.random.default_rng(3).standard_normal(A.shape[0])
+    x = np.zeros_like(f)
+    for blk in order:
+        rhs = f[blk] - A[blk] @ x + A[np.ix_(blk, blk)] @ x[blk]
+        x[blk] = np.linalg.solve(A[np.ix_(blk, blk)], rhs)
+    assert np.abs(mg.coarse_gs(f, 1) - x).max() < 1e-12 * np.abs(x).max()
+
+
+def test_vcycle_is_linear_and_single_level_is_gs():
+    mg = _small_mg()
+    n = mg.levels[-1].A * mg.grid.S
+    rng = np.random.default_rng(4)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    lhs = mg.vcycle(2.5 * x + y)
+    assert np.abs(lhs - 2.5 * mg.vcycle(x) - mg.vcycle(y)).max() < 1e-12 * np.abs(lhs).max()
+    one = _small_mg(level=0)
+    r = rng.standard_normal(one.levels[0].A * one.grid.S)
+    assert np.array_equal(one.vcycle(r), one.coarse_gs(r))
+
+
+def test_vcycle_matches_explicit_two_grid_formula():
+    """Fig. lmg on two levels with nu_pre = nu_post = 1, written as matrices:
+    phi1 = L^-1 f, r = f - A phi1, phi = phi1 + P G R r,
+    z = L^-1 (S phi + f), with G the coarse Gauss-Seidel map."""
+    mg = _small_mg(n=2)
+    lv = mg.levels[1]
+    L = lv.dense(lv.apply_L)
+    S = lv.dense(lv.apply_S)
+    A = L - S
+    P = np.kron(mg.P[1], np.eye(mg.grid.S))
+    lv0 = mg.levels[0]
+    G = lv0.dense(mg.coarse_gs)
+    Li = np.linalg.inv(L)
+    f = np.random.default_rng(5).standard_normal(A.shape[0])
+    phi = Li @ f
+    phi = phi + P @ G @ P.T @ (f - A @ phi)
+    z = Li @ (S @ phi + f)
+    assert np.abs(mg.vcycle(f) - z).max() < 1e-10 * np.abs(z).max()
+
+
+def test_mg_gmres_matches_dense_solve():
+    prob = inputs.small_problem(dim=2, n=3, level=1, g=0.9, order=8, c=0.95, seed=3)
+    op = OracleProblem(prob)
+    b = op.rhs()
+    res = krylov.gmres(op.outer.apply_A, op.mg.vcycle, b, 1e-12, prob.restart)
+    assert res.converged
+    ref = np.linalg.solve(op.outer.dense(op.outer.apply_A), b)
+    assert np.abs(res.x - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_mg_needs_fewer_iterations_than_single_grid():
+    """Trend only (parity unpinned: the paper's counts are BiCGStab with
+    Fokker-Planck moments): for forward-peaked scatter the V-cycle beats the
+    single sweep preconditioner (Table 1, Section 5.4)."""
+    prob = inputs.small_problem(dim=2, n=4, level=2, g=0.95, order=12, c=0.99, seed=1)
+    op = OracleProblem(prob)
+    b = op.rhs()
+    mgres = krylov.gmres(op.outer.apply_A, op.mg.vcycle, b, 1e-8, 10)
+    sgres = krylov.gmres(op.outer.apply_A, op.outer.sweep, b, 1e-8, 10)
+    assert mgres.converged and sgres.converged
+    assert mgres.iters < sgres.iters
