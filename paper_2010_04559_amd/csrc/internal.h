@@ -1,0 +1,105 @@
+// Internal declarations shared by the library's host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tr {
+
+// Per-ordinate data of an angular level.
+struct alignas(16) OrdInfo {
+  double c[3];   // |Omega_xi| / h_xi
+  double a[3];   // |Omega_xi|
+  int flip;      // bit xi set when Omega_xi < 0
+  int patch;
+};
+
+struct Grid {
+  int dim, ns;
+  int n[3];
+  double h[3];
+  double vol;         // cell volume
+  long long C, S;     // cells, spatial dofs
+};
+
+// Sweep schedule: cells of the (+,+,+) orientation grouped by diagonal
+// plane; a cell is packed as ix | iy << 10 | iz << 20.
+struct Planes {
+  const int *cells;
+  const int *off;     // [nplanes + 1]
+  int nplanes;
+  int max_plane;
+};
+
+template <typename T>
+struct SweepArgs {
+  const T *f;           // [A][S] right-hand side in ordinate form
+  const T *s;           // [A][S] scatter moments G u (may be null)
+  T *u;                 // [A][S] ordinate values (output)
+  const double *sig_t, *sig_s;
+  const OrdInfo *ord;
+  Planes pl;
+  Grid g;
+};
+
+// ------------------------------------------------------------- launchers
+template <typename T>
+void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st);
+
+void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t,
+                      const double *sig_s, const OrdInfo *ord, const Planes &pl, const int *plane_off_host,
+                      const Grid &g, int nu, const int *octant_order, bool adjoint, hipStream_t st);
+
+// out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * in[3p+m][s]
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
+                    hipStream_t st);
+
+// Restriction to level l-1: fc[p] = sum_children R_c (sigma_s N (s_new - s_prev))_c
+// (apply_sn = 0: plain fc[p] = sum_children R_c in_c).
+template <typename Tin, typename Tout>
+void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,
+                     const int *n_child, int Pc, const double *sig_s, bool apply_sn, const Grid &g,
+                     hipStream_t st);
+
+// Prolongation: uf[c] (+)= P_c uc[owner(c)]
+template <typename Tin, typename Tout>
+void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *owner, int Pf, long long S, bool add,
+                    hipStream_t st);
+
+// y = L x - sigma_s N s  (canonical FP64, s = S~ x); adjoint: L^T x - sigma_s N s
+void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
+                  const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st);
+
+// out[a][j][i] = sigma_s[j] vol Nshape(in[a][j][.])[i]
+template <typename T>
+void launch_scale_sn(const T *in, T *out, const double *sig_s, int A, const Grid &g, hipStream_t st);
+
+void launch_rhs_volume(double *b, const double *q, const double *ipsi, int A, const Grid &g, hipStream_t st);
+void launch_rhs_face(double *b, const double *coef, const int *cells, int ncells, const double *face_int, int A,
+                     const Grid &g, hipStream_t st);
+void launch_detector(double *w, const double *ipsi, int A, const Grid &g, const int lo[3], const int hi[3],
+                     hipStream_t st);
+void launch_grad_t(const double *lam, const double *phi, const double *w, int P, const Grid &g, double *gt,
+                   hipStream_t st);
+void launch_grad_s(const double *lam, const double *t, int A, const Grid &g, double *gs, hipStream_t st);
+
+// BLAS-1 (FP64) and helpers
+void launch_dot_partial(const double *x, const double *y, long long n, double *partial, int nblocks,
+                        hipStream_t st);
+void launch_dot_final(const double *partial, int nblocks, double *out, hipStream_t st);
+void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st);
+void launch_scal(long long n, double a, double *x, hipStream_t st);
+void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st);
+template <typename T>
+void launch_fill(T *x, long long n, T v, hipStream_t st);
+template <typename Tin, typename Tout>
+void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st);
+
+// C[M][N] = A[M][K] * B[K][N]   (row-major; ld of B and C is N)
+template <typename T>
+void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st);
+
+}  // namespace tr

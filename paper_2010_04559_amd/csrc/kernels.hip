@@ -1,0 +1,859 @@
+// Transport kernels for CDNA4 (gfx950): the ordinate-space DG transport
+// sweep, the coarsest-level block Gauss-Seidel sweep, the problem-operator
+// apply, basis conversions, inter-level transfers, sources and BLAS-1.
+//
+// Ordinate form.  With the collocated 3-point rule (points and weights w_k
+// of each patch) the Lin coefficients phi_d of a patch and the values at its
+// ordinates u_k are related by u = Psi phi, Psi = (3 I + J)/6 (symmetric).
+// A weak-form right-hand side f of a patch becomes f^ = W^{-1} Psi^{-1} f,
+// after which every (cell, ordinate) block of eq. complete is the upwind DG
+// system of one discrete direction (local_solve.h).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "local_solve.h"
+
+namespace tr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int insert_bit(int t, int d, int bit) {
+  return (t & ((1 << d) - 1)) | (bit << d) | ((t >> d) << (d + 1));
+}
+
+template <typename T, int NS>
+__device__ __forceinline__ void load_node_vec(const T *p, T *v) {
+#pragma unroll
+  for (int b = 0; b < NS; ++b) v[b] = p[b];
+}
+
+template <typename T, int NS>
+__device__ __forceinline__ void store_node_vec(T *p, const T *v) {
+#pragma unroll
+  for (int b = 0; b < NS; ++b) p[b] = v[b];
+}
+
+__device__ __forceinline__ void unpack_cell(int packed, int flip, const Grid &g, int ci[3], int ix[3]) {
+  ci[0] = packed & 1023;
+  ci[1] = (packed >> 10) & 1023;
+  ci[2] = (packed >> 20) & 1023;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ix[d] = ((flip >> d) & 1) ? g.n[d] - 1 - ci[d] : ci[d];
+}
+
+__device__ __forceinline__ long long cell_index(const int ix[3], const Grid &g) {
+  return ix[0] + (long long)g.n[0] * (ix[1] + (long long)g.n[1] * ix[2]);
+}
+
+// Right-hand side of one ordinate's cell system, in the form solved by
+// spectral_solve: forward  v = N^{-1} f + sigma_s s + upwind inflow (scaled),
+//                 adjoint  v = f + sigma_s N s + downwind coupling.
+template <typename T, int DIM, bool ADJ>
+__device__ __forceinline__ void cell_rhs(T *v, const T *fk, const T *sk, const T *uk, long long j, const int ci[3],
+                                         const int ix[3], int flip, const T *c, const T *a, double sigs,
+                                         const Grid &g) {
+  constexpr int NS = 1 << DIM;
+  load_node_vec<T, NS>(fk + j * NS, v);
+  if (!ADJ) {
+    mass_shape<T, DIM, true>(v);
+    const T iv = T(1.0 / g.vol);
+#pragma unroll
+    for (int b = 0; b < NS; ++b) v[b] *= iv;
+    if (sk) {
+      T sv[NS];
+      load_node_vec<T, NS>(sk + j * NS, sv);
+#pragma unroll
+      for (int b = 0; b < NS; ++b) v[b] += T(sigs) * sv[b];
+    }
+  } else if (sk) {
+    T sv[NS];
+    load_node_vec<T, NS>(sk + j * NS, sv);
+    mass_shape<T, DIM, false>(sv);
+    const T f = T(sigs * g.vol);
+#pragma unroll
+    for (int b = 0; b < NS; ++b) v[b] += f * sv[b];
+  }
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int fl = (flip >> d) & 1;
+    const int dir = fl ? -1 : 1;
+    const bool has = ADJ ? (ci[d] < g.n[d] - 1) : (ci[d] > 0);
+    if (!has) continue;
+    int nx[3] = {ix[0], ix[1], ix[2]};
+    nx[d] += ADJ ? dir : -dir;
+    const long long jn = cell_index(nx, g);
+    const T *un = uk + jn * NS;
+    T tr[NS / 2];
+    if (!ADJ) {
+      const int nbit = fl ? 0 : 1;   // neighbour's outflow face
+      const int own0 = fl ? 1 : 0;   // own inflow face
+#pragma unroll
+      for (int t = 0; t < NS / 2; ++t) tr[t] = un[insert_bit(t, d, nbit)];
+#pragma unroll
+      for (int t = 0; t < NS / 2; ++t) {
+        v[insert_bit(t, d, own0)] += T(4) * c[d] * tr[t];
+        v[insert_bit(t, d, 1 - own0)] -= T(2) * c[d] * tr[t];
+      }
+    } else {
+      const int nbit = fl ? 1 : 0;   // neighbour's inflow face
+      const int own1 = fl ? 0 : 1;   // own outflow face
+#pragma unroll
+      for (int t = 0; t < NS / 2; ++t) tr[t] = un[insert_bit(t, d, nbit)];
+      mass_shape<T, DIM - 1, false>(tr);
+      T hs = T(1);
+#pragma unroll
+      for (int e = 0; e < DIM; ++e)
+        if (e != d) hs *= T(g.h[e]);
+#pragma unroll
+      for (int t = 0; t < NS / 2; ++t) v[insert_bit(t, d, own1)] += a[d] * hs * tr[t];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ sweep
+// One workgroup per ordinate walks the diagonal planes of its direction
+// (downwind first for the adjoint); the cells of a plane are independent.
+template <typename T, int DIM, bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> a) {
+  constexpr int NS = 1 << DIM;
+  const int k = blockIdx.x;
+  const OrdInfo o = a.ord[k];
+  const int flip = o.flip;
+  const T c[3] = {T(o.c[0]), T(o.c[1]), T(o.c[2])};
+  const T av[3] = {T(o.a[0]), T(o.a[1]), T(o.a[2])};
+  const long long S = a.g.S;
+  const T *fk = a.f + (long long)k * S;
+  const T *sk = a.s ? a.s + (long long)k * S : nullptr;
+  T *uk = a.u + (long long)k * S;
+  for (int pp = 0; pp < a.pl.nplanes; ++pp) {
+    const int p = ADJ ? a.pl.nplanes - 1 - pp : pp;
+    const int beg = a.pl.off[p], end = a.pl.off[p + 1];
+    for (int idx = beg + threadIdx.x; idx < end; idx += kBlock) {
+      int ci[3], ix[3];
+      unpack_cell(a.pl.cells[idx], flip, a.g, ci, ix);
+      const long long j = cell_index(ix, a.g);
+      T v[NS];
+      cell_rhs<T, DIM, ADJ>(v, fk, sk, uk, j, ci, ix, flip, c, av, a.sig_s[j], a.g);
+      spectral_solve<T, DIM, ADJ>(v, c, T(a.sig_t[j]), flip);
+      if (ADJ) {
+        mass_shape<T, DIM, true>(v);
+        const T iv = T(1.0 / a.g.vol);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) v[b] *= iv;
+      }
+      store_node_vec<T, NS>(uk + j * NS, v);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------- coarse Gauss-Seidel
+// T_0 has one patch (three ordinates) per octant.  One launch handles one
+// diagonal plane of one octant: each thread solves the coupled system of a
+// cell's three ordinates with the patch's own scatter implicit and every
+// other unknown at its latest value (Section 5.2).  In the spectral basis
+// the 24x24 (3-D) block splits into four complex 3x3 systems.
+template <int DIM, bool ADJ>
+__global__ __launch_bounds__(64) void k_gs_plane(const double *__restrict__ f, double *__restrict__ u,
+                                                 const double *__restrict__ G, const double *__restrict__ sig_t,
+                                                 const double *__restrict__ sig_s, const OrdInfo *__restrict__ ord,
+                                                 Planes pl, Grid g, int octant, int plane) {
+  constexpr int NS = 1 << DIM;
+  constexpr int NM = DIM == 3 ? 4 : 2;
+  const int idx = pl.off[plane] + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= pl.off[plane + 1]) return;
+  const int k0 = 3 * octant;
+  const int flip = ord[k0].flip;
+  int ci[3], ix[3];
+  unpack_cell(pl.cells[idx], flip, g, ci, ix);
+  const long long j = cell_index(ix, g);
+  const long long S = g.S;
+  const double st = sig_t[j], ss = sig_s[j];
+
+  // scatter from the other octants' ordinates at this cell (latest values)
+  double acc[3][NS];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int b = 0; b < NS; ++b) acc[m][b] = 0.0;
+  for (int kp = 0; kp < 24; ++kp) {
+    if (kp / 3 == octant) continue;
+    double uv[NS];
+    load_node_vec<double, NS>(u + kp * S + j * NS, uv);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double gm = G[(k0 + m) * 24 + kp];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) acc[m][b] += gm * uv[b];
+    }
+  }
+  double v[3][NS];
+  double cc[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const OrdInfo o = ord[k0 + m];
+    const double c[3] = {o.c[0], o.c[1], o.c[2]};
+    const double av[3] = {o.a[0], o.a[1], o.a[2]};
+    cc[m][0] = c[0];
+    cc[m][1] = c[1];
+    cc[m][2] = c[2];
+    cell_rhs<double, DIM, ADJ>(v[m], f + (k0 + m) * S, nullptr, u + (k0 + m) * S, j, ci, ix, flip, c, av, 0.0, g);
+    if (!ADJ) {
+#pragma unroll
+      for (int b = 0; b < NS; ++b) v[m][b] += ss * acc[m][b];
+    } else {
+      mass_shape<double, DIM, false>(acc[m]);
+#pragma unroll
+      for (int b = 0; b < NS; ++b) v[m][b] += ss * g.vol * acc[m][b];
+    }
+  }
+  // spectral transforms (all three ordinates share the octant's orientation)
+  AxisXf<double> ax[3];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ax[d] = axis_xf<double>((flip >> d) & 1, ADJ);
+  cx<double> md[3][NM];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) modes_forward<double, DIM>(v[m], ax, md[m]);
+  double gq[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int mp = 0; mp < 3; ++mp) gq[m][mp] = ss * G[(k0 + m) * 24 + k0 + mp];
+#pragma unroll
+  for (int mode = 0; mode < NM; ++mode) {
+    cx<double> M[3][3], r[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      r[m] = md[m][mode];
+#pragma unroll
+      for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-gq[m][mp], 0.0};
+      const cx<double> dm = mode_eig<double, DIM>(mode, cc[m], st);
+      M[m][m] = cadd(M[m][m], dm);
+    }
+    // Gaussian elimination (the blocks are diagonally dominant: the real
+    // part of D exceeds sigma_t + 2 sum c, the scatter block is below sigma_s)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const cx<double> ip = cinv(M[p][p]);
+#pragma unroll
+      for (int i = p + 1; i < 3; ++i) {
+        const cx<double> l = cmul(M[i][p], ip);
+#pragma unroll
+        for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(l, M[p][jj]));
+        r[i] = csub(r[i], cmul(l, r[p]));
+      }
+    }
+#pragma unroll
+    for (int p = 2; p >= 0; --p) {
+      cx<double> t = r[p];
+#pragma unroll
+      for (int jj = p + 1; jj < 3; ++jj) t = csub(t, cmul(M[p][jj], r[jj]));
+      r[p] = cmul(t, cinv(M[p][p]));
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) md[m][mode] = r[m];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double out[NS];
+    modes_backward<double, DIM>(md[m], ax, out);
+    if (ADJ) {
+      mass_shape<double, DIM, true>(out);
+#pragma unroll
+      for (int b = 0; b < NS; ++b) out[b] *= 1.0 / g.vol;
+    }
+    store_node_vec<double, NS>(u + (k0 + m) * S + j * NS, out);
+  }
+}
+
+// ------------------------------------------------------------- conversions
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, int P, long long S,
+                          const double *__restrict__ pre, const double *__restrict__ post) {
+  const long long total = (long long)P * S;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(t / S);
+    const long long s = t - (long long)p * S;
+    double x[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      x[m] = (double)in[(3LL * p + m) * S + s];
+      if (pre) x[m] *= pre[3 * p + m];
+    }
+    const double sum = x[0] + x[1] + x[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double y = 2.0 * x[k] - sum * (1.0 / 3.0);   // Psi^{-1} = 2 I - J / 3
+      if (post) y *= post[3 * p + k];
+      out[(3LL * p + k) * S + s] = (Tout)y;
+    }
+  }
+}
+
+// ------------------------------------------------------------- transfers
+template <typename Tin, typename Tout, int DIM>
+__global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict__ s_prev, Tout *__restrict__ fc,
+                           const double *__restrict__ R, const int *__restrict__ first_child,
+                           const int *__restrict__ n_child, int Pc, const double *__restrict__ sig_s,
+                           int apply_sn, Grid g) {
+  constexpr int NS = 1 << DIM;
+  const long long C = g.C, S = g.S;
+  const long long total = (long long)Pc * C;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(t / C);
+    const long long j = t - (long long)p * C;
+    double out[3][NS];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int b = 0; b < NS; ++b) out[m][b] = 0.0;
+    const int c0 = first_child[p], nc = n_child[p];
+    for (int c = c0; c < c0 + nc; ++c) {
+      double x[3][NS];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const long long off = (3LL * c + m) * S + j * NS;
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          double v = (double)s_new[off + b];
+          if (s_prev) v -= (double)s_prev[off + b];
+          x[m][b] = v;
+        }
+        if (apply_sn) {
+          mass_shape<double, DIM, false>(x[m]);
+          const double f = sig_s[j] * g.vol;
+#pragma unroll
+          for (int b = 0; b < NS; ++b) x[m][b] *= f;
+        }
+      }
+      const double *Rc = R + 9LL * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double r = Rc[k * 3 + m];
+#pragma unroll
+          for (int b = 0; b < NS; ++b) out[k][b] += r * x[m][b];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const long long off = (3LL * p + k) * S + j * NS;
+#pragma unroll
+      for (int b = 0; b < NS; ++b) fc[off + b] = (Tout)out[k][b];
+    }
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_prolong(const Tin *__restrict__ uc, Tout *__restrict__ uf, const double *__restrict__ Pb,
+                          const int *__restrict__ owner, int Pf, long long S, int add) {
+  const long long total = (long long)Pf * S;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(t / S);
+    const long long s = t - (long long)c * S;
+    const int p = owner[c];
+    double x[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = (double)uc[(3LL * p + d) * S + s];
+    const double *B = Pb + 9LL * c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double y = B[k * 3] * x[0] + B[k * 3 + 1] * x[1] + B[k * 3 + 2] * x[2];
+      Tout *dst = uf + (3LL * c + k) * S + s;
+      if (add) y += (double)*dst;
+      *dst = (Tout)y;
+    }
+  }
+}
+
+// --------------------------------------------------------- operator apply
+// Apply 2x2 matrix [[m00, m01], [m10, m11]] along axis d (physical order).
+template <int DIM>
+__device__ __forceinline__ void axis_apply(double *v, int d, double m00, double m01, double m10, double m11) {
+  constexpr int NS = 1 << DIM;
+  const int bit = 1 << d;
+#pragma unroll
+  for (int b = 0; b < NS; ++b) {
+    if (b & bit) continue;
+    const double p0 = v[b], p1 = v[b | bit];
+    v[b] = m00 * p0 + m01 * p1;
+    v[b | bit] = m10 * p0 + m11 * p1;
+  }
+}
+
+// y = L x - sigma_s N (S~ x) on the finest level, canonical layout.
+// Forward:  per patch, u = Psi x, per ordinate r_k = A_loc u_k - upwind
+//           coupling, y = Psi W r.
+// Adjoint:  L^T = Psi L^T_ord W Psi: mu = W Psi x, r_k = A_loc^T mu_k -
+//           downwind coupling, y = Psi r (S is symmetric, so S^T x = S x).
+template <int DIM, bool ADJ>
+__global__ void k_apply(const double *__restrict__ x, const double *__restrict__ s, double *__restrict__ y,
+                        const double *__restrict__ sig_t, const double *__restrict__ sig_s,
+                        const OrdInfo *__restrict__ ord, const double *__restrict__ w, int P, Grid g) {
+  constexpr int NS = 1 << DIM;
+  const long long C = g.C, S = g.S;
+  const long long total = (long long)P * C;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(t / C);
+    const long long j = t - (long long)q * C;
+    int ix[3] = {(int)(j % g.n[0]), (int)((j / g.n[0]) % g.n[1]), (int)(j / ((long long)g.n[0] * g.n[1]))};
+    double xv[3][NS];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) load_node_vec<double, NS>(x + (3LL * q + m) * S + j * NS, xv[m]);
+    double yk[3][NS];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const OrdInfo o = ord[3 * q + k];
+      const int flip = o.flip;
+      const double wk = ADJ ? w[3 * q + k] : 1.0;
+      double u[NS];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) u[b] = wk * (xv[0][b] + xv[1][b] + xv[2][b] + 3.0 * xv[k][b]) * (1.0 / 6.0);
+      // removal
+      double r[NS];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) r[b] = u[b];
+      mass_shape<double, DIM, false>(r);
+#pragma unroll
+      for (int b = 0; b < NS; ++b) r[b] *= sig_t[j] * g.vol;
+      // streaming |Omega_d| T1_d (x) N on the other axes (T1 = [[1,1],[-1,1]]/2
+      // oriented along the flow; its transpose is the flipped matrix),
+      // minus the coupling to the upwind (adjoint: downwind) neighbour
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int fl = (flip >> d) & 1;
+        double tv[NS];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) tv[b] = u[b];
+        if (fl != (ADJ ? 1 : 0))
+          axis_apply<DIM>(tv, d, 0.5, -0.5, 0.5, 0.5);
+        else
+          axis_apply<DIM>(tv, d, 0.5, 0.5, -0.5, 0.5);
+        double hs = 1.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+          if (e != d) {
+            axis_apply<DIM>(tv, e, 2.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 2.0 / 6.0);
+            hs *= g.h[e];
+          }
+#pragma unroll
+        for (int b = 0; b < NS; ++b) r[b] += o.a[d] * hs * tv[b];
+        // forward: neighbour upstream (fl ? +1 : -1); adjoint: downstream
+        const int step = (fl ? 1 : -1) * (ADJ ? -1 : 1);
+        const int ok = step > 0 ? (ix[d] < g.n[d] - 1) : (ix[d] > 0);
+        if (ok) {
+          int nx[3] = {ix[0], ix[1], ix[2]};
+          nx[d] += step;
+          const long long jn = nx[0] + (long long)g.n[0] * (nx[1] + (long long)g.n[1] * nx[2]);
+          // forward: neighbour's outflow face into own inflow face;
+          // adjoint: neighbour's inflow face into own outflow face
+          const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
+          const int own = 1 - nbit;
+          double tr[NS / 2];
+#pragma unroll
+          for (int tt = 0; tt < NS / 2; ++tt) {
+            const int b = insert_bit(tt, d, nbit);
+            const double x0 = x[(3LL * q + 0) * S + jn * NS + b];
+            const double x1 = x[(3LL * q + 1) * S + jn * NS + b];
+            const double x2 = x[(3LL * q + 2) * S + jn * NS + b];
+            const double xk = k == 0 ? x0 : (k == 1 ? x1 : x2);
+            tr[tt] = wk * (x0 + x1 + x2 + 3.0 * xk) * (1.0 / 6.0);
+          }
+          mass_shape<double, DIM - 1, false>(tr);
+#pragma unroll
+          for (int tt = 0; tt < NS / 2; ++tt) r[insert_bit(tt, d, own)] -= o.a[d] * hs * tr[tt];
+        }
+      }
+      const double wo = ADJ ? 1.0 : w[3 * q + k];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) yk[k][b] = wo * r[b];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      double sv[NS];
+      load_node_vec<double, NS>(s + (3LL * q + m) * S + j * NS, sv);
+      mass_shape<double, DIM, false>(sv);
+      double out[NS];
+#pragma unroll
+      for (int b = 0; b < NS; ++b)
+        out[b] = (yk[0][b] + yk[1][b] + yk[2][b] + 3.0 * yk[m][b]) * (1.0 / 6.0) - sig_s[j] * g.vol * sv[b];
+      store_node_vec<double, NS>(y + (3LL * q + m) * S + j * NS, out);
+    }
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_scale_sn(const T *__restrict__ in, T *__restrict__ out, const double *__restrict__ sig_s, int A,
+                           Grid g) {
+  constexpr int NS = 1 << DIM;
+  const long long total = (long long)A * g.C;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long j = t % g.C;
+    double v[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) v[b] = (double)in[t * NS + b];
+    mass_shape<double, DIM, false>(v);
+    const double f = sig_s[j] * g.vol;
+#pragma unroll
+    for (int b = 0; b < NS; ++b) out[t * NS + b] = (T)(f * v[b]);
+  }
+}
+
+// ---------------------------------------------------------------- sources
+__global__ void k_rhs_volume(double *__restrict__ b, const double *__restrict__ q, const double *__restrict__ ipsi,
+                             int A, Grid g) {
+  const long long total = (long long)A * g.S;
+  const double bint = g.vol / g.ns;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long a = t / g.S;
+    const long long j = (t - a * g.S) / g.ns;
+    b[t] = q ? q[j] * bint * ipsi[a] : 0.0;
+  }
+}
+
+__global__ void k_rhs_face(double *__restrict__ b, const double *__restrict__ coef, const int *__restrict__ cells,
+                           int ncells, const double *__restrict__ face_int, int A, Grid g) {
+  const long long total = (long long)A * ncells;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long a = t / ncells;
+    const int jc = cells[t - a * ncells];
+    const double cf = coef[a];
+    if (cf == 0.0) continue;
+    for (int i = 0; i < g.ns; ++i) b[a * g.S + (long long)jc * g.ns + i] += cf * face_int[i];
+  }
+}
+
+__global__ void k_detector(double *__restrict__ w, const double *__restrict__ ipsi, int A, Grid g, int lo0, int lo1,
+                           int lo2, int hi0, int hi1, int hi2) {
+  const long long total = (long long)A * g.S;
+  const double bint = g.vol / g.ns;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long a = t / g.S;
+    const long long j = (t - a * g.S) / g.ns;
+    const int ix = (int)(j % g.n[0]), iy = (int)((j / g.n[0]) % g.n[1]), iz = (int)(j / ((long long)g.n[0] * g.n[1]));
+    bool in = ix >= lo0 && ix <= hi0 && iy >= lo1 && iy <= hi1;
+    if (g.dim == 3) in = in && iz >= lo2 && iz <= hi2;
+    w[t] = in ? ipsi[a] * bint : 0.0;
+  }
+}
+
+// grad_t[j] = -sum_q lambda_jq^T (N (x) M_q) phi_jq with M_q = Psi W Psi
+template <int DIM>
+__global__ void k_grad_t(const double *__restrict__ lam, const double *__restrict__ phi,
+                         const double *__restrict__ w, int P, Grid g, double *__restrict__ gt) {
+  constexpr int NS = 1 << DIM;
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < g.C;
+       j += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int q = 0; q < P; ++q) {
+      double lv[3][NS], pv[3][NS];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        load_node_vec<double, NS>(lam + (3LL * q + m) * g.S + j * NS, lv[m]);
+        load_node_vec<double, NS>(phi + (3LL * q + m) * g.S + j * NS, pv[m]);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double lk[NS], pk[NS];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          lk[b] = (lv[0][b] + lv[1][b] + lv[2][b] + 3.0 * lv[k][b]) * (1.0 / 6.0);
+          pk[b] = (pv[0][b] + pv[1][b] + pv[2][b] + 3.0 * pv[k][b]) * (1.0 / 6.0);
+        }
+        mass_shape<double, DIM, false>(pk);
+        double dd = 0.0;
+#pragma unroll
+        for (int b = 0; b < NS; ++b) dd += lk[b] * pk[b];
+        acc += w[3 * q + k] * dd;
+      }
+    }
+    gt[j] = -acc * g.vol;
+  }
+}
+
+// grad_s[j] = sum_a lambda_aj^T N t_aj with t = S~ phi
+template <int DIM>
+__global__ void k_grad_s(const double *__restrict__ lam, const double *__restrict__ tt, int A, Grid g,
+                         double *__restrict__ gs) {
+  constexpr int NS = 1 << DIM;
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < g.C;
+       j += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int a = 0; a < A; ++a) {
+      double lv[NS], tv[NS];
+      load_node_vec<double, NS>(lam + (long long)a * g.S + j * NS, lv);
+      load_node_vec<double, NS>(tt + (long long)a * g.S + j * NS, tv);
+      mass_shape<double, DIM, false>(tv);
+#pragma unroll
+      for (int b = 0; b < NS; ++b) acc += lv[b] * tv[b];
+    }
+    gs[j] = acc * g.vol;
+  }
+}
+
+// ----------------------------------------------------------------- BLAS-1
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y,
+                                                        long long n, double *__restrict__ partial) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    acc += x[i] * y[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_final(const double *__restrict__ partial, int nb,
+                                                      double *__restrict__ out) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_axpy(long long n, double a, const double *__restrict__ x, double *__restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+__global__ void k_scal(long long n, double a, double *__restrict__ x) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] *= a;
+}
+
+__global__ void k_axpby(long long n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
+                        double *__restrict__ z) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    z[i] = a * x[i] + b * y[i];
+}
+
+template <typename T>
+__global__ void k_fill(T *x, long long n, T v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_cast(const Tin *__restrict__ in, Tout *__restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = (Tout)in[i];
+}
+
+int grid_for(long long n, int block = kBlock) {
+  long long g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+template <typename T>
+void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st) {
+  if (a.g.dim == 3) {
+    if (adjoint)
+      hipLaunchKernelGGL((k_sweep<T, 3, true>), dim3(n_ord), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep<T, 3, false>), dim3(n_ord), dim3(kBlock), 0, st, a);
+  } else {
+    if (adjoint)
+      hipLaunchKernelGGL((k_sweep<T, 2, true>), dim3(n_ord), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep<T, 2, false>), dim3(n_ord), dim3(kBlock), 0, st, a);
+  }
+}
+template void launch_sweep<double>(const SweepArgs<double> &, int, bool, hipStream_t);
+template void launch_sweep<float>(const SweepArgs<float> &, int, bool, hipStream_t);
+
+void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
+                      const OrdInfo *ord, const Planes &pl, const int *off_host, const Grid &g, int nu,
+                      const int *octant_order, bool adjoint, hipStream_t st) {
+  launch_fill<double>(u, 24LL * g.S, 0.0, st);
+  for (int sweep = 0; sweep < nu; ++sweep)
+    for (int oi = 0; oi < 8; ++oi) {
+      const int o = octant_order[oi];
+      for (int pp = 0; pp < pl.nplanes; ++pp) {
+        const int p = adjoint ? pl.nplanes - 1 - pp : pp;
+        const int cnt = off_host[p + 1] - off_host[p];
+        const int blocks = (cnt + 63) / 64;
+        if (g.dim == 3) {
+          if (adjoint)
+            hipLaunchKernelGGL((k_gs_plane<3, true>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord, pl,
+                               g, o, p);
+          else
+            hipLaunchKernelGGL((k_gs_plane<3, false>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord,
+                               pl, g, o, p);
+        } else {
+          if (adjoint)
+            hipLaunchKernelGGL((k_gs_plane<2, true>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord, pl,
+                               g, o, p);
+          else
+            hipLaunchKernelGGL((k_gs_plane<2, false>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord,
+                               pl, g, o, p);
+        }
+      }
+    }
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
+                    hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for((long long)P * S)), dim3(kBlock), 0, st, in, out, P, S,
+                     pre, post);
+}
+template void launch_convert<double, double>(const double *, double *, int, long long, const double *,
+                                             const double *, hipStream_t);
+template void launch_convert<double, float>(const double *, float *, int, long long, const double *, const double *,
+                                            hipStream_t);
+template void launch_convert<float, double>(const float *, double *, int, long long, const double *, const double *,
+                                            hipStream_t);
+template void launch_convert<float, float>(const float *, float *, int, long long, const double *, const double *,
+                                           hipStream_t);
+
+template <typename Tin, typename Tout>
+void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,
+                     const int *n_child, int Pc, const double *sig_s, bool apply_sn, const Grid &g,
+                     hipStream_t st) {
+  const int grid = grid_for((long long)Pc * g.C);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_restrict<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, s_new, s_prev, fc, R,
+                       first_child, n_child, Pc, sig_s, (int)apply_sn, g);
+  else
+    hipLaunchKernelGGL((k_restrict<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, s_new, s_prev, fc, R,
+                       first_child, n_child, Pc, sig_s, (int)apply_sn, g);
+}
+#define TR_INST_RESTRICT(TI, TO)                                                                               \
+  template void launch_restrict<TI, TO>(const TI *, const TI *, TO *, const double *, const int *, const int *, \
+                                        int, const double *, bool, const Grid &, hipStream_t);
+TR_INST_RESTRICT(double, double)
+TR_INST_RESTRICT(float, float)
+TR_INST_RESTRICT(float, double)
+TR_INST_RESTRICT(double, float)
+
+template <typename Tin, typename Tout>
+void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *owner, int Pf, long long S, bool add,
+                    hipStream_t st) {
+  hipLaunchKernelGGL((k_prolong<Tin, Tout>), dim3(grid_for((long long)Pf * S)), dim3(kBlock), 0, st, uc, uf, Pblk,
+                     owner, Pf, S, (int)add);
+}
+#define TR_INST_PROLONG(TI, TO)                                                                              \
+  template void launch_prolong<TI, TO>(const TI *, TO *, const double *, const int *, int, long long, bool, \
+                                       hipStream_t);
+TR_INST_PROLONG(double, double)
+TR_INST_PROLONG(float, float)
+TR_INST_PROLONG(double, float)
+TR_INST_PROLONG(float, double)
+
+void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
+                  const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
+  const int grid = grid_for((long long)P * g.C);
+  if (g.dim == 3) {
+    if (adjoint)
+      hipLaunchKernelGGL((k_apply<3, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+    else
+      hipLaunchKernelGGL((k_apply<3, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+  } else {
+    if (adjoint)
+      hipLaunchKernelGGL((k_apply<2, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+    else
+      hipLaunchKernelGGL((k_apply<2, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+  }
+}
+
+template <typename T>
+void launch_scale_sn(const T *in, T *out, const double *sig_s, int A, const Grid &g, hipStream_t st) {
+  const int grid = grid_for((long long)A * g.C);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_scale_sn<T, 3>), dim3(grid), dim3(kBlock), 0, st, in, out, sig_s, A, g);
+  else
+    hipLaunchKernelGGL((k_scale_sn<T, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, sig_s, A, g);
+}
+template void launch_scale_sn<double>(const double *, double *, const double *, int, const Grid &, hipStream_t);
+template void launch_scale_sn<float>(const float *, float *, const double *, int, const Grid &, hipStream_t);
+
+void launch_rhs_volume(double *b, const double *q, const double *ipsi, int A, const Grid &g, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_volume, dim3(grid_for((long long)A * g.S)), dim3(kBlock), 0, st, b, q, ipsi, A, g);
+}
+
+void launch_rhs_face(double *b, const double *coef, const int *cells, int ncells, const double *face_int, int A,
+                     const Grid &g, hipStream_t st) {
+  if (ncells <= 0) return;
+  hipLaunchKernelGGL(k_rhs_face, dim3(grid_for((long long)A * ncells)), dim3(kBlock), 0, st, b, coef, cells, ncells,
+                     face_int, A, g);
+}
+
+void launch_detector(double *w, const double *ipsi, int A, const Grid &g, const int lo[3], const int hi[3],
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_detector, dim3(grid_for((long long)A * g.S)), dim3(kBlock), 0, st, w, ipsi, A, g, lo[0],
+                     lo[1], lo[2], hi[0], hi[1], hi[2]);
+}
+
+void launch_grad_t(const double *lam, const double *phi, const double *w, int P, const Grid &g, double *gt,
+                   hipStream_t st) {
+  const int grid = grid_for(g.C, 64);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_grad_t<3>), dim3(grid), dim3(64), 0, st, lam, phi, w, P, g, gt);
+  else
+    hipLaunchKernelGGL((k_grad_t<2>), dim3(grid), dim3(64), 0, st, lam, phi, w, P, g, gt);
+}
+
+void launch_grad_s(const double *lam, const double *t, int A, const Grid &g, double *gs, hipStream_t st) {
+  const int grid = grid_for(g.C, 64);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_grad_s<3>), dim3(grid), dim3(64), 0, st, lam, t, A, g, gs);
+  else
+    hipLaunchKernelGGL((k_grad_s<2>), dim3(grid), dim3(64), 0, st, lam, t, A, g, gs);
+}
+
+void launch_dot_partial(const double *x, const double *y, long long n, double *partial, int nblocks,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblocks), dim3(kBlock), 0, st, x, y, n, partial);
+}
+void launch_dot_final(const double *partial, int nblocks, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, st, partial, nblocks, out);
+}
+void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(kBlock), 0, st, n, a, x, y);
+}
+void launch_scal(long long n, double a, double *x, hipStream_t st) {
+  hipLaunchKernelGGL(k_scal, dim3(grid_for(n)), dim3(kBlock), 0, st, n, a, x);
+}
+void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kBlock), 0, st, n, a, x, b, y, z);
+}
+template <typename T>
+void launch_fill(T *x, long long n, T v, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, x, n, v);
+}
+template void launch_fill<double>(double *, long long, double, hipStream_t);
+template void launch_fill<float>(float *, long long, float, hipStream_t);
+template <typename Tin, typename Tout>
+void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(kBlock), 0, st, in, out, n);
+}
+template void launch_cast<double, float>(const double *, float *, long long, hipStream_t);
+template void launch_cast<float, double>(const float *, double *, long long, hipStream_t);
+
+}  // namespace tr

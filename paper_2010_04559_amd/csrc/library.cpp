@@ -1,0 +1,1139 @@
+// Host side of the transport library: problem setup, the angular multigrid
+// V-cycle (Fig. lmg), restarted GMRES and the adjoint gradient, behind the
+// C ABI of tr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tr.h"
+#include "angular_setup.h"
+#include "internal.h"
+
+using tr::Grid;
+using tr::OrdInfo;
+using tr::Planes;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIPCHK(call)                                                      \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess) throw HipError{e_, #call};                      \
+  } while (0)
+
+struct ArgError {
+  std::string msg;
+};
+
+// Psi = (3 I + J) / 6 and its inverse 2 I - J / 3 (identical on every patch).
+const double kPsi[3][3] = {{4.0 / 6, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 4.0 / 6, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 4.0 / 6}};
+const double kPsiInv[3][3] = {{5.0 / 3, -1.0 / 3, -1.0 / 3}, {-1.0 / 3, 5.0 / 3, -1.0 / 3}, {-1.0 / 3, -1.0 / 3, 5.0 / 3}};
+
+void mat3_mul(const double *a, const double *b, double *c) {
+  double t[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) s += a[i * 3 + k] * b[k * 3 + j];
+      t[i * 3 + j] = s;
+    }
+  std::memcpy(c, t, sizeof t);
+}
+
+struct DevLevel {
+  int P = 0, A = 0, order = 0;
+  OrdInfo *ord = nullptr;
+  double *w = nullptr, *winv = nullptr, *ipsi = nullptr;
+  double *St64 = nullptr;      // canonical S~ (order of this level), A x A
+  float *St32 = nullptr;
+  double *G64 = nullptr, *Gt64 = nullptr;  // ordinate-form scatter and transpose
+  float *G32 = nullptr, *Gt32 = nullptr;
+  int *owner = nullptr;                    // level >= 1: owner patch on level l-1
+  double *Pu = nullptr, *Ru = nullptr, *Pa = nullptr, *Ra = nullptr, *Pc = nullptr, *Rc = nullptr;
+  int *first_child = nullptr, *n_child = nullptr;  // over level l-1 patches
+  // workspaces (ordinate form)
+  double *f64 = nullptr, *u64 = nullptr, *sa64 = nullptr, *sb64 = nullptr;
+  float *f32 = nullptr, *u32 = nullptr, *sa32 = nullptr, *sb32 = nullptr;
+};
+
+struct EventTimer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  struct Rec {
+    int comp;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  int open_comp = -1;
+  hipEvent_t open_ev = nullptr;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  void begin(int comp) {
+    if (!on) return;
+    open_comp = comp;
+    open_ev = get();
+    HIPCHK(hipEventRecord(open_ev, st));
+  }
+  void end() {
+    if (!on) return;
+    hipEvent_t b = get();
+    HIPCHK(hipEventRecord(b, st));
+    recs.push_back({open_comp, open_ev, b});
+  }
+  ~EventTimer() {
+    for (auto &r : recs) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    for (auto e : pool) hipEventDestroy(e);
+  }
+};
+
+// Device scratch freed at scope exit (the caller synchronises the stream first).
+struct TmpBuf {
+  void *p = nullptr;
+  explicit TmpBuf(size_t bytes) {
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) throw std::bad_alloc();
+  }
+  ~TmpBuf() { hipFree(p); }
+  template <typename T>
+  T *as() { return static_cast<T *>(p); }
+};
+
+enum { C_SWEEP = 0, C_SCATTER, C_TRANSFER, C_COARSE, C_APPLY, C_ORTH, C_OTHER, C_SWEEP_FINE, C_N };
+
+}  // namespace
+
+struct tr_handle {
+  tr_problem prob{};
+  std::vector<double> sig_t_host, sig_s_host, moments;
+  std::vector<int> mg_order;
+  int octant_order[8];
+  Grid g{};
+  Planes pl{};
+  std::vector<int> plane_off_host;
+  int *d_cells = nullptr, *d_off = nullptr;
+  double *sig_t = nullptr, *sig_s = nullptr;
+  tr::HostAngular ang;
+  std::vector<DevLevel> lv;
+  double *Souter = nullptr;  // canonical S~ at the problem's order on the finest level
+  double *iom = nullptr;     // [A][3] int Omega^xi psi on the finest level
+  double *dot_partial = nullptr, *dot_out = nullptr;
+  double *tmp = nullptr;     // one finest-level FP64 vector
+  double *tmp2 = nullptr;
+  int dot_blocks = 1024;
+  // Krylov workspace
+  int kry_m = 0;
+  std::vector<double *> V, Z;
+  double *kw = nullptr, *kx = nullptr;
+  bool mixed_ready = false;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  EventTimer *timer = nullptr;
+
+  template <typename T>
+  T *alloc(size_t n) {
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    bytes += n * sizeof(T);
+    return static_cast<T *>(p);
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v) {
+    T *p = alloc<T>(v.size());
+    HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  int top() const { return (int)lv.size() - 1; }
+  long long vec_len(int l) const { return (long long)lv[l].A * g.S; }
+  ~tr_handle() {
+    for (void *p : allocs) hipFree(p);
+  }
+};
+
+namespace {
+
+void tbegin(tr_handle *h, int c) {
+  if (h->timer) h->timer->begin(c);
+}
+void tend(tr_handle *h) {
+  if (h->timer) h->timer->end();
+}
+
+// ------------------------------------------------------------------ setup
+void build(tr_handle *h, const tr_problem *p) {
+  if (p->dim != 2 && p->dim != 3) throw ArgError{"dim must be 2 or 3"};
+  for (int d = 0; d < p->dim; ++d) {
+    if (p->n[d] < 1 || p->n[d] > 1000) throw ArgError{"cells per axis must be in 1..1000"};
+    if (!(p->len[d] > 0)) throw ArgError{"domain lengths must be positive"};
+  }
+  if (p->order < 0 || p->order > 96) throw ArgError{"order out of range 0..96"};
+  if (!p->moments || !p->sigma_t || !p->sigma_s || !p->mg_order) throw ArgError{"null array in problem"};
+  if (p->nu_pre < 1 || p->nu_post < 0 || p->nu_coarse < 1) throw ArgError{"need nu_pre >= 1, nu_post >= 0, nu_coarse >= 1"};
+  {
+    int seen[8] = {0};
+    for (int i = 0; i < 8; ++i) {
+      int o = p->octant_order[i];
+      if (o < 0 || o > 7 || seen[o]++) throw ArgError{"octant_order must be a permutation of 0..7"};
+    }
+  }
+  h->prob = *p;
+  std::memcpy(h->octant_order, p->octant_order, sizeof h->octant_order);
+  Grid &g = h->g;
+  g.dim = p->dim;
+  g.ns = 1 << p->dim;
+  g.n[0] = p->n[0];
+  g.n[1] = p->n[1];
+  g.n[2] = p->dim == 3 ? p->n[2] : 1;
+  g.vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    g.h[d] = d < p->dim ? p->len[d] / p->n[d] : 1.0;
+    if (d < p->dim) g.vol *= g.h[d];
+  }
+  g.C = (long long)g.n[0] * g.n[1] * g.n[2];
+  g.S = g.C * g.ns;
+  h->sig_t_host.assign(p->sigma_t, p->sigma_t + g.C);
+  h->sig_s_host.assign(p->sigma_s, p->sigma_s + g.C);
+  for (long long j = 0; j < g.C; ++j) {
+    if (!(std::isfinite(h->sig_t_host[j]) && h->sig_t_host[j] > 0)) throw ArgError{"sigma_t must be finite and > 0"};
+    if (!(std::isfinite(h->sig_s_host[j]) && h->sig_s_host[j] >= 0)) throw ArgError{"sigma_s must be finite and >= 0"};
+  }
+
+  tr::RefineSpec spec;
+  spec.base_level = p->ang_base_level;
+  spec.cone_axis = {p->cone_axis[0], p->cone_axis[1], p->cone_axis[2]};
+  spec.cone_half_angle_deg = p->cone_half_angle_deg;
+  spec.cone_extra_levels = p->cone_extra_levels;
+  spec.closure = p->irregularity_closure != 0;
+  if (spec.cone_extra_levels > 0 &&
+      !(std::fabs(spec.cone_axis.x) + std::fabs(spec.cone_axis.y) + std::fabs(spec.cone_axis.z) > 0))
+    throw ArgError{"cone axis must be nonzero"};
+  std::string err;
+  if (!tr::build_angular(spec, h->ang, err)) throw ArgError{err};
+  const int nlev = (int)h->ang.lv.size();
+  if (p->n_levels != nlev)
+    throw ArgError{"n_levels does not match the angular mesh (it has " + std::to_string(nlev) + " levels)"};
+  if (nlev > 16) throw ArgError{"too many angular levels"};
+  h->mg_order.assign(p->mg_order, p->mg_order + nlev);
+  int maxo = p->order;
+  for (int o : h->mg_order) {
+    if (o < 0 || o > 96) throw ArgError{"mg_order out of range 0..96"};
+    maxo = std::max(maxo, o);
+  }
+  h->moments.assign(p->moments, p->moments + maxo + 1);
+  for (double m : h->moments)
+    if (!std::isfinite(m)) throw ArgError{"moments must be finite"};
+
+  // sweep schedule (orientation +,+,+): cells grouped by ix + iy + iz
+  {
+    const int np = g.n[0] + g.n[1] + g.n[2] - 2;
+    std::vector<std::vector<int>> buckets(np);
+    for (int iz = 0; iz < g.n[2]; ++iz)
+      for (int iy = 0; iy < g.n[1]; ++iy)
+        for (int ix = 0; ix < g.n[0]; ++ix) buckets[ix + iy + iz].push_back(ix | (iy << 10) | (iz << 20));
+    std::vector<int> cells, off{0};
+    int mx = 0;
+    for (auto &b : buckets) {
+      cells.insert(cells.end(), b.begin(), b.end());
+      off.push_back((int)cells.size());
+      mx = std::max(mx, (int)b.size());
+    }
+    h->plane_off_host = off;
+    h->d_cells = h->upload(cells);
+    h->d_off = h->upload(off);
+    h->pl.cells = h->d_cells;
+    h->pl.off = h->d_off;
+    h->pl.nplanes = np;
+    h->pl.max_plane = mx;
+  }
+  h->sig_t = h->upload(h->sig_t_host);
+  h->sig_s = h->upload(h->sig_s_host);
+
+  // levels
+  h->lv.assign(nlev, DevLevel());
+  for (int l = 0; l < nlev; ++l) {
+    const tr::HostLevel &H = h->ang.lv[l];
+    DevLevel &D = h->lv[l];
+    D.P = H.P;
+    D.A = H.A;
+    D.order = h->mg_order[l];
+    std::vector<OrdInfo> ord(H.A);
+    std::vector<double> winv(H.A);
+    for (int a = 0; a < H.A; ++a) {
+      OrdInfo o{};
+      int flip = 0;
+      for (int d = 0; d < 3; ++d) {
+        double om = H.omega[3 * a + d];
+        bool active = d < g.dim;
+        o.a[d] = active ? std::fabs(om) : 0.0;
+        o.c[d] = active ? std::fabs(om) / g.h[d] : 0.0;
+        if (active && om < 0) flip |= 1 << d;
+      }
+      o.flip = flip;
+      o.patch = a / 3;
+      ord[a] = o;
+      if (!(H.w[a] > 0)) throw ArgError{"internal: nonpositive quadrature weight"};
+      winv[a] = 1.0 / H.w[a];
+    }
+    D.ord = h->upload(ord);
+    D.w = h->upload(H.w);
+    D.winv = h->upload(winv);
+    D.ipsi = h->upload(H.ipsi);
+    // scatter matrices at this level's order
+    std::vector<double> mom(h->moments.begin(), h->moments.begin() + D.order + 1);
+    std::vector<double> St;
+    tr::scatter_matrix(h->ang, l, mom, St);
+    const int A = H.A;
+    std::vector<double> G((size_t)A * A), Gt((size_t)A * A);
+    for (int q = 0; q < H.P; ++q)
+      for (int p2 = 0; p2 < H.P; ++p2) {
+        double blk[9], t1[9], t2[9];
+        for (int m = 0; m < 3; ++m)
+          for (int d = 0; d < 3; ++d) blk[m * 3 + d] = St[(size_t)(3 * q + m) * A + 3 * p2 + d];
+        mat3_mul(&kPsiInv[0][0], blk, t1);
+        mat3_mul(t1, &kPsiInv[0][0], t2);
+        for (int k = 0; k < 3; ++k)
+          for (int kk = 0; kk < 3; ++kk) {
+            double v = t2[k * 3 + kk] / H.w[3 * q + k];
+            G[(size_t)(3 * q + k) * A + 3 * p2 + kk] = v;
+            Gt[(size_t)(3 * p2 + kk) * A + 3 * q + k] = v;
+          }
+      }
+    std::vector<float> St32(St.begin(), St.end()), G32(G.begin(), G.end()), Gt32(Gt.begin(), Gt.end());
+    D.St64 = h->upload(St);
+    D.St32 = h->upload(St32);
+    D.G64 = h->upload(G);
+    D.Gt64 = h->upload(Gt);
+    D.G32 = h->upload(G32);
+    D.Gt32 = h->upload(Gt32);
+    if (l == nlev - 1) {
+      if (p->order == D.order) {
+        h->Souter = D.St64;
+      } else {
+        std::vector<double> mo(h->moments.begin(), h->moments.begin() + p->order + 1), So;
+        tr::scatter_matrix(h->ang, l, mo, So);
+        h->Souter = h->upload(So);
+      }
+      h->iom = h->upload(H.iom);
+    }
+    if (l > 0) {
+      const tr::HostLevel &Hc = h->ang.lv[l - 1];
+      std::vector<double> Pu(9 * (size_t)H.P), Ru(9 * (size_t)H.P), Pa(9 * (size_t)H.P), Ra(9 * (size_t)H.P),
+          Pc(9 * (size_t)H.P), Rc(9 * (size_t)H.P);
+      for (int c = 0; c < H.P; ++c) {
+        const int par = H.owner[c];
+        double P0[9], PT[9], t1[9], t2[9];
+        for (int i = 0; i < 9; ++i) P0[i] = H.pblk[(size_t)c * 9 + i];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) PT[i * 3 + j] = P0[j * 3 + i];
+        double Wc[9] = {0}, Wpi[9] = {0};
+        for (int k = 0; k < 3; ++k) {
+          Wc[k * 4] = H.w[3 * c + k];
+          Wpi[k * 4] = 1.0 / Hc.w[3 * par + k];
+        }
+        // ordinate-form prolongation  Psi P Psi^{-1}
+        mat3_mul(&kPsi[0][0], P0, t1);
+        mat3_mul(t1, &kPsiInv[0][0], t2);
+        std::memcpy(&Pu[9 * (size_t)c], t2, sizeof t2);
+        // ordinate-form restriction  W_p^{-1} Psi^{-1} P^T Psi W_c
+        mat3_mul(Wpi, &kPsiInv[0][0], t1);
+        mat3_mul(t1, PT, t2);
+        mat3_mul(t2, &kPsi[0][0], t1);
+        mat3_mul(t1, Wc, t2);
+        std::memcpy(&Ru[9 * (size_t)c], t2, sizeof t2);
+        // adjoint form: prolongation W_c Psi P Psi^{-1} W_p^{-1}
+        mat3_mul(Wc, &kPsi[0][0], t1);
+        mat3_mul(t1, P0, t2);
+        mat3_mul(t2, &kPsiInv[0][0], t1);
+        mat3_mul(t1, Wpi, t2);
+        std::memcpy(&Pa[9 * (size_t)c], t2, sizeof t2);
+        // adjoint form: restriction Psi^{-1} P^T Psi
+        mat3_mul(&kPsiInv[0][0], PT, t1);
+        mat3_mul(t1, &kPsi[0][0], t2);
+        std::memcpy(&Ra[9 * (size_t)c], t2, sizeof t2);
+        std::memcpy(&Pc[9 * (size_t)c], P0, sizeof P0);
+        std::memcpy(&Rc[9 * (size_t)c], PT, sizeof PT);
+      }
+      D.owner = h->upload(H.owner);
+      D.Pu = h->upload(Pu);
+      D.Ru = h->upload(Ru);
+      D.Pa = h->upload(Pa);
+      D.Ra = h->upload(Ra);
+      D.Pc = h->upload(Pc);
+      D.Rc = h->upload(Rc);
+      D.first_child = h->upload(H.first_child);
+      D.n_child = h->upload(H.n_child);
+    }
+    const long long n = (long long)D.A * g.S;
+    D.f64 = h->alloc<double>(n);
+    D.u64 = h->alloc<double>(n);
+    D.sa64 = h->alloc<double>(n);
+    D.sb64 = h->alloc<double>(n);
+    tr::launch_fill<double>(D.f64, n, 0.0, nullptr);
+    tr::launch_fill<double>(D.u64, n, 0.0, nullptr);
+  }
+  const long long nf = h->vec_len(h->top());
+  h->tmp = h->alloc<double>(nf);
+  h->tmp2 = h->alloc<double>(nf);
+  h->dot_partial = h->alloc<double>(h->dot_blocks);
+  h->dot_out = h->alloc<double>(1);
+  HIPCHK(hipDeviceSynchronize());
+}
+
+void ensure_mixed(tr_handle *h) {
+  if (h->mixed_ready) return;
+  for (int l = 1; l < (int)h->lv.size(); ++l) {
+    DevLevel &D = h->lv[l];
+    const long long n = (long long)D.A * h->g.S;
+    D.f32 = h->alloc<float>(n);
+    D.u32 = h->alloc<float>(n);
+    D.sa32 = h->alloc<float>(n);
+    D.sb32 = h->alloc<float>(n);
+  }
+  h->mixed_ready = true;
+}
+
+// --------------------------------------------------------------- pieces
+template <typename T>
+struct LevelBuf;
+template <>
+struct LevelBuf<double> {
+  static double *f(DevLevel &D) { return D.f64; }
+  static double *u(DevLevel &D) { return D.u64; }
+  static double *sa(DevLevel &D) { return D.sa64; }
+  static double *sb(DevLevel &D) { return D.sb64; }
+  static const double *G(DevLevel &D, bool adj) { return adj ? D.Gt64 : D.G64; }
+  static const double *St(DevLevel &D) { return D.St64; }
+};
+template <>
+struct LevelBuf<float> {
+  static float *f(DevLevel &D) { return D.f32; }
+  static float *u(DevLevel &D) { return D.u32; }
+  static float *sa(DevLevel &D) { return D.sa32; }
+  static float *sb(DevLevel &D) { return D.sb32; }
+  static const float *G(DevLevel &D, bool adj) { return adj ? D.Gt32 : D.G32; }
+  static const float *St(DevLevel &D) { return D.St32; }
+};
+
+template <typename T>
+void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipStream_t st) {
+  tr::SweepArgs<T> a;
+  a.f = f;
+  a.s = s;
+  a.u = u;
+  a.sig_t = h->sig_t;
+  a.sig_s = h->sig_s;
+  a.ord = h->lv[l].ord;
+  a.pl = h->pl;
+  a.g = h->g;
+  const bool fine = l == h->top();
+  tbegin(h, fine ? C_SWEEP_FINE : C_SWEEP);
+  tr::launch_sweep<T>(a, h->lv[l].A, adj, st);
+  tend(h);
+}
+
+template <typename T>
+void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st) {
+  tbegin(h, C_SCATTER);
+  tr::launch_gemm<T>(G, x, y, A, (int)h->g.S, A, st);
+  tend(h);
+}
+
+void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipStream_t st) {
+  DevLevel &D = h->lv[0];
+  tbegin(h, C_COARSE);
+  tr::launch_coarse_gs(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->plane_off_host.data(), h->g,
+                       nu, h->octant_order, adj, st);
+  tend(h);
+}
+
+// Fig. lmg on level l >= 0 in ordinate form; f (level l's f buffer) is the
+// right-hand side, the result is left in level l's u buffer.
+template <typename T>
+void mg_level(tr_handle *h, int l, bool adj, hipStream_t st);
+
+template <typename Tc>
+struct Coarse;
+
+template <typename T>
+void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
+  DevLevel &D = h->lv[l];
+  const int nu_pre = h->prob.nu_pre, nu_post = h->prob.nu_post;
+  T *f = LevelBuf<T>::f(D), *u = LevelBuf<T>::u(D);
+  T *sa = LevelBuf<T>::sa(D), *sb = LevelBuf<T>::sb(D);
+  const T *G = LevelBuf<T>::G(D, adj);
+  // pre-smoothing (source iteration from zero)
+  do_sweep<T>(h, l, f, nullptr, u, adj, st);
+  T *s_prev = nullptr;
+  for (int it = 1; it < nu_pre; ++it) {
+    do_gemm<T>(h, G, u, sa, D.A, st);
+    do_sweep<T>(h, l, f, sa, u, adj, st);
+    s_prev = sa;
+    std::swap(sa, sb);
+  }
+  // residual S (u - u_prev), restricted to level l-1
+  do_gemm<T>(h, G, u, sa, D.A, st);
+  DevLevel &Dc = h->lv[l - 1];
+  tbegin(h, C_TRANSFER);
+  if (l - 1 == 0)
+    tr::launch_restrict<T, double>(sa, s_prev, Dc.f64, adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P, h->sig_s,
+                                   true, h->g, st);
+  else
+    tr::launch_restrict<T, T>(sa, s_prev, LevelBuf<T>::f(Dc), adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P,
+                              h->sig_s, true, h->g, st);
+  tend(h);
+  if (l - 1 == 0)
+    do_coarse(h, Dc.f64, Dc.u64, h->prob.nu_coarse, adj, st);
+  else
+    mg_level<T>(h, l - 1, adj, st);
+  tbegin(h, C_TRANSFER);
+  if (l - 1 == 0)
+    tr::launch_prolong<double, T>(Dc.u64, u, adj ? D.Pa : D.Pu, D.owner, D.P, h->g.S, true, st);
+  else
+    tr::launch_prolong<T, T>(LevelBuf<T>::u(Dc), u, adj ? D.Pa : D.Pu, D.owner, D.P, h->g.S, true, st);
+  tend(h);
+  for (int it = 0; it < nu_post; ++it) {
+    do_gemm<T>(h, G, u, sa, D.A, st);
+    do_sweep<T>(h, l, f, sa, u, adj, st);
+  }
+}
+
+// z = M^{-1} r (canonical FP64 in and out)
+void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st) {
+  const int L = h->top();
+  DevLevel &D = h->lv[L];
+  const double *pre_in = nullptr, *post_in = adj ? nullptr : D.winv;
+  const double *pre_out = adj ? D.winv : nullptr, *post_out = nullptr;
+  if (mode == TR_PREC_SG) {
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, double>(r, D.f64, D.P, h->g.S, pre_in, post_in, st);
+    tend(h);
+    do_sweep<double>(h, L, D.f64, nullptr, D.u64, adj, st);
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st);
+    tend(h);
+    return;
+  }
+  if (L == 0) {
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, double>(r, D.f64, D.P, h->g.S, pre_in, post_in, st);
+    tend(h);
+    do_coarse(h, D.f64, D.u64, h->prob.nu_coarse, adj, st);
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st);
+    tend(h);
+    return;
+  }
+  if (mode == TR_PREC_MIXED) {
+    ensure_mixed(h);
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, float>(r, D.f32, D.P, h->g.S, pre_in, post_in, st);
+    tend(h);
+    mg_level<float>(h, L, adj, st);
+    tbegin(h, C_OTHER);
+    tr::launch_convert<float, double>(D.u32, z, D.P, h->g.S, pre_out, post_out, st);
+    tend(h);
+  } else {
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, double>(r, D.f64, D.P, h->g.S, pre_in, post_in, st);
+    tend(h);
+    mg_level<double>(h, L, adj, st);
+    tbegin(h, C_OTHER);
+    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st);
+    tend(h);
+  }
+}
+
+// y = A x (adj: A^T x), canonical FP64 on the finest level
+void apply_A(tr_handle *h, bool adj, const double *x, double *y, hipStream_t st) {
+  DevLevel &D = h->lv[h->top()];
+  tbegin(h, C_SCATTER);
+  tr::launch_gemm<double>(h->Souter, x, h->tmp, D.A, (int)h->g.S, D.A, st);
+  tend(h);
+  tbegin(h, C_APPLY);
+  tr::launch_apply(x, h->tmp, y, h->sig_t, h->sig_s, D.ord, D.w, D.P, h->g, adj, st);
+  tend(h);
+}
+
+double dot(tr_handle *h, const double *x, const double *y, long long n, hipStream_t st) {
+  tr::launch_dot_partial(x, y, n, h->dot_partial, h->dot_blocks, st);
+  tr::launch_dot_final(h->dot_partial, h->dot_blocks, h->dot_out, st);
+  double v = 0;
+  HIPCHK(hipMemcpyAsync(&v, h->dot_out, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return v;
+}
+
+void ensure_krylov(tr_handle *h, int m) {
+  if (h->kry_m >= m) return;
+  const long long n = h->vec_len(h->top());
+  while ((int)h->V.size() < m + 1) h->V.push_back(h->alloc<double>(n));
+  // keep M^{-1} v_j (flexible form) when it fits in a quarter of free memory
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  const size_t need = (size_t)m * n * sizeof(double);
+  if (need < fr / 4) {
+    while ((int)h->Z.size() < m) h->Z.push_back(h->alloc<double>(n));
+  } else {
+    h->Z.clear();
+  }
+  if (!h->kw) h->kw = h->alloc<double>(n);
+  if (!h->kx) h->kx = h->alloc<double>(n);
+  h->kry_m = m;
+}
+
+// Restarted right-preconditioned GMRES(m), x0 = 0, modified Gram-Schmidt.
+int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
+          hipStream_t st) {
+  const int m = o->restart;
+  ensure_krylov(h, m);
+  const long long n = h->vec_len(h->top());
+  const bool keepZ = (int)h->Z.size() >= m;
+  double *w = h->kw;
+  tr::launch_fill<double>(x, n, 0.0, st);
+  tbegin(h, C_ORTH);
+  const double bnorm = std::sqrt(dot(h, b, b, n, st));
+  tend(h);
+  stats->iters = 0;
+  stats->restarts = 0;
+  stats->converged = 0;
+  stats->rel_res = 0;
+  if (bnorm == 0.0) {
+    stats->converged = 1;
+    return TR_OK;
+  }
+  HIPCHK(hipMemcpyAsync(h->V[0], b, n * sizeof(double), hipMemcpyDeviceToDevice, st));  // r0 = b
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  for (int cycle = 0; cycle <= o->max_restarts; ++cycle) {
+    tbegin(h, C_ORTH);
+    const double beta = std::sqrt(dot(h, h->V[0], h->V[0], n, st));
+    tend(h);
+    stats->rel_res = beta / bnorm;
+    stats->restarts = cycle;
+    if (beta / bnorm < o->tol) {
+      stats->converged = 1;
+      return TR_OK;
+    }
+    if (cycle == o->max_restarts) break;
+    tbegin(h, C_ORTH);
+    tr::launch_scal(n, 1.0 / beta, h->V[0], st);
+    tend(h);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double *zj = keepZ ? h->Z[j] : h->tmp2;
+      precondition(h, o->prec_mode, adj, h->V[j], zj, st);
+      apply_A(h, adj, zj, w, st);
+      stats->iters++;
+      tbegin(h, C_ORTH);
+      for (int i = 0; i <= j; ++i) {
+        const double hij = dot(h, w, h->V[i], n, st);
+        H[(size_t)i * m + j] = hij;
+        tr::launch_axpy(n, -hij, h->V[i], w, st);
+      }
+      const double hn = std::sqrt(dot(h, w, w, n, st));
+      tend(h);
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = t;
+      }
+      const double rho = std::hypot(H[(size_t)j * m + j], hn);
+      cs[j] = H[(size_t)j * m + j] / rho;
+      sn[j] = hn / rho;
+      const bool breakdown = hn == 0.0;
+      if (!breakdown) {
+        tbegin(h, C_ORTH);
+        tr::launch_axpby(n, 1.0 / hn, w, 0.0, w, h->V[j + 1], st);
+        tend(h);
+      }
+      H[(size_t)j * m + j] = rho;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      k = j + 1;
+      if (std::fabs(gv[j + 1]) / bnorm < o->tol || breakdown) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int jj = i + 1; jj < k; ++jj) t -= H[(size_t)i * m + jj] * y[jj];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    tbegin(h, C_ORTH);
+    if (keepZ) {
+      for (int i = 0; i < k; ++i) tr::launch_axpy(n, y[i], h->Z[i], x, st);
+    } else {
+      tr::launch_fill<double>(w, n, 0.0, st);
+      for (int i = 0; i < k; ++i) tr::launch_axpy(n, y[i], h->V[i], w, st);
+    }
+    tend(h);
+    if (!keepZ) {
+      precondition(h, o->prec_mode, adj, w, h->tmp2, st);
+      tbegin(h, C_ORTH);
+      tr::launch_axpy(n, 1.0, h->tmp2, x, st);
+      tend(h);
+    }
+    // explicit residual r = b - A x into V[0]
+    apply_A(h, adj, x, w, st);
+    tbegin(h, C_ORTH);
+    tr::launch_axpby(n, 1.0, b, -1.0, w, h->V[0], st);
+    tend(h);
+  }
+  return TR_ERR_NOCONV;
+}
+
+void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
+  s->ms_total = ms_total;
+  s->ms_sweep = s->ms_scatter = s->ms_transfer = s->ms_coarse = s->ms_apply = s->ms_orth = s->ms_other = 0;
+  s->n_sweep = s->n_scatter = s->n_coarse = 0;
+  s->ms_sweep_finest = 0;
+  s->n_sweep_finest = 0;
+  if (!h->timer) return;
+  for (auto &r : h->timer->recs) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    switch (r.comp) {
+      case C_SWEEP: s->ms_sweep += ms; s->n_sweep++; break;
+      case C_SWEEP_FINE: s->ms_sweep += ms; s->n_sweep++; s->ms_sweep_finest += ms; s->n_sweep_finest++; break;
+      case C_SCATTER: s->ms_scatter += ms; s->n_scatter++; break;
+      case C_TRANSFER: s->ms_transfer += ms; break;
+      case C_COARSE: s->ms_coarse += ms; s->n_coarse++; break;
+      case C_APPLY: s->ms_apply += ms; break;
+      case C_ORTH: s->ms_orth += ms; break;
+      default: s->ms_other += ms; break;
+    }
+  }
+}
+
+int translate(const std::function<int()> &fn) {
+  try {
+    return fn();
+  } catch (const ArgError &e) {
+    return fail(TR_ERR_ARG, e.msg);
+  } catch (const HipError &e) {
+    return fail(TR_ERR_HIP, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  } catch (const std::bad_alloc &) {
+    return fail(TR_ERR_ALLOC, "out of memory");
+  } catch (const std::exception &e) {
+    return fail(TR_ERR_HIP, e.what());
+  }
+}
+
+int check_level(tr_handle *h, int level) {
+  if (!h) return fail(TR_ERR_ARG, "null handle");
+  if (level < 0 || level > h->top()) return fail(TR_ERR_ARG, "level out of range");
+  return TR_OK;
+}
+
+hipStream_t S(tr_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *tr_last_error(void) { return g_err.c_str(); }
+
+int tr_setup(const tr_problem *prob, tr_handle **out) {
+  if (!prob || !out) return fail(TR_ERR_ARG, "null argument");
+  *out = nullptr;
+  tr_handle *h = nullptr;
+  int rc = translate([&]() {
+    h = new tr_handle();
+    build(h, prob);
+    return TR_OK;
+  });
+  if (rc != TR_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return TR_OK;
+}
+
+void tr_destroy(tr_handle *h) { delete h; }
+
+int tr_info(const tr_handle *h, tr_info_t *out) {
+  if (!h || !out) return fail(TR_ERR_ARG, "null argument");
+  std::memset(out, 0, sizeof *out);
+  out->dim = h->g.dim;
+  out->cells = (int)h->g.C;
+  out->spatial_dofs = (int)h->g.S;
+  out->n_levels = (int)h->lv.size();
+  for (size_t l = 0; l < h->lv.size(); ++l) out->patches[l] = h->lv[l].P;
+  out->order_outer = h->prob.order;
+  out->device_bytes = h->bytes;
+  return TR_OK;
+}
+
+int tr_set_sigma(tr_handle *h, const double *sigma_t, const double *sigma_s, tr_stream st) {
+  if (!h || !sigma_t || !sigma_s) return fail(TR_ERR_ARG, "null argument");
+  return translate([&]() {
+    HIPCHK(hipMemcpyAsync(h->sig_t, sigma_t, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
+    HIPCHK(hipMemcpyAsync(h->sig_s, sigma_s, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
+    return TR_OK;
+  });
+}
+
+int tr_rhs(tr_handle *h, const double *q_cell, const tr_inflow *in, double *b, tr_stream st) {
+  if (!h || !b) return fail(TR_ERR_ARG, "null argument");
+  return translate([&]() {
+    const int L = h->top();
+    DevLevel &D = h->lv[L];
+    const tr::HostLevel &H = h->ang.lv[L];
+    const Grid &g = h->g;
+    tr::launch_rhs_volume(b, q_cell, D.ipsi, D.A, g, S(st));
+    if (!in || in->kind == TR_INFLOW_NONE) return TR_OK;
+    if (in->kind != TR_INFLOW_ISO && in->kind != TR_INFLOW_BEAM) throw ArgError{"unknown inflow kind"};
+    if (in->axis < 0 || in->axis >= g.dim || (in->side != 0 && in->side != 1)) throw ArgError{"bad inflow face"};
+    const int ax = in->axis, side = in->side;
+    const double sigma_f = side == 0 ? -1.0 : 1.0;
+    // cells of the face box
+    std::vector<int> cells;
+    for (int iz = 0; iz < g.n[2]; ++iz)
+      for (int iy = 0; iy < g.n[1]; ++iy)
+        for (int ix = 0; ix < g.n[0]; ++ix) {
+          int c[3] = {ix, iy, iz};
+          if (c[ax] != (side == 0 ? 0 : g.n[ax] - 1)) continue;
+          bool ok = true;
+          for (int d = 0; d < g.dim; ++d)
+            if (d != ax && (c[d] < in->lo[d] || c[d] > in->hi[d])) ok = false;
+          if (ok) cells.push_back(ix + g.n[0] * (iy + g.n[1] * iz));
+        }
+    // face integral of each node: nodes on the face get prod_{other} h / 2
+    std::vector<double> fint(g.ns, 0.0);
+    for (int b2 = 0; b2 < g.ns; ++b2) {
+      if (((b2 >> ax) & 1) != side) continue;
+      double v = 1.0;
+      for (int d = 0; d < g.dim; ++d)
+        if (d != ax) v *= g.h[d] / 2.0;
+      fint[b2] = v;
+    }
+    std::vector<double> coef(D.A, 0.0);
+    if (in->kind == TR_INFLOW_ISO) {
+      for (int q = 0; q < D.P; ++q) {
+        const double s = (H.octant[q] >> ax) & 1 ? -1.0 : 1.0;
+        if (sigma_f * s >= 0) continue;  // not incoming through this face
+        for (int m = 0; m < 3; ++m) coef[3 * q + m] = -sigma_f * in->value * H.iom[3 * (3 * q + m) + ax];
+      }
+    } else {
+      double dn = std::sqrt(in->direction[0] * in->direction[0] + in->direction[1] * in->direction[1] +
+                            in->direction[2] * in->direction[2]);
+      if (!(dn > 0)) throw ArgError{"beam direction must be nonzero"};
+      tr::V3 d{in->direction[0] / dn, in->direction[1] / dn, in->direction[2] / dn};
+      const double dd[3] = {d.x, d.y, d.z};
+      if (-sigma_f * dd[ax] <= 0) throw ArgError{"beam direction does not enter through the face"};
+      std::vector<std::pair<int, std::array<double, 3>>> hits;
+      for (int q = 0; q < D.P; ++q) {
+        const tr::PatchNode &pn = h->ang.tree[H.node[q]];
+        double sx = (pn.octant & 1) ? -1 : 1, sy = (pn.octant & 2) ? -1 : 1, sz = (pn.octant & 4) ? -1 : 1;
+        if (sx * d.x + sy * d.y + sz * d.z <= 1e-14) continue;
+        double psi[3];
+        tr::lin_basis(pn, d, psi);
+        if (psi[0] >= -1e-12 && psi[1] >= -1e-12 && psi[2] >= -1e-12) hits.push_back({q, {psi[0], psi[1], psi[2]}});
+      }
+      for (auto &hq : hits)
+        for (int m = 0; m < 3; ++m) coef[3 * hq.first + m] = in->value * hq.second[m] / (double)hits.size();
+    }
+    TmpBuf tcoef(D.A * sizeof(double)), tcells(cells.size() * sizeof(int)), tfint(g.ns * sizeof(double));
+    double *dcoef = tcoef.as<double>(), *dfint = tfint.as<double>();
+    int *dcells = tcells.as<int>();
+    HIPCHK(hipMemcpyAsync(dcoef, coef.data(), D.A * sizeof(double), hipMemcpyHostToDevice, S(st)));
+    if (!cells.empty())
+      HIPCHK(hipMemcpyAsync(dcells, cells.data(), cells.size() * sizeof(int), hipMemcpyHostToDevice, S(st)));
+    HIPCHK(hipMemcpyAsync(dfint, fint.data(), g.ns * sizeof(double), hipMemcpyHostToDevice, S(st)));
+    tr::launch_rhs_face(b, dcoef, dcells, (int)cells.size(), dfint, D.A, g, S(st));
+    HIPCHK(hipStreamSynchronize(S(st)));
+    return TR_OK;
+  });
+}
+
+int tr_detector(tr_handle *h, const int lo[3], const int hi[3], double *w, tr_stream st) {
+  if (!h || !lo || !hi || !w) return fail(TR_ERR_ARG, "null argument");
+  return translate([&]() {
+    DevLevel &D = h->lv[h->top()];
+    tr::launch_detector(w, D.ipsi, D.A, h->g, lo, hi, S(st));
+    return TR_OK;
+  });
+}
+
+static int sweep_common(tr_handle *h, int level, int prec, const void *g, void *phi, bool adj, tr_stream st) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!g || !phi) return fail(TR_ERR_ARG, "null buffer");
+  if (prec != TR_F64 && prec != TR_F32) return fail(TR_ERR_ARG, "bad precision");
+  return translate([&]() {
+    DevLevel &D = h->lv[level];
+    const double *pre_in = nullptr, *post_in = adj ? nullptr : D.winv;
+    const double *pre_out = adj ? D.winv : nullptr;
+    if (prec == TR_F64) {
+      tr::launch_convert<double, double>((const double *)g, D.f64, D.P, h->g.S, pre_in, post_in, S(st));
+      do_sweep<double>(h, level, D.f64, nullptr, D.u64, adj, S(st));
+      tr::launch_convert<double, double>(D.u64, (double *)phi, D.P, h->g.S, pre_out, nullptr, S(st));
+    } else {
+      const size_t bytes = (size_t)h->vec_len(level) * sizeof(float);
+      TmpBuf tf(bytes), tu(bytes);
+      float *f = tf.as<float>(), *u = tu.as<float>();
+      tr::launch_convert<float, float>((const float *)g, f, D.P, h->g.S, pre_in, post_in, S(st));
+      do_sweep<float>(h, level, f, nullptr, u, adj, S(st));
+      tr::launch_convert<float, float>(u, (float *)phi, D.P, h->g.S, pre_out, nullptr, S(st));
+      HIPCHK(hipStreamSynchronize(S(st)));
+    }
+    return TR_OK;
+  });
+}
+
+int tr_sweep(tr_handle *h, int level, int prec, const void *g, void *phi, tr_stream st) {
+  return sweep_common(h, level, prec, g, phi, false, st);
+}
+
+int tr_sweep_adjoint(tr_handle *h, int level, int prec, const void *g, void *lam, tr_stream st) {
+  return sweep_common(h, level, prec, g, lam, true, st);
+}
+
+int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, void *s, tr_stream st) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!phi || !s) return fail(TR_ERR_ARG, "null buffer");
+  if (outer && level != h->top()) return fail(TR_ERR_ARG, "the problem operator lives on the finest level");
+  if (prec != TR_F64 && prec != TR_F32) return fail(TR_ERR_ARG, "bad precision");
+  if (outer && prec != TR_F64) return fail(TR_ERR_UNSUPPORTED, "the problem operator is FP64 only");
+  return translate([&]() {
+    DevLevel &D = h->lv[level];
+    if (prec == TR_F64) {
+      const double *St = outer ? h->Souter : D.St64;
+      double *t = level == h->top() ? h->tmp : D.sb64;
+      tr::launch_gemm<double>(St, (const double *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+      tr::launch_scale_sn<double>(t, (double *)s, h->sig_s, D.A, h->g, S(st));
+    } else {
+      TmpBuf tb((size_t)h->vec_len(level) * sizeof(float));
+      float *t = tb.as<float>();
+      tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+      tr::launch_scale_sn<float>(t, (float *)s, h->sig_s, D.A, h->g, S(st));
+      HIPCHK(hipStreamSynchronize(S(st)));
+    }
+    return TR_OK;
+  });
+}
+
+int tr_apply(tr_handle *h, const double *x, double *y, tr_stream st) {
+  if (!h || !x || !y) return fail(TR_ERR_ARG, "null argument");
+  return translate([&]() {
+    apply_A(h, false, x, y, S(st));
+    return TR_OK;
+  });
+}
+
+int tr_transfer(tr_handle *h, int level, int dir, int prec, const void *in, void *out, tr_stream st) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (level < 1) return fail(TR_ERR_ARG, "transfers act between levels l-1 and l >= 1");
+  if (!in || !out) return fail(TR_ERR_ARG, "null buffer");
+  if (dir != TR_RESTRICT && dir != TR_PROLONG) return fail(TR_ERR_ARG, "bad direction");
+  return translate([&]() {
+    DevLevel &D = h->lv[level], &Dc = h->lv[level - 1];
+    if (dir == TR_PROLONG) {
+      if (prec == TR_F64)
+        tr::launch_prolong<double, double>((const double *)in, (double *)out, D.Pc, D.owner, D.P, h->g.S, false, S(st));
+      else
+        tr::launch_prolong<float, float>((const float *)in, (float *)out, D.Pc, D.owner, D.P, h->g.S, false, S(st));
+    } else {
+      if (prec == TR_F64)
+        tr::launch_restrict<double, double>((const double *)in, nullptr, (double *)out, D.Rc, D.first_child,
+                                            D.n_child, Dc.P, nullptr, false, h->g, S(st));
+      else
+        tr::launch_restrict<float, float>((const float *)in, nullptr, (float *)out, D.Rc, D.first_child, D.n_child,
+                                          Dc.P, nullptr, false, h->g, S(st));
+    }
+    return TR_OK;
+  });
+}
+
+int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi, tr_stream st) {
+  if (!h || !f || !phi) return fail(TR_ERR_ARG, "null argument");
+  if (nu < 1) return fail(TR_ERR_ARG, "nu must be >= 1");
+  return translate([&]() {
+    DevLevel &D = h->lv[0];
+    const bool adj = adjoint != 0;
+    tr::launch_convert<double, double>(f, D.f64, D.P, h->g.S, nullptr, adj ? nullptr : D.winv, S(st));
+    do_coarse(h, D.f64, D.u64, nu, adj, S(st));
+    tr::launch_convert<double, double>(D.u64, phi, D.P, h->g.S, adj ? D.winv : nullptr, nullptr, S(st));
+    return TR_OK;
+  });
+}
+
+int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, double *z, tr_stream st) {
+  if (!h || !r || !z) return fail(TR_ERR_ARG, "null argument");
+  if (prec_mode != TR_PREC_F64 && prec_mode != TR_PREC_MIXED && prec_mode != TR_PREC_SG)
+    return fail(TR_ERR_ARG, "bad preconditioner mode");
+  return translate([&]() {
+    precondition(h, prec_mode, adjoint != 0, r, z, S(st));
+    return TR_OK;
+  });
+}
+
+static int solve_common(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o,
+                        tr_solve_stats *stats, tr_stream st) {
+  if (!h || !b || !x || !o || !stats) return fail(TR_ERR_ARG, "null argument");
+  if (o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->tol > 0))
+    return fail(TR_ERR_ARG, "bad solver options");
+  if (o->prec_mode != TR_PREC_F64 && o->prec_mode != TR_PREC_MIXED && o->prec_mode != TR_PREC_SG)
+    return fail(TR_ERR_ARG, "bad preconditioner mode");
+  std::unique_ptr<EventTimer> timer;
+  int rc = translate([&]() {
+    if (o->timing) {
+      timer.reset(new EventTimer());
+      timer->on = true;
+      timer->st = S(st);
+      h->timer = timer.get();
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, S(st)));
+    int r = gmres(h, adj, b, x, o, stats, S(st));
+    HIPCHK(hipEventRecord(e1, S(st)));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    fill_stats(h, stats, ms);
+    h->timer = nullptr;
+    return r;
+  });
+  h->timer = nullptr;
+  if (rc == TR_ERR_NOCONV) g_err = "GMRES reached max_restarts before the tolerance";
+  return rc;
+}
+
+int tr_gmres_solve(tr_handle *h, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
+                   tr_stream st) {
+  return solve_common(h, false, b, x, o, stats, st);
+}
+
+int tr_adjoint_grad(tr_handle *h, const double *w, const double *phi, double *lambda, double *grad_t, double *grad_s,
+                    const tr_solve_opts *o, tr_solve_stats *stats, tr_stream st) {
+  if (!h || !w || !phi || !grad_t || !grad_s || !o || !stats) return fail(TR_ERR_ARG, "null argument");
+  double *lam = lambda;
+  int rc = TR_OK;
+  rc = translate([&]() {
+    if (!lam) lam = h->kx ? h->kx : (h->kx = h->alloc<double>(h->vec_len(h->top())));
+    return TR_OK;
+  });
+  if (rc) return rc;
+  rc = solve_common(h, true, w, lam, o, stats, st);
+  if (rc != TR_OK && rc != TR_ERR_NOCONV) return rc;
+  int rc2 = translate([&]() {
+    DevLevel &D = h->lv[h->top()];
+    tr::launch_grad_t(lam, phi, D.w, D.P, h->g, grad_t, S(st));
+    tr::launch_gemm<double>(h->Souter, phi, h->tmp, D.A, (int)h->g.S, D.A, S(st));
+    tr::launch_grad_s(lam, h->tmp, D.A, h->g, grad_s, S(st));
+    HIPCHK(hipStreamSynchronize(S(st)));
+    return TR_OK;
+  });
+  return rc2 ? rc2 : rc;
+}
+
+int tr_time_sweep_kernel(tr_handle *h, int level, int prec, int reps, double *ms, tr_stream st) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!ms || reps < 1) return fail(TR_ERR_ARG, "bad argument");
+  return translate([&]() {
+    DevLevel &D = h->lv[level];
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    if (prec == TR_F32) {
+      if (level == 0) throw ArgError{"FP32 sweeps run on levels >= 1"};
+      ensure_mixed(h);
+      tr::launch_cast<double, float>(D.f64, D.f32, h->vec_len(level), S(st));
+      do_sweep<float>(h, level, D.f32, nullptr, D.u32, false, S(st));
+      HIPCHK(hipEventRecord(e0, S(st)));
+      for (int i = 0; i < reps; ++i) do_sweep<float>(h, level, D.f32, nullptr, D.u32, false, S(st));
+    } else {
+      do_sweep<double>(h, level, D.f64, nullptr, D.u64, false, S(st));
+      HIPCHK(hipEventRecord(e0, S(st)));
+      for (int i = 0; i < reps; ++i) do_sweep<double>(h, level, D.f64, nullptr, D.u64, false, S(st));
+    }
+    HIPCHK(hipEventRecord(e1, S(st)));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return TR_OK;
+  });
+}
+
+int tr_time_scatter_kernel(tr_handle *h, int level, int outer, int prec, int reps, double *ms, tr_stream st) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (!ms || reps < 1) return fail(TR_ERR_ARG, "bad argument");
+  if (outer && level != h->top()) return fail(TR_ERR_ARG, "the problem operator lives on the finest level");
+  return translate([&]() {
+    DevLevel &D = h->lv[level];
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    if (prec == TR_F32) {
+      if (level == 0) throw ArgError{"FP32 runs on levels >= 1"};
+      ensure_mixed(h);
+      tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+      HIPCHK(hipEventRecord(e0, S(st)));
+      for (int i = 0; i < reps; ++i) tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+    } else {
+      const double *G = outer ? h->Souter : D.G64;
+      tr::launch_gemm<double>(G, D.u64, D.sa64, D.A, (int)h->g.S, D.A, S(st));
+      HIPCHK(hipEventRecord(e0, S(st)));
+      for (int i = 0; i < reps; ++i) tr::launch_gemm<double>(G, D.u64, D.sa64, D.A, (int)h->g.S, D.A, S(st));
+    }
+    HIPCHK(hipEventRecord(e1, S(st)));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return TR_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""Python face of the HIP transport library: a handle per problem, torch
+tensors for device memory and the current HIP stream for ordering.
+
+Every operation runs in the library's HIP kernels; this module only
+marshals arguments.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from .inputs import Problem
+
+_MODES = {"f64": _lib.TR_PREC_F64, "mixed": _lib.TR_PREC_MIXED, "sg": _lib.TR_PREC_SG}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Transport:
+    """One discretised problem on the current HIP device."""
+
+    def __init__(self, prob: Problem):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.lib = _lib.load()
+        self.prob = prob
+        p = _lib.TrProblem()
+        p.dim = prob.dim
+        for d in range(3):
+            p.n[d] = int(prob.n[d]) if d < len(prob.n) else 1
+            p.len[d] = float(prob.length[d])
+        a = prob.angular
+        p.ang_base_level = a.base_level
+        for d in range(3):
+            p.cone_axis[d] = float(a.cone_axis[d])
+        p.cone_half_angle_deg = float(a.cone_half_angle_deg)
+        p.cone_extra_levels = int(a.extra_levels)
+        p.irregularity_closure = 1 if a.closure else 0
+        self._st = np.ascontiguousarray(prob.sigma_t, dtype=np.float64)
+        self._ss = np.ascontiguousarray(prob.sigma_s, dtype=np.float64)
+        self._mom = np.ascontiguousarray(prob.moments(max([prob.order] + list(prob.mg_orders))), dtype=np.float64)
+        self._ord = np.ascontiguousarray(prob.mg_orders, dtype=np.int32)
+        p.sigma_t = self._st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.sigma_s = self._ss.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.order = prob.order
+        p.moments = self._mom.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.n_levels = len(prob.mg_orders)
+        p.mg_order = self._ord.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        p.nu_pre, p.nu_post, p.nu_coarse = prob.nu_pre, prob.nu_post, prob.nu_coarse
+        for i in range(8):
+            p.octant_order[i] = i
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.tr_setup(ctypes.byref(p), ctypes.byref(h)))
+        self.h = h
+        info = _lib.TrInfo()
+        _lib.check(self.lib.tr_info(self.h, ctypes.byref(info)))
+        self.info = info
+        self.C = info.cells
+        self.S = info.spatial_dofs
+        self.patches = [info.patches[l] for l in range(info.n_levels)]
+        self.nlev = info.n_levels
+        self.dev = torch.device("cuda")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ sizes
+    def n(self, level=None):
+        level = self.nlev - 1 if level is None else level
+        return 3 * self.patches[level] * self.S
+
+    def zeros(self, level=None, dtype=None):
+        torch = _torch()
+        return torch.zeros(self.n(level), dtype=dtype or torch.float64, device=self.dev)
+
+    # ------------------------------------------------------------ data
+    def rhs(self):
+        torch = _torch()
+        prob = self.prob
+        b = self.zeros()
+        q = torch.as_tensor(np.asarray(prob.q_cell, dtype=np.float64), device=self.dev)
+        inf = None
+        if prob.inflow is not None:
+            f = prob.inflow
+            inf = _lib.TrInflow()
+            inf.kind = _lib.TR_INFLOW_ISO if f.kind == "iso" else _lib.TR_INFLOW_BEAM
+            inf.axis, inf.side = f.axis, f.side
+            for d in range(3):
+                inf.lo[d] = int(min(f.lo[d], 2 ** 30))
+                inf.hi[d] = int(min(f.hi[d], 2 ** 30))
+                inf.direction[d] = float(f.direction[d])
+            inf.value = float(f.value)
+        _lib.check(self.lib.tr_rhs(self.h, _ptr(q), ctypes.byref(inf) if inf is not None else None, _ptr(b),
+                                   _stream()))
+        return b
+
+    def detector(self, lo=None, hi=None):
+        if lo is None:
+            lo, hi = self.prob.detector
+        w = self.zeros()
+        lo_a = (ctypes.c_int * 3)(*[int(v) for v in lo])
+        hi_a = (ctypes.c_int * 3)(*[int(v) for v in hi])
+        _lib.check(self.lib.tr_detector(self.h, lo_a, hi_a, _ptr(w), _stream()))
+        return w
+
+    def set_sigma(self, sigma_t, sigma_s):
+        torch = _torch()
+        st = torch.as_tensor(sigma_t, dtype=torch.float64, device=self.dev).contiguous()
+        ss = torch.as_tensor(sigma_s, dtype=torch.float64, device=self.dev).contiguous()
+        _lib.check(self.lib.tr_set_sigma(self.h, _ptr(st), _ptr(ss), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    # ------------------------------------------------------------ operators
+    def _prec(self, t):
+        torch = _torch()
+        return _lib.TR_F64 if t.dtype == torch.float64 else _lib.TR_F32
+
+    def sweep(self, level, g, adjoint=False):
+        out = _torch().empty_like(g)
+        fn = self.lib.tr_sweep_adjoint if adjoint else self.lib.tr_sweep
+        _lib.check(fn(self.h, level, self._prec(g), _ptr(g), _ptr(out), _stream()))
+        return out
+
+    def scatter(self, level, phi, outer=False):
+        out = _torch().empty_like(phi)
+        _lib.check(self.lib.tr_scatter(self.h, level, 1 if outer else 0, self._prec(phi), _ptr(phi), _ptr(out),
+                                       _stream()))
+        return out
+
+    def apply(self, x):
+        y = _torch().empty_like(x)
+        _lib.check(self.lib.tr_apply(self.h, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def prolong(self, level, xc):
+        torch = _torch()
+        out = torch.empty(self.n(level), dtype=xc.dtype, device=self.dev)
+        _lib.check(self.lib.tr_transfer(self.h, level, _lib.TR_PROLONG, self._prec(xc), _ptr(xc), _ptr(out),
+                                        _stream()))
+        return out
+
+    def restrict(self, level, xf):
+        torch = _torch()
+        out = torch.empty(self.n(level - 1), dtype=xf.dtype, device=self.dev)
+        _lib.check(self.lib.tr_transfer(self.h, level, _lib.TR_RESTRICT, self._prec(xf), _ptr(xf), _ptr(out),
+                                        _stream()))
+        return out
+
+    def coarse_gs(self, f, nu, adjoint=False):
+        out = _torch().empty_like(f)
+        _lib.check(self.lib.tr_coarse_gs(self.h, nu, 1 if adjoint else 0, _ptr(f), _ptr(out), _stream()))
+        return out
+
+    def vcycle(self, r, mode="f64", adjoint=False):
+        z = _torch().empty_like(r)
+        _lib.check(self.lib.tr_mg_vcycle(self.h, _MODES[mode], 1 if adjoint else 0, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def _opts(self, tol, restart, max_restarts, mode, timing):
+        o = _lib.TrSolveOpts()
+        o.tol = self.prob.tol if tol is None else tol
+        o.restart = self.prob.restart if restart is None else restart
+        o.max_restarts = max_restarts
+        o.prec_mode = _MODES[mode]
+        o.timing = 1 if timing else 0
+        return o
+
+    def solve(self, b, tol=None, restart=None, max_restarts=200, mode="f64", timing=False, check=True):
+        x = _torch().empty_like(b)
+        o = self._opts(tol, restart, max_restarts, mode, timing)
+        st = _lib.TrSolveStats()
+        rc = self.lib.tr_gmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st), _stream())
+        _lib.check(rc, allow=() if check else (_lib.TR_ERR_NOCONV,))
+        return x, st.as_dict()
+
+    def adjoint_grad(self, w, phi, tol=None, restart=None, max_restarts=200, mode="f64", timing=False):
+        torch = _torch()
+        lam = torch.empty_like(phi)
+        gt = torch.empty(self.C, dtype=torch.float64, device=self.dev)
+        gs = torch.empty(self.C, dtype=torch.float64, device=self.dev)
+        o = self._opts(tol, restart, max_restarts, mode, timing)
+        st = _lib.TrSolveStats()
+        _lib.check(self.lib.tr_adjoint_grad(self.h, _ptr(w), _ptr(phi), _ptr(lam), _ptr(gt), _ptr(gs),
+                                            ctypes.byref(o), ctypes.byref(st), _stream()))
+        return gt, gs, lam, st.as_dict()
+
+    def time_sweep_kernel(self, level=None, prec="f64", reps=10):
+        level = self.nlev - 1 if level is None else level
+        ms = ctypes.c_double()
+        _lib.check(self.lib.tr_time_sweep_kernel(self.h, level, _lib.TR_F64 if prec == "f64" else _lib.TR_F32,
+                                                 reps, ctypes.byref(ms), _stream()))
+        return ms.value
+
+    def time_scatter_kernel(self, level=None, outer=False, prec="f64", reps=10):
+        level = self.nlev - 1 if level is None else level
+        ms = ctypes.c_double()
+        _lib.check(self.lib.tr_time_scatter_kernel(self.h, level, 1 if outer else 0,
+                                                   _lib.TR_F64 if prec == "f64" else _lib.TR_F32, reps,
+                                                   ctypes.byref(ms), _stream()))
+        return ms.value

@@ -1,0 +1,136 @@
+"""GPU parity of every hot-path operator against the oracle, element by
+element, on seeded random inputs (FP64: relative 1e-12; FP32: 1e-5)."""
+import numpy as np
+import pytest
+
+from gpu_util import Pair, small, to_dev, to_np, rel, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(dim=2, n=3, level=1, order=4),            # ragged: S = 36
+    dict(dim=2, n=5, level=2, order=8, seed=1),    # S = 100, A = 384
+    dict(dim=3, n=3, level=1, order=6, seed=2),    # S = 216
+    dict(dim=3, n=4, level=2, order=10, seed=3),   # S = 512, A = 384 (several GEMM tiles)
+]
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)))
+def pair(request):
+    kw = CASES[request.param]
+    print("case", kw, flush=True)
+    return Pair(small(**kw))
+
+
+def _rand(n, seed):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def test_sweep_fp64(pair):
+    for l in range(pair.tr.nlev):
+        lv = pair.level(l)
+        g = _rand(lv.A * lv.grid.S, 10 + l)
+        got = to_np(pair.tr.sweep(l, to_dev(g)))
+        assert rel(got, lv.sweep(g)) < 1e-12, l
+
+
+def test_sweep_adjoint_fp64(pair):
+    for l in range(pair.tr.nlev):
+        lv = pair.level(l)
+        g = _rand(lv.A * lv.grid.S, 20 + l)
+        got = to_np(pair.tr.sweep(l, to_dev(g), adjoint=True))
+        assert rel(got, lv.sweep_T(g)) < 1e-12, l
+
+
+def test_sweep_fp32(pair):
+    torch = torch_mod()
+    l = pair.tr.nlev - 1
+    lv = pair.level(l)
+    g = _rand(lv.A * lv.grid.S, 30)
+    got = to_np(pair.tr.sweep(l, to_dev(g, torch.float32)))
+    assert rel(got, lv.sweep(g)) < 2e-5
+
+
+def test_scatter_levels_and_outer(pair):
+    for l in range(pair.tr.nlev):
+        lv = pair.level(l)
+        x = _rand(lv.A * lv.grid.S, 40 + l)
+        got = to_np(pair.tr.scatter(l, to_dev(x)))
+        assert rel(got, lv.apply_S(x)) < 1e-12, l
+    lv = pair.level(0, outer=True)
+    x = _rand(lv.A * lv.grid.S, 50)
+    got = to_np(pair.tr.scatter(pair.tr.nlev - 1, to_dev(x), outer=True))
+    assert rel(got, lv.apply_S(x)) < 1e-12
+
+
+def test_scatter_fp32(pair):
+    torch = torch_mod()
+    l = pair.tr.nlev - 1
+    lv = pair.level(l)
+    x = _rand(lv.A * lv.grid.S, 60)
+    got = to_np(pair.tr.scatter(l, to_dev(x, torch.float32)))
+    assert rel(got, lv.apply_S(x)) < 1e-5
+
+
+def test_apply(pair):
+    lv = pair.level(0, outer=True)
+    x = _rand(lv.A * lv.grid.S, 70)
+    got = to_np(pair.tr.apply(to_dev(x)))
+    assert rel(got, lv.apply_A(x)) < 1e-12
+
+
+def test_transfers(pair):
+    mg = pair.op.mg
+    S = mg.grid.S
+    for l in range(1, pair.tr.nlev):
+        xc = _rand(mg.levels[l - 1].A * S, 80 + l)
+        got = to_np(pair.tr.prolong(l, to_dev(xc)))
+        assert rel(got, mg.prolong(l, xc)) < 1e-14
+        xf = _rand(mg.levels[l].A * S, 90 + l)
+        got = to_np(pair.tr.restrict(l, to_dev(xf)))
+        assert rel(got, mg.restrict(l, xf)) < 1e-14
+
+
+@pytest.mark.parametrize("nu", [1, 3])
+def test_coarse_gauss_seidel(pair, nu):
+    lv0 = pair.op.mg.levels[0]
+    f = _rand(lv0.A * lv0.grid.S, 100 + nu)
+    got = to_np(pair.tr.coarse_gs(to_dev(f), nu))
+    assert rel(got, pair.op.mg.coarse_gs(f, nu)) < 1e-11
+    got = to_np(pair.tr.coarse_gs(to_dev(f), nu, adjoint=True))
+    assert rel(got, pair.op.mg.coarse_gs(f, nu, adjoint=True)) < 1e-11
+
+
+def test_vcycle_fp64(pair):
+    lv = pair.level(0, outer=True)
+    r = _rand(lv.A * lv.grid.S, 110)
+    got = to_np(pair.tr.vcycle(to_dev(r)))
+    assert rel(got, pair.op.mg.vcycle(r)) < 1e-11
+    got = to_np(pair.tr.vcycle(to_dev(r), adjoint=True))
+    assert rel(got, pair.op.mg.vcycle(r, adjoint=True)) < 1e-11
+    got = to_np(pair.tr.vcycle(to_dev(r), mode="sg"))
+    assert rel(got, lv.sweep(r)) < 1e-12
+
+
+def test_vcycle_mixed_precision(pair):
+    lv = pair.level(0, outer=True)
+    r = _rand(lv.A * lv.grid.S, 120)
+    got = to_np(pair.tr.vcycle(to_dev(r), mode="mixed"))
+    assert rel(got, pair.op.mg.vcycle(r)) < 1e-4
+
+
+def test_rhs_and_detector(pair):
+    prob = pair.prob
+    got = to_np(pair.tr.rhs())
+    assert rel(got, pair.op.rhs()) < 1e-13
+    lo, hi = (0, 1, 0), (1, 2, 1)
+    got = to_np(pair.tr.detector(lo, hi))
+    assert rel(got, pair.op.outer.detector_weights(lo, hi)) < 1e-13
+
+
+def test_determinism(pair):
+    lv = pair.level(0, outer=True)
+    r = to_dev(_rand(lv.A * lv.grid.S, 130))
+    a = to_np(pair.tr.vcycle(r))
+    b = to_np(pair.tr.vcycle(r))
+    assert np.array_equal(a, b)
