@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the angular-multigrid transport solver on one MI355X.
+
+One step = one full solve of the 3-D heterogeneous problem (unit cube,
+32^3 trilinear DG cells, angular level 2 = 128 patches x 3 ordinates, HG
+g = 0.95 at Legendre order 16, lognormal sigma_t, c = 0.98, central unit
+source, vacuum) to ||b - A x|| / ||b|| < 1e-8 with FP64 GMRES(10) and the
+FP64 angular-multigrid V(1,1) preconditioner, right-hand side already in HBM.
+Every transport sweep, scatter GEMM, transfer, coarse Gauss-Seidel sweep and
+Krylov update of the solve runs inside the timed region.
+
+value = sweep DoF-updates per second of the whole solve: the sum over all
+transport sweeps of (ordinates x spatial dofs), divided by the solve's wall
+time.  Also reported: the same solve with the FP32 V-cycle, the component
+breakdown, and the roofline of the finest-level sweep kernel measured with
+HIP events on the library's stream.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "local_solve.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2010_04559_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, digest):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "sweep_fp64_cfg2_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel") != kernel or d.get("sources_digest") != digest:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(prob):
+    """The oracle's transport sweep on a bounded sample of the same workload:
+    the 48 patches of three octants on the 32^3 grid (3/8 of one
+    finest-level sweep), FP64 numpy on the host."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import numpy as np
+    from oracle import angular as ang, spatial as sp, transport as otr
+    grid = sp.Grid(prob.dim, prob.n, prob.length)
+    patches = [p for p in ang.AngularMesh.uniform(prob.angular.base_level).leaves() if p.octant in (0, 1, 2)]
+    lv = otr.Level(grid, patches, prob.sigma_t, prob.sigma_s, [1.0])
+    g = np.random.default_rng(0).standard_normal(lv.A * grid.S)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    lv.sweep(g)
+    t1 = time.perf_counter()
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    dofs = lv.A * grid.S
+    return {"value": dofs / (t1 - t0), "unit": "DoF-updates/s", "cores": max(1, round(cpu / (t1 - t0))),
+            "kind": "oracle",
+            "sample": "oracle transport sweep (coupled 24x24 local solves) over the 48 patches of 3 of 8 "
+                      "octants on the 32^3 grid: %d DoF-updates in %.1f s" % (dofs, t1 - t0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32, help="cells per axis")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
+              "note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2010_04559_amd import inputs
+    from paper_2010_04559_amd.transport import Transport
+
+    prob = inputs.config2(args.n)
+    t_setup = time.perf_counter()
+    tr = Transport(prob)
+    b = tr.rhs()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print("setup %.1f s, patches %s, S=%d" % (t_setup, tr.patches, tr.S), file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        x, st = tr.solve(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        x, st = tr.solve(b)
+        print("step %d: iters %d rel_res %.2e" % (i, st["iters"], st["rel_res"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    value = st["sweep_dof_updates"] / (ms_step * 1e-3)
+
+    # explicit residual check of the last solve through the library's operator
+    r = b - tr.apply(x)
+    rel_res = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+
+    # FP32 V-cycle inside FP64 GMRES
+    mixed = None
+    if not args.no_mixed:
+        xm, stm = tr.solve(b, mode="mixed")
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(args.steps):
+            xm, stm = tr.solve(b, mode="mixed")
+        torch.cuda.synchronize()
+        ms_mixed = (time.perf_counter() - tm0) / args.steps * 1e3
+        dx = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
+        mixed = {"ms": ms_mixed, "iters": stm["iters"], "rel_res": stm["rel_res"], "rel_diff_vs_fp64": dx}
+        print("mixed: %.1f ms, iters %d" % (ms_mixed, stm["iters"]), file=sys.stderr, flush=True)
+
+    # component breakdown (HIP events around every launch group)
+    _, stt = tr.solve(b, timing=True)
+    breakdown = {k: round(stt[k], 3) for k in ("ms_total", "ms_sweep", "ms_scatter", "ms_transfer", "ms_coarse",
+                                               "ms_apply", "ms_orth", "ms_other")}
+
+    # roofline of the finest-level FP64 sweep kernel: algorithmic bytes per
+    # DoF-update = 16 (read the right-hand side, write the solution)
+    L = tr.nlev - 1
+    dofs = 3 * tr.patches[L] * tr.S
+    ms_sweep = tr.time_sweep_kernel(L, "f64", reps=20)
+    achieved = dofs * 16 / (ms_sweep * 1e-3) / 1e9
+    digest = kernel_sources_digest()
+    traffic = measured_traffic("k_sweep<double,3,false>", digest)
+    ms_sweep32 = tr.time_sweep_kernel(L, "f32", reps=20)
+    ms_gemm = tr.time_scatter_kernel(L, outer=False, prec="f64", reps=10)
+    A = 3 * tr.patches[L]
+    gemm_tfs = 2.0 * A * A * tr.S / (ms_gemm * 1e-3) / 1e12
+    ms_gemm32 = tr.time_scatter_kernel(L, outer=False, prec="f32", reps=10)
+    gemm32_tfs = 2.0 * A * A * tr.S / (ms_gemm32 * 1e-3) / 1e12
+
+    line = {
+        "metric": "sweep DoF-updates/s; time-to-1e-8 residual, FP32-MG vs FP64 plain, 1 GPU",
+        "value": value,
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D unit cube %d^3 trilinear DG, angular level 2 (128 patches x 3), HG g=0.95 "
+                               "L=16, lognormal sigma_t (median 5, log-sd 1, seed 0), c=0.98, central 4^3 unit "
+                               "source, vacuum; GMRES(10) + FP64 angular MG V(1,1), tol 1e-8" % args.n,
+                   "cells": tr.C, "spatial_dofs": tr.S, "angular_dofs": A, "dofs": dofs,
+                   "parallelism": "single GPU"},
+        "time_to_tol_ms": {"fp64_plain": ms_step, "fp32_mg": mixed["ms"] if mixed else None},
+        "iters": {"fp64_plain": st["iters"], "fp32_mg": mixed["iters"] if mixed else None},
+        "explicit_rel_res": rel_res,
+        "mixed": mixed,
+        "breakdown_ms": breakdown,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep<double,3,false> (finest-level FP64 transport sweep)",
+                     "ms_per_launch": ms_sweep, "bytes_per_launch": dofs * 16},
+        "sweep_kernel": {"fp64_dof_per_s": dofs / (ms_sweep * 1e-3), "fp32_dof_per_s": dofs / (ms_sweep32 * 1e-3),
+                         "fp32_ms": ms_sweep32},
+        "scatter_gemm": {"fp64_ms": ms_gemm, "fp64_tflops": gemm_tfs, "fp64_frac": gemm_tfs / FP64_PEAK_TFS,
+                         "fp32_ms": ms_gemm32, "fp32_tflops": gemm32_tfs, "fp32_frac": gemm32_tfs / FP32_PEAK_TFS},
+        "setup_s": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

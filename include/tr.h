@@ -111,6 +111,8 @@ typedef struct {
   int n_sweep, n_scatter, n_coarse; /* launches timed in each component           */
   double ms_sweep_finest;       /* time in finest-level transport sweeps          */
   int n_sweep_finest;
+  int n_precond;                /* preconditioner applications                    */
+  double sweep_dof_updates;     /* sum over transport sweeps of (ordinates x spatial dofs) */
 } tr_solve_stats;
 
 /* Build the angular mesh, quadrature, level operators, prolongations and

@@ -54,7 +54,8 @@ class TrSolveStats(ctypes.Structure):
                 ("ms_coarse", ctypes.c_double), ("ms_apply", ctypes.c_double), ("ms_orth", ctypes.c_double),
                 ("ms_other", ctypes.c_double), ("n_sweep", ctypes.c_int), ("n_scatter", ctypes.c_int),
                 ("n_coarse", ctypes.c_int), ("ms_sweep_finest", ctypes.c_double),
-                ("n_sweep_finest", ctypes.c_int)]
+                ("n_sweep_finest", ctypes.c_int), ("n_precond", ctypes.c_int),
+                ("sweep_dof_updates", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

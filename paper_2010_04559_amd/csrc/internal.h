@@ -48,9 +48,15 @@ struct SweepArgs {
 template <typename T>
 void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st);
 
-void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t,
-                      const double *sig_s, const OrdInfo *ord, const Planes &pl, const int *plane_off_host,
-                      const Grid &g, int nu, const int *octant_order, bool adjoint, hipStream_t st);
+// nu Gauss-Seidel sweeps on T_0 from zero, as one cooperative launch over a
+// precomputed step schedule (items = (octant << 28) | cell-list index).
+// The grid barrier uses bar_arrive[max_blocks], bar_release[1] and bar_err[1]
+// (zeroed once); generations continue from gen0, which the caller advances
+// by nsteps per launch.  bar_err != 0 after the launch means a barrier timed out.
+void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
+                      const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
+                      int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
+                      int *bar_err, int max_blocks, unsigned gen0, hipStream_t st);
 
 // out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * in[3p+m][s]
 template <typename Tin, typename Tout>

@@ -10,6 +10,9 @@
 // system of one discrete direction (local_solve.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <stdexcept>
+
 #include "internal.h"
 #include "local_solve.h"
 
@@ -48,122 +51,260 @@ __device__ __forceinline__ long long cell_index(const int ix[3], const Grid &g) 
 }
 
 // Right-hand side of one ordinate's cell system, in the form solved by
-// spectral_solve: forward  v = N^{-1} f + sigma_s s + upwind inflow (scaled),
-//                 adjoint  v = f + sigma_s N s + downwind coupling.
-template <typename T, int DIM, bool ADJ>
-__device__ __forceinline__ void cell_rhs(T *v, const T *fk, const T *sk, const T *uk, long long j, const int ci[3],
-                                         const int ix[3], int flip, const T *c, const T *a, double sigs,
-                                         const Grid &g) {
+// spectral_solve, from the cell's preloaded f and (optional) s values:
+//   forward  v = N^{-1} f + sigma_s s + upwind inflow (scaled by N^{-1}),
+//   adjoint  v = f + sigma_s N s + downwind coupling.
+template <typename T, int DIM, bool ADJ, int FLIP>
+__device__ __forceinline__ void cell_rhs(T *v, const T *fv, const T *sv, bool has_s, const T *uk, const int ci[3],
+                                         const int ix[3], const T *c, const T *a, double sigs, const Grid &g) {
+  constexpr int flip = FLIP;
   constexpr int NS = 1 << DIM;
-  load_node_vec<T, NS>(fk + j * NS, v);
+  // issue the neighbour-trace loads first (they are the only loads on the
+  // sweep's dependence chain); a missing neighbour reads the cell itself
+  // and is masked out below
+  T tr[DIM][NS / 2];
+  bool has[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int fl = (flip >> d) & 1;
+    const int dir = fl ? -1 : 1;
+    has[d] = ADJ ? (ci[d] < g.n[d] - 1) : (ci[d] > 0);
+    int nx[3] = {ix[0], ix[1], ix[2]};
+    if (has[d]) nx[d] += ADJ ? dir : -dir;
+    const T *un = uk + cell_index(nx, g) * NS;
+    // forward: the neighbour's outflow face; adjoint: its inflow face
+    const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+#pragma unroll
+    for (int t = 0; t < NS / 2; ++t) tr[d][t] = un[insert_bit(t, d, nbit)];
+  }
+#pragma unroll
+  for (int b = 0; b < NS; ++b) v[b] = fv[b];
   if (!ADJ) {
     mass_shape<T, DIM, true>(v);
     const T iv = T(1.0 / g.vol);
 #pragma unroll
     for (int b = 0; b < NS; ++b) v[b] *= iv;
-    if (sk) {
-      T sv[NS];
-      load_node_vec<T, NS>(sk + j * NS, sv);
+    if (has_s) {
 #pragma unroll
       for (int b = 0; b < NS; ++b) v[b] += T(sigs) * sv[b];
     }
-  } else if (sk) {
-    T sv[NS];
-    load_node_vec<T, NS>(sk + j * NS, sv);
-    mass_shape<T, DIM, false>(sv);
+  } else if (has_s) {
+    T t[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) t[b] = sv[b];
+    mass_shape<T, DIM, false>(t);
     const T f = T(sigs * g.vol);
 #pragma unroll
-    for (int b = 0; b < NS; ++b) v[b] += f * sv[b];
+    for (int b = 0; b < NS; ++b) v[b] += f * t[b];
   }
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
+    if (!has[d]) continue;
     const int fl = (flip >> d) & 1;
-    const int dir = fl ? -1 : 1;
-    const bool has = ADJ ? (ci[d] < g.n[d] - 1) : (ci[d] > 0);
-    if (!has) continue;
-    int nx[3] = {ix[0], ix[1], ix[2]};
-    nx[d] += ADJ ? dir : -dir;
-    const long long jn = cell_index(nx, g);
-    const T *un = uk + jn * NS;
-    T tr[NS / 2];
     if (!ADJ) {
-      const int nbit = fl ? 0 : 1;   // neighbour's outflow face
       const int own0 = fl ? 1 : 0;   // own inflow face
 #pragma unroll
-      for (int t = 0; t < NS / 2; ++t) tr[t] = un[insert_bit(t, d, nbit)];
-#pragma unroll
       for (int t = 0; t < NS / 2; ++t) {
-        v[insert_bit(t, d, own0)] += T(4) * c[d] * tr[t];
-        v[insert_bit(t, d, 1 - own0)] -= T(2) * c[d] * tr[t];
+        v[insert_bit(t, d, own0)] += T(4) * c[d] * tr[d][t];
+        v[insert_bit(t, d, 1 - own0)] -= T(2) * c[d] * tr[d][t];
       }
     } else {
-      const int nbit = fl ? 1 : 0;   // neighbour's inflow face
       const int own1 = fl ? 0 : 1;   // own outflow face
-#pragma unroll
-      for (int t = 0; t < NS / 2; ++t) tr[t] = un[insert_bit(t, d, nbit)];
-      mass_shape<T, DIM - 1, false>(tr);
+      mass_shape<T, DIM - 1, false>(tr[d]);
       T hs = T(1);
 #pragma unroll
       for (int e = 0; e < DIM; ++e)
         if (e != d) hs *= T(g.h[e]);
 #pragma unroll
-      for (int t = 0; t < NS / 2; ++t) v[insert_bit(t, d, own1)] += a[d] * hs * tr[t];
+      for (int t = 0; t < NS / 2; ++t) v[insert_bit(t, d, own1)] += a[d] * hs * tr[d][t];
     }
   }
 }
 
 // ------------------------------------------------------------------ sweep
 // One workgroup per ordinate walks the diagonal planes of its direction
-// (downwind first for the adjoint); the cells of a plane are independent.
-template <typename T, int DIM, bool ADJ>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> a) {
+// (downwind first for the adjoint); the cells of a plane are independent
+// and each thread owns up to R of them.  The right-hand side and scatter
+// source of the next plane do not depend on the sweep, so they are loaded
+// into registers while the current plane is solved; only the upwind traces
+// (written one plane earlier by this workgroup, L2-resident) sit on the
+// dependence chain.
+constexpr int kSweepThreads = 512;
+
+// Body of the sweep for one ordinate whose octant sign bits FLIP are known
+// at compile time, so every face-node index is a constant.
+template <typename T, int DIM, bool ADJ, int R, bool PF, int FLIP>
+__device__ __forceinline__ void sweep_body(const SweepArgs<T> &a, int k) {
   constexpr int NS = 1 << DIM;
-  const int k = blockIdx.x;
+  constexpr int RB = PF ? R : 1;  // register-buffered cells per thread
+  constexpr int flip = FLIP;
   const OrdInfo o = a.ord[k];
-  const int flip = o.flip;
   const T c[3] = {T(o.c[0]), T(o.c[1]), T(o.c[2])};
   const T av[3] = {T(o.a[0]), T(o.a[1]), T(o.a[2])};
   const long long S = a.g.S;
   const T *fk = a.f + (long long)k * S;
-  const T *sk = a.s ? a.s + (long long)k * S : nullptr;
+  const bool has_s = a.s != nullptr;
+  const T *sk = has_s ? a.s + (long long)k * S : fk;
   T *uk = a.u + (long long)k * S;
-  for (int pp = 0; pp < a.pl.nplanes; ++pp) {
-    const int p = ADJ ? a.pl.nplanes - 1 - pp : pp;
+  const int np = a.pl.nplanes;
+
+  T fc[RB][NS], sc[RB][NS];
+  auto load = [&](int pp, T (&fb)[RB][NS], T (&sb)[RB][NS]) {
+    const int p = ADJ ? np - 1 - pp : pp;
     const int beg = a.pl.off[p], end = a.pl.off[p + 1];
-    for (int idx = beg + threadIdx.x; idx < end; idx += kBlock) {
-      int ci[3], ix[3];
-      unpack_cell(a.pl.cells[idx], flip, a.g, ci, ix);
-      const long long j = cell_index(ix, a.g);
-      T v[NS];
-      cell_rhs<T, DIM, ADJ>(v, fk, sk, uk, j, ci, ix, flip, c, av, a.sig_s[j], a.g);
-      spectral_solve<T, DIM, ADJ>(v, c, T(a.sig_t[j]), flip);
-      if (ADJ) {
-        mass_shape<T, DIM, true>(v);
-        const T iv = T(1.0 / a.g.vol);
 #pragma unroll
-        for (int b = 0; b < NS; ++b) v[b] *= iv;
+    for (int r = 0; r < RB; ++r) {
+      const int idx = beg + threadIdx.x + r * kSweepThreads;
+      if (idx < end) {
+        int ci[3], ix[3];
+        unpack_cell(a.pl.cells[idx], flip, a.g, ci, ix);
+        const long long j = cell_index(ix, a.g);
+        load_node_vec<T, NS>(fk + j * NS, fb[r]);
+        if (has_s) load_node_vec<T, NS>(sk + j * NS, sb[r]);
       }
-      store_node_vec<T, NS>(uk + j * NS, v);
+    }
+  };
+  if (PF) load(0, fc, sc);
+  for (int pp = 0; pp < np; ++pp) {
+    T fn[RB][NS], sn[RB][NS];
+    if (PF && pp + 1 < np) load(pp + 1, fn, sn);
+    const int p = ADJ ? np - 1 - pp : pp;
+    const int beg = a.pl.off[p], end = a.pl.off[p + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int idx = beg + threadIdx.x + r * kSweepThreads;
+      if (idx < end) {
+        int ci[3], ix[3];
+        unpack_cell(a.pl.cells[idx], flip, a.g, ci, ix);
+        const long long j = cell_index(ix, a.g);
+        T v[NS];
+        if (PF) {
+          cell_rhs<T, DIM, ADJ, FLIP>(v, fc[PF ? r : 0], sc[PF ? r : 0], has_s, uk, ci, ix, c, av, a.sig_s[j], a.g);
+        } else {
+          T fv[NS], sv[NS];
+          load_node_vec<T, NS>(fk + j * NS, fv);
+          if (has_s) load_node_vec<T, NS>(sk + j * NS, sv);
+          cell_rhs<T, DIM, ADJ, FLIP>(v, fv, sv, has_s, uk, ci, ix, c, av, a.sig_s[j], a.g);
+        }
+        spectral_solve<T, DIM, ADJ>(v, c, T(a.sig_t[j]), flip);
+        if (ADJ) {
+          mass_shape<T, DIM, true>(v);
+          const T iv = T(1.0 / a.g.vol);
+#pragma unroll
+          for (int b = 0; b < NS; ++b) v[b] *= iv;
+        }
+        store_node_vec<T, NS>(uk + j * NS, v);
+      }
     }
     __syncthreads();
+    if (PF) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          fc[r][b] = fn[r][b];
+          sc[r][b] = sn[r][b];
+        }
+    }
+  }
+}
+
+template <typename T, int DIM, bool ADJ, int R, bool PF>
+__global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs<T> a) {
+  const int k = blockIdx.x;
+  switch (a.ord[k].flip) {
+    case 0: sweep_body<T, DIM, ADJ, R, PF, 0>(a, k); break;
+    case 1: sweep_body<T, DIM, ADJ, R, PF, 1>(a, k); break;
+    case 2: sweep_body<T, DIM, ADJ, R, PF, 2>(a, k); break;
+    case 3: sweep_body<T, DIM, ADJ, R, PF, 3>(a, k); break;
+    case 4: if (DIM == 3) sweep_body<T, DIM, ADJ, R, PF, 4>(a, k); break;
+    case 5: if (DIM == 3) sweep_body<T, DIM, ADJ, R, PF, 5>(a, k); break;
+    case 6: if (DIM == 3) sweep_body<T, DIM, ADJ, R, PF, 6>(a, k); break;
+    default: if (DIM == 3) sweep_body<T, DIM, ADJ, R, PF, 7>(a, k); break;
   }
 }
 
 // ------------------------------------------------------- coarse Gauss-Seidel
 // T_0 has one patch (three ordinates) per octant.  One launch handles one
-// diagonal plane of one octant: each thread solves the coupled system of a
-// cell's three ordinates with the patch's own scatter implicit and every
-// other unknown at its latest value (Section 5.2).  In the spectral basis
-// the 24x24 (3-D) block splits into four complex 3x3 systems.
+// diagonal plane of one octant: each (cell, octant) block is solved with
+// the patch's own scatter implicit and every other unknown at its latest
+// value (Section 5.2).  A cell occupies 2^dim consecutive lanes, one per
+// Q1 node; the tensor-product transforms of local_solve.h become lane
+// butterflies (__shfl_xor over the node bits), after which lane b holds
+// spectral mode b and solves that mode's complex 3x3 system (the three
+// ordinates coupled by the self-scatter block) on its own.
+__device__ __forceinline__ double shx(double v, int mask) { return __shfl_xor(v, mask, 64); }
+
+__device__ __forceinline__ cx<double> shx(cx<double> v, int mask) {
+  return {__shfl_xor(v.re, mask, 64), __shfl_xor(v.im, mask, 64)};
+}
+
+// Node-space 2x2 operator along axis d: out = m_same * own + m_other * partner
+// (used for the symmetric mass shapes).
+template <int DIM>
+__device__ __forceinline__ double lane_mass(double v, int bits_mask, bool inverse) {
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    if (!((bits_mask >> d) & 1)) continue;
+    const double p = shx(v, 1 << d);
+    v = inverse ? 4.0 * v - 2.0 * p : (2.0 * v + p) * (1.0 / 6.0);
+  }
+  return v;
+}
+
+template <int DIM>
+__device__ __forceinline__ cx<double> lane_forward(double v, int b, const AxisXf<double> *ax) {
+  // stage x: real input
+  cx<double> y;
+  {
+    const double p = shx(v, 1);
+    const double v0 = (b & 1) ? p : v, v1 = (b & 1) ? v : p;
+    cx<double> f0 = ax[0].fwd[0], f1 = ax[0].fwd[1];
+    if (b & 1) {
+      f0.im = -f0.im;
+      f1.im = -f1.im;
+    }
+    y = cadd(rmul(f0, v0), rmul(f1, v1));
+  }
+#pragma unroll
+  for (int d = 1; d < DIM; ++d) {
+    const int bit = 1 << d;
+    const cx<double> p = shx(y, bit);
+    const cx<double> v0 = (b & bit) ? p : y, v1 = (b & bit) ? y : p;
+    cx<double> f0 = ax[d].fwd[0], f1 = ax[d].fwd[1];
+    if (b & bit) {
+      f0.im = -f0.im;
+      f1.im = -f1.im;
+    }
+    y = cadd(cmul(f0, v0), cmul(f1, v1));
+  }
+  return y;
+}
+
+template <int DIM>
+__device__ __forceinline__ double lane_backward(cx<double> U, int b, const AxisXf<double> *ax) {
+#pragma unroll
+  for (int d = DIM - 1; d >= 0; --d) {
+    const int bit = 1 << d;
+    const cx<double> p = shx(U, bit);
+    const cx<double> u0 = (b & bit) ? p : U, u1 = (b & bit) ? U : p;
+    const cx<double> c = (b & bit) ? ax[d].bwd[1] : ax[d].bwd[0];
+    const cx<double> cc{c.re, -c.im};
+    U = cadd(cmul(c, u0), cmul(cc, u1));
+  }
+  return U.re;
+}
+
+// Gauss-Seidel update of one (cell, octant) block by the 2^dim lanes of a
+// cell group; every lane of the wave must call it (idle groups pass
+// active = false with a valid cell and store nothing).
 template <int DIM, bool ADJ>
-__global__ __launch_bounds__(64) void k_gs_plane(const double *__restrict__ f, double *__restrict__ u,
-                                                 const double *__restrict__ G, const double *__restrict__ sig_t,
-                                                 const double *__restrict__ sig_s, const OrdInfo *__restrict__ ord,
-                                                 Planes pl, Grid g, int octant, int plane) {
+__device__ __forceinline__ void gs_update(const double *__restrict__ f, double *__restrict__ u,
+                                          const double *__restrict__ G, const double *__restrict__ sig_t,
+                                          const double *__restrict__ sig_s, const OrdInfo *__restrict__ ord,
+                                          const Planes &pl, const Grid &g, int octant, int idx, bool active,
+                                          int b) {
   constexpr int NS = 1 << DIM;
-  constexpr int NM = DIM == 3 ? 4 : 2;
-  const int idx = pl.off[plane] + blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= pl.off[plane + 1]) return;
   const int k0 = 3 * octant;
   const int flip = ord[k0].flip;
   int ci[3], ix[3];
@@ -171,100 +312,208 @@ __global__ __launch_bounds__(64) void k_gs_plane(const double *__restrict__ f, d
   const long long j = cell_index(ix, g);
   const long long S = g.S;
   const double st = sig_t[j], ss = sig_s[j];
+  const double *up = u + j * NS + b;
 
-  // scatter from the other octants' ordinates at this cell (latest values)
-  double acc[3][NS];
+  // gather everything the update reads before using any of it: all 24
+  // ordinate values at this node, the right-hand side and the upwind
+  // (adjoint: downwind) traces of the octant's three ordinates
+  double uv[24];
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
+  for (int kp = 0; kp < 24; ++kp) uv[kp] = up[kp * S];
+  double fv[3], tr[3][DIM];
+  bool has[DIM];
+  long long jn[DIM];
 #pragma unroll
-    for (int b = 0; b < NS; ++b) acc[m][b] = 0.0;
-  for (int kp = 0; kp < 24; ++kp) {
-    if (kp / 3 == octant) continue;
-    double uv[NS];
-    load_node_vec<double, NS>(u + kp * S + j * NS, uv);
+  for (int d = 0; d < DIM; ++d) {
+    const int fl = (flip >> d) & 1;
+    const int dir = fl ? -1 : 1;
+    has[d] = ADJ ? (ci[d] < g.n[d] - 1) : (ci[d] > 0);
+    int nx[3] = {ix[0], ix[1], ix[2]};
+    nx[d] += has[d] ? (ADJ ? dir : -dir) : 0;
+    jn[d] = cell_index(nx, g);
+  }
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const double gm = G[(k0 + m) * 24 + kp];
+  for (int m = 0; m < 3; ++m) {
+    fv[m] = f[(k0 + m) * S + j * NS + b];
 #pragma unroll
-      for (int b = 0; b < NS; ++b) acc[m][b] += gm * uv[b];
+    for (int d = 0; d < DIM; ++d) {
+      const int fl = (flip >> d) & 1;
+      const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+      const int bn = (b & ~(1 << d)) | (nbit << d);
+      tr[m][d] = u[(k0 + m) * S + jn[d] * NS + bn];
     }
   }
-  double v[3][NS];
+  // scatter from the other octants' ordinates (latest values)
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kp = 0; kp < 24; ++kp) {
+    const double w = (kp / 3 == octant) ? 0.0 : uv[kp];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc[m] += G[(k0 + m) * 24 + kp] * w;
+  }
+  double v[3];
   double cc[3][3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     const OrdInfo o = ord[k0 + m];
-    const double c[3] = {o.c[0], o.c[1], o.c[2]};
-    const double av[3] = {o.a[0], o.a[1], o.a[2]};
-    cc[m][0] = c[0];
-    cc[m][1] = c[1];
-    cc[m][2] = c[2];
-    cell_rhs<double, DIM, ADJ>(v[m], f + (k0 + m) * S, nullptr, u + (k0 + m) * S, j, ci, ix, flip, c, av, 0.0, g);
+    cc[m][0] = o.c[0];
+    cc[m][1] = o.c[1];
+    cc[m][2] = o.c[2];
     if (!ADJ) {
-#pragma unroll
-      for (int b = 0; b < NS; ++b) v[m][b] += ss * acc[m][b];
+      v[m] = lane_mass<DIM>(fv[m], NS - 1, true) * (1.0 / g.vol) + ss * acc[m];
     } else {
-      mass_shape<double, DIM, false>(acc[m]);
+      v[m] = fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false);
+    }
 #pragma unroll
-      for (int b = 0; b < NS; ++b) v[m][b] += ss * g.vol * acc[m][b];
+    for (int d = 0; d < DIM; ++d) {
+      const int fl = (flip >> d) & 1;
+      double t = has[d] ? tr[m][d] : 0.0;
+      if (!ADJ) {
+        const int own0 = fl ? 1 : 0;
+        v[m] += (((b >> d) & 1) == own0 ? 4.0 : -2.0) * o.c[d] * t;
+      } else {
+        double hs = 1.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+          if (e != d) hs *= g.h[e];
+        t = lane_mass<DIM>(t, (NS - 1) & ~(1 << d), false);
+        const int own1 = fl ? 0 : 1;
+        if (((b >> d) & 1) == own1) v[m] += o.a[d] * hs * t;
+      }
     }
   }
-  // spectral transforms (all three ordinates share the octant's orientation)
   AxisXf<double> ax[3];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) ax[d] = axis_xf<double>((flip >> d) & 1, ADJ);
-  cx<double> md[3][NM];
+  cx<double> r[3];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) modes_forward<double, DIM>(v[m], ax, md[m]);
-  double gq[3][3];
+  for (int m = 0; m < 3; ++m) r[m] = lane_forward<DIM>(v[m], b, ax);
+  // this lane's mode: bit d of b selects lambda_- on axis d
+  cx<double> M[3][3];
+  const double r2 = 1.41421356237309504880;
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
+  for (int m = 0; m < 3; ++m) {
 #pragma unroll
-    for (int mp = 0; mp < 3; ++mp) gq[m][mp] = ss * G[(k0 + m) * 24 + k0 + mp];
+    for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-ss * G[(k0 + m) * 24 + k0 + mp], 0.0};
+    double re = st, im = 0.0;
 #pragma unroll
-  for (int mode = 0; mode < NM; ++mode) {
-    cx<double> M[3][3], r[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      r[m] = md[m][mode];
-#pragma unroll
-      for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-gq[m][mp], 0.0};
-      const cx<double> dm = mode_eig<double, DIM>(mode, cc[m], st);
-      M[m][m] = cadd(M[m][m], dm);
+    for (int d = 0; d < DIM; ++d) {
+      re += 2.0 * cc[m][d];
+      im += (((b >> d) & 1) ? -r2 : r2) * cc[m][d];
     }
-    // Gaussian elimination (the blocks are diagonally dominant: the real
-    // part of D exceeds sigma_t + 2 sum c, the scatter block is below sigma_s)
+    M[m][m].re += re;
+    M[m][m].im += im;
+  }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const cx<double> ip = cinv(M[p][p]);
+  for (int p = 0; p < 3; ++p) {
+    const cx<double> ip = cinv(M[p][p]);
 #pragma unroll
-      for (int i = p + 1; i < 3; ++i) {
-        const cx<double> l = cmul(M[i][p], ip);
+    for (int i = p + 1; i < 3; ++i) {
+      const cx<double> l = cmul(M[i][p], ip);
 #pragma unroll
-        for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(l, M[p][jj]));
-        r[i] = csub(r[i], cmul(l, r[p]));
-      }
+      for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(l, M[p][jj]));
+      r[i] = csub(r[i], cmul(l, r[p]));
     }
+  }
 #pragma unroll
-    for (int p = 2; p >= 0; --p) {
-      cx<double> t = r[p];
+  for (int p = 2; p >= 0; --p) {
+    cx<double> t = r[p];
 #pragma unroll
-      for (int jj = p + 1; jj < 3; ++jj) t = csub(t, cmul(M[p][jj], r[jj]));
-      r[p] = cmul(t, cinv(M[p][p]));
-    }
-#pragma unroll
-    for (int m = 0; m < 3; ++m) md[m][mode] = r[m];
+    for (int jj = p + 1; jj < 3; ++jj) t = csub(t, cmul(M[p][jj], r[jj]));
+    r[p] = cmul(t, cinv(M[p][p]));
   }
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    double out[NS];
-    modes_backward<double, DIM>(md[m], ax, out);
-    if (ADJ) {
-      mass_shape<double, DIM, true>(out);
-#pragma unroll
-      for (int b = 0; b < NS; ++b) out[b] *= 1.0 / g.vol;
+    double out = lane_backward<DIM>(r[m], b, ax);
+    if (ADJ) out = lane_mass<DIM>(out, NS - 1, true) * (1.0 / g.vol);
+    if (active) u[(k0 + m) * S + j * NS + b] = out;
+  }
+}
+
+
+// The whole coarse solve (nu sweeps over the octants) as one cooperative
+// launch.  The host orders the (sweep, octant, cell) updates into steps:
+// an update is placed one step after the latest of its upwind neighbours'
+// updates (same sweep and octant) and the same cell's previous update, so
+// every value it reads is final and the result equals the sequential
+// Gauss-Seidel sweep; items of one step touch distinct cells.  An item is
+// (octant << 28) | index into the plane-ordered cell list.  A grid-wide
+// barrier separates the steps.
+// Grid-wide barrier for a cooperative launch without contended atomics:
+// every block but 0 publishes its arrival generation in its own slot, block
+// 0 waits for all slots with one thread per slot, then publishes the
+// release generation.  Spins are bounded; on timeout the error word is set
+// and every block leaves its loops, so the kernel always terminates.
+struct GridBarrier {
+  unsigned *arrive;   // [blocks]
+  unsigned *release;  // [1]
+  int *err;           // [1]
+};
+
+__device__ __forceinline__ bool barrier_spin_done(const unsigned *p, unsigned gen, int *err, long &spins) {
+  if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen) return true;
+  if (++spins > (1L << 25) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  return false;
+}
+
+__device__ bool grid_barrier(const GridBarrier &gb, unsigned gen) {
+  __shared__ int ok;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (unsigned i = threadIdx.x + 1; i < gridDim.x; i += blockDim.x) {
+      long spins = 0;
+      while (!barrier_spin_done(gb.arrive + i, gen, gb.err, spins)) {
+      }
     }
-    store_node_vec<double, NS>(u + (k0 + m) * S + j * NS, out);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_store(gb.release, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(gb.arrive + blockIdx.x, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (!barrier_spin_done(gb.release, gen, gb.err, spins)) {
+    }
+    __threadfence();
+  }
+  if (threadIdx.x == 0) ok = __hip_atomic_load(gb.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+  __syncthreads();
+  return ok;
+}
+
+// The whole coarse solve (nu sweeps over the octants) as one cooperative
+// launch.  The host orders the (sweep, octant, cell) updates into steps:
+// an update is placed one step after the latest of its upwind neighbours'
+// updates (same sweep and octant) and the same cell's previous update, so
+// every value it reads is final and the result equals the sequential
+// Gauss-Seidel sweep; items of one step touch distinct cells.  An item is
+// (octant << 28) | index into the plane-ordered cell list.  A grid-wide
+// barrier separates the steps.
+template <int DIM, bool ADJ>
+__global__ __launch_bounds__(256) void k_gs_solve(const double *__restrict__ f, double *__restrict__ u,
+                                                  const double *__restrict__ G, const double *__restrict__ sig_t,
+                                                  const double *__restrict__ sig_s,
+                                                  const OrdInfo *__restrict__ ord, Planes pl, Grid g,
+                                                  const int *__restrict__ step_off, const int *__restrict__ items,
+                                                  int nsteps, GridBarrier gb, unsigned gen0) {
+  constexpr int NS = 1 << DIM;
+  constexpr int CPB = 256 / NS;  // cells per block per round
+  const int b = threadIdx.x & (NS - 1);
+  const int slot = threadIdx.x / NS;
+  for (int t = 0; t < nsteps; ++t) {
+    const int beg = step_off[t], end = step_off[t + 1];
+    for (int base = beg + blockIdx.x * CPB; base < end; base += gridDim.x * CPB) {
+      const int it = base + slot;
+      const bool active = it < end;
+      const int item = items[active ? it : beg];
+      gs_update<DIM, ADJ>(f, u, G, sig_t, sig_s, ord, pl, g, item >> 28, item & ((1 << 28) - 1), active, b);
+    }
+    if (!grid_barrier(gb, gen0 + t + 1)) return;
   }
 }
 
@@ -670,51 +919,64 @@ int grid_for(long long n, int block = kBlock) {
 }  // namespace
 
 // ------------------------------------------------------------- launchers
+template <typename T, int DIM, bool ADJ>
+static void launch_sweep_r(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
+  const int R = (a.pl.max_plane + kSweepThreads - 1) / kSweepThreads;
+  // register prefetch of the next plane when a thread owns one cell per
+  // plane; with more cells per thread the prefetch buffers would halve the
+  // workgroups resident per CU, so those variants load at use
+  if (R <= 1)
+    hipLaunchKernelGGL((k_sweep<T, DIM, ADJ, 1, true>), dim3(n_ord), dim3(kSweepThreads), 0, st, a);
+  else if (R <= 2)
+    hipLaunchKernelGGL((k_sweep<T, DIM, ADJ, 2, false>), dim3(n_ord), dim3(kSweepThreads), 0, st, a);
+  else if (R <= 4)
+    hipLaunchKernelGGL((k_sweep<T, DIM, ADJ, 4, false>), dim3(n_ord), dim3(kSweepThreads), 0, st, a);
+  else if (R <= 8)
+    hipLaunchKernelGGL((k_sweep<T, DIM, ADJ, 8, false>), dim3(n_ord), dim3(kSweepThreads), 0, st, a);
+  else
+    throw std::runtime_error("sweep plane larger than 4096 cells");
+}
+
 template <typename T>
 void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st) {
   if (a.g.dim == 3) {
     if (adjoint)
-      hipLaunchKernelGGL((k_sweep<T, 3, true>), dim3(n_ord), dim3(kBlock), 0, st, a);
+      launch_sweep_r<T, 3, true>(a, n_ord, st);
     else
-      hipLaunchKernelGGL((k_sweep<T, 3, false>), dim3(n_ord), dim3(kBlock), 0, st, a);
+      launch_sweep_r<T, 3, false>(a, n_ord, st);
   } else {
     if (adjoint)
-      hipLaunchKernelGGL((k_sweep<T, 2, true>), dim3(n_ord), dim3(kBlock), 0, st, a);
+      launch_sweep_r<T, 2, true>(a, n_ord, st);
     else
-      hipLaunchKernelGGL((k_sweep<T, 2, false>), dim3(n_ord), dim3(kBlock), 0, st, a);
+      launch_sweep_r<T, 2, false>(a, n_ord, st);
   }
 }
 template void launch_sweep<double>(const SweepArgs<double> &, int, bool, hipStream_t);
 template void launch_sweep<float>(const SweepArgs<float> &, int, bool, hipStream_t);
 
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
-                      const OrdInfo *ord, const Planes &pl, const int *off_host, const Grid &g, int nu,
-                      const int *octant_order, bool adjoint, hipStream_t st) {
+                      const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
+                      int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
+                      int *bar_err, int max_blocks, unsigned gen0, hipStream_t st) {
   launch_fill<double>(u, 24LL * g.S, 0.0, st);
-  for (int sweep = 0; sweep < nu; ++sweep)
-    for (int oi = 0; oi < 8; ++oi) {
-      const int o = octant_order[oi];
-      for (int pp = 0; pp < pl.nplanes; ++pp) {
-        const int p = adjoint ? pl.nplanes - 1 - pp : pp;
-        const int cnt = off_host[p + 1] - off_host[p];
-        const int blocks = (cnt + 63) / 64;
-        if (g.dim == 3) {
-          if (adjoint)
-            hipLaunchKernelGGL((k_gs_plane<3, true>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord, pl,
-                               g, o, p);
-          else
-            hipLaunchKernelGGL((k_gs_plane<3, false>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord,
-                               pl, g, o, p);
-        } else {
-          if (adjoint)
-            hipLaunchKernelGGL((k_gs_plane<2, true>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord, pl,
-                               g, o, p);
-          else
-            hipLaunchKernelGGL((k_gs_plane<2, false>), dim3(blocks), dim3(64), 0, st, f, u, G, sig_t, sig_s, ord,
-                               pl, g, o, p);
-        }
-      }
-    }
+  void *fn = nullptr;
+  if (g.dim == 3)
+    fn = adjoint ? (void *)k_gs_solve<3, true> : (void *)k_gs_solve<3, false>;
+  else
+    fn = adjoint ? (void *)k_gs_solve<2, true> : (void *)k_gs_solve<2, false>;
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1)
+    throw std::runtime_error("cannot size the cooperative Gauss-Seidel launch");
+  const int cpb = 256 / g.ns;
+  int blocks = (max_items + cpb - 1) / cpb;
+  blocks = std::max(1, std::min(std::min(blocks, ncu * per_cu), max_blocks));
+  GridBarrier gb{bar_arrive, bar_release, bar_err};
+  void *args[] = {(void *)&f,    (void *)&u,     (void *)&G,        (void *)&sig_t, (void *)&sig_s,
+                  (void *)&ord,  (void *)&pl,    (void *)&g,        (void *)&step_off, (void *)&items,
+                  (void *)&nsteps, (void *)&gb, (void *)&gen0};
+  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st) != hipSuccess)
+    throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
 }
 
 template <typename Tin, typename Tout>

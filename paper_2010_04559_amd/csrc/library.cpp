@@ -157,6 +157,19 @@ struct tr_handle {
   std::vector<double *> V, Z;
   double *kw = nullptr, *kx = nullptr;
   bool mixed_ready = false;
+  struct GsSchedule {
+    int nu = 0;
+    bool adj = false;
+    int nsteps = 0, max_items = 0;
+    int *step_off = nullptr, *items = nullptr;
+  };
+  std::vector<GsSchedule> gs_sched;
+  unsigned *bar_arrive = nullptr, *bar_release = nullptr;
+  int *bar_err = nullptr;
+  unsigned bar_gen = 0;
+  static constexpr int kMaxGsBlocks = 1024;
+  long long n_precond = 0;
+  double sweep_dofs = 0;
   std::vector<void *> allocs;
   size_t bytes = 0;
   EventTimer *timer = nullptr;
@@ -460,6 +473,7 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   a.pl = h->pl;
   a.g = h->g;
   const bool fine = l == h->top();
+  h->sweep_dofs += (double)h->lv[l].A * (double)h->g.S;
   tbegin(h, fine ? C_SWEEP_FINE : C_SWEEP);
   tr::launch_sweep<T>(a, h->lv[l].A, adj, st);
   tend(h);
@@ -472,12 +486,105 @@ void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st) 
   tend(h);
 }
 
+// Step schedule of nu Gauss-Seidel sweeps on T_0 (octants in the given
+// order, cells in upwind order, downwind first for the adjoint): each
+// (sweep, octant, cell) update goes one step after the latest of its
+// upwind neighbours' updates in the same octant sweep and of the cell's
+// previous update, the earliest step at which everything it reads is final.
+const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
+  for (auto &sc : h->gs_sched)
+    if (sc.nu == nu && sc.adj == adj) return sc;
+  const Grid &g = h->g;
+  const long long C = g.C;
+  std::vector<int> last(C, -1), to(C, -1);
+  std::vector<std::vector<int>> steps;
+  const int np = h->pl.nplanes;
+  std::vector<int> cells_host;
+  {
+    cells_host.resize(h->plane_off_host.back());
+    HIPCHK(hipMemcpy(cells_host.data(), h->d_cells, cells_host.size() * sizeof(int), hipMemcpyDeviceToHost));
+  }
+  for (int sweep = 0; sweep < nu; ++sweep)
+    for (int oi = 0; oi < 8; ++oi) {
+      const int o = h->octant_order[oi];
+      for (int pp = 0; pp < np; ++pp) {
+        const int p = adj ? np - 1 - pp : pp;
+        for (int idx = h->plane_off_host[p]; idx < h->plane_off_host[p + 1]; ++idx) {
+          const int packed = cells_host[idx];
+          int ci[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023}, ix[3];
+          for (int d = 0; d < 3; ++d) ix[d] = ((o >> d) & 1) ? g.n[d] - 1 - ci[d] : ci[d];
+          const long long j = ix[0] + (long long)g.n[0] * (ix[1] + (long long)g.n[1] * ix[2]);
+          int t = last[j] + 1;
+          for (int d = 0; d < g.dim; ++d) {
+            const bool has = adj ? ci[d] < g.n[d] - 1 : ci[d] > 0;
+            if (!has) continue;
+            int nx[3] = {ix[0], ix[1], ix[2]};
+            const int dir = ((o >> d) & 1) ? -1 : 1;
+            nx[d] += adj ? dir : -dir;
+            const long long jn = nx[0] + (long long)g.n[0] * (nx[1] + (long long)g.n[1] * nx[2]);
+            t = std::max(t, to[jn] + 1);
+          }
+          to[j] = t;
+          last[j] = t;
+          if ((int)steps.size() <= t) steps.resize(t + 1);
+          steps[t].push_back((o << 28) | idx);
+        }
+      }
+    }
+  std::vector<int> off{0}, items;
+  int mx = 0;
+  for (auto &st : steps) {
+    items.insert(items.end(), st.begin(), st.end());
+    off.push_back((int)items.size());
+    mx = std::max(mx, (int)st.size());
+  }
+  tr_handle::GsSchedule sc;
+  sc.nu = nu;
+  sc.adj = adj;
+  sc.nsteps = (int)steps.size();
+  sc.max_items = mx;
+  sc.step_off = h->upload(off);
+  sc.items = h->upload(items);
+  h->gs_sched.push_back(sc);
+  return h->gs_sched.back();
+}
+
+void check_barrier(tr_handle *h, hipStream_t st) {
+  if (!h->bar_err) return;
+  int e = 0;
+  HIPCHK(hipMemcpyAsync(&e, h->bar_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (e) throw std::runtime_error("coarse Gauss-Seidel grid barrier timed out");
+}
+
 void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipStream_t st) {
   DevLevel &D = h->lv[0];
+  const tr_handle::GsSchedule &sc = gs_schedule(h, nu, adj);
+  if (!h->bar_arrive) {
+    h->bar_arrive = h->alloc<unsigned>(tr_handle::kMaxGsBlocks);
+    h->bar_release = h->alloc<unsigned>(1);
+    h->bar_err = h->alloc<int>(1);
+    HIPCHK(hipMemset(h->bar_arrive, 0, tr_handle::kMaxGsBlocks * sizeof(unsigned)));
+    HIPCHK(hipMemset(h->bar_release, 0, sizeof(unsigned)));
+    HIPCHK(hipMemset(h->bar_err, 0, sizeof(int)));
+    HIPCHK(hipDeviceSynchronize());
+    h->bar_gen = 0;
+  }
+  if (h->bar_gen > 0xF0000000u - (unsigned)sc.nsteps) {
+    // restart the generation count (all earlier launches on this handle's
+    // stream have finished once the stream is synchronised)
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemset(h->bar_arrive, 0, tr_handle::kMaxGsBlocks * sizeof(unsigned)));
+    HIPCHK(hipMemset(h->bar_release, 0, sizeof(unsigned)));
+    HIPCHK(hipDeviceSynchronize());
+    h->bar_gen = 0;
+  }
   tbegin(h, C_COARSE);
-  tr::launch_coarse_gs(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->plane_off_host.data(), h->g,
-                       nu, h->octant_order, adj, st);
+  tr::launch_coarse_gs(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->g, sc.step_off, sc.items,
+                       sc.nsteps, sc.max_items, adj, h->bar_arrive, h->bar_release, h->bar_err,
+                       tr_handle::kMaxGsBlocks, h->bar_gen, st);
   tend(h);
+  h->bar_gen += (unsigned)sc.nsteps;
 }
 
 // Fig. lmg on level l >= 0 in ordinate form; f (level l's f buffer) is the
@@ -534,6 +641,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
 // z = M^{-1} r (canonical FP64 in and out)
 void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st) {
   const int L = h->top();
+  h->n_precond++;
   DevLevel &D = h->lv[L];
   const double *pre_in = nullptr, *post_in = adj ? nullptr : D.winv;
   const double *pre_out = adj ? D.winv : nullptr, *post_out = nullptr;
@@ -720,6 +828,8 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
 
 void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
   s->ms_total = ms_total;
+  s->n_precond = (int)h->n_precond;
+  s->sweep_dof_updates = h->sweep_dofs;
   s->ms_sweep = s->ms_scatter = s->ms_transfer = s->ms_coarse = s->ms_apply = s->ms_orth = s->ms_other = 0;
   s->n_sweep = s->n_scatter = s->n_coarse = 0;
   s->ms_sweep_finest = 0;
@@ -994,6 +1104,7 @@ int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi
     tr::launch_convert<double, double>(f, D.f64, D.P, h->g.S, nullptr, adj ? nullptr : D.winv, S(st));
     do_coarse(h, D.f64, D.u64, nu, adj, S(st));
     tr::launch_convert<double, double>(D.u64, phi, D.P, h->g.S, adj ? D.winv : nullptr, nullptr, S(st));
+    check_barrier(h, S(st));
     return TR_OK;
   });
 }
@@ -1004,6 +1115,7 @@ int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, doub
     return fail(TR_ERR_ARG, "bad preconditioner mode");
   return translate([&]() {
     precondition(h, prec_mode, adjoint != 0, r, z, S(st));
+    check_barrier(h, S(st));
     return TR_OK;
   });
 }
@@ -1026,9 +1138,12 @@ static int solve_common(tr_handle *h, bool adj, const double *b, double *x, cons
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    h->n_precond = 0;
+    h->sweep_dofs = 0;
     HIPCHK(hipEventRecord(e0, S(st)));
     int r = gmres(h, adj, b, x, o, stats, S(st));
     HIPCHK(hipEventRecord(e1, S(st)));
+    check_barrier(h, S(st));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));

@@ -134,3 +134,35 @@ def test_determinism(pair):
     a = to_np(pair.tr.vcycle(r))
     b = to_np(pair.tr.vcycle(r))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [(28, 28, 28), (64, 64, 20)])
+def test_sweep_large_planes(n):
+    """Planes of 588 and ~1280 cells: several cells per thread per plane."""
+    from paper_2010_04559_amd import inputs
+    torch = torch_mod()
+    prob = inputs.small_problem(dim=3, n=4, level=0, order=2, seed=12)
+    C = n[0] * n[1] * n[2]
+    rng = np.random.default_rng(13)
+    prob.n = n
+    prob.sigma_t = rng.uniform(0.5, 4.0, C)
+    prob.sigma_s = 0.5 * prob.sigma_t
+    prob.q_cell = np.zeros(C)
+    prob.inflow = None
+    print("case", n, flush=True)
+    pr = Pair(prob, with_mg=False)
+    lv = pr.op.outer
+    g = _rand(lv.A * lv.grid.S, 14)
+    assert rel(to_np(pr.tr.sweep(0, to_dev(g))), lv.sweep(g)) < 1e-12
+    assert rel(to_np(pr.tr.sweep(0, to_dev(g), adjoint=True)), lv.sweep_T(g)) < 1e-12
+
+
+def test_coarse_gs_multiblock_planes():
+    """A 12^3 grid: planes of up to 127 cells span several workgroups."""
+    prob = small(dim=3, n=12, level=0, order=3, seed=15)
+    print("case 12^3 level 0", flush=True)
+    pr = Pair(prob)
+    lv0 = pr.op.mg.levels[0]
+    f = _rand(lv0.A * lv0.grid.S, 16)
+    assert rel(to_np(pr.tr.coarse_gs(to_dev(f), 2)), pr.op.mg.coarse_gs(f, 2)) < 1e-11
+    assert rel(to_np(pr.tr.coarse_gs(to_dev(f), 2, adjoint=True)), pr.op.mg.coarse_gs(f, 2, adjoint=True)) < 1e-11
