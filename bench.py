@@ -86,6 +86,10 @@ def main():
     ap.add_argument("--n", type=int, default=32, help="cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="cfg2 (default) is the headline line; the others print a measurement line of "
+                         "their own (2-D square, 48^3 precision study, 32^3 beam gradient, cone mesh)")
+    ap.add_argument("--fd-cells", type=int, default=6, help="finite-difference cells for cfg4/cfg5")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
@@ -95,6 +99,9 @@ def main():
     from paper_2010_04559_amd import inputs
     from paper_2010_04559_amd.transport import Transport
 
+    if args.workload != "cfg2":
+        print(json.dumps(other_workload(args)))
+        return
     prob = inputs.config2(args.n)
     t_setup = time.perf_counter()
     tr = Transport(prob)
@@ -190,6 +197,86 @@ def main():
         print("cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(line))
+
+
+def _solve_timed(tr, b, mode, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        x, st = tr.solve(b, mode=mode)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, st = tr.solve(b, mode=mode)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return x, st, ms
+
+
+def other_workload(args):
+    """Measurements of the other problem configurations (not the headline)."""
+    import numpy as np
+    import torch
+    from paper_2010_04559_amd import inputs
+    from paper_2010_04559_amd.transport import Transport
+    make = {"cfg1": inputs.config1, "cfg3": inputs.config3, "cfg4": inputs.config4, "cfg5": inputs.config5}
+    prob = make[args.workload]()
+    t_setup = time.perf_counter()
+    tr = Transport(prob)
+    b = tr.rhs()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print("%s setup %.1f s, patches %s, S=%d" % (prob.name, t_setup, tr.patches, tr.S), file=sys.stderr, flush=True)
+    out = {"workload": prob.name, "patches": tr.patches, "spatial_dofs": tr.S,
+           "dofs": 3 * tr.patches[-1] * tr.S, "setup_s": t_setup, "solves": {}}
+    modes = ["f64", "mixed"]
+    xs = {}
+    for mode in modes:
+        x, st, ms = _solve_timed(tr, b, mode, args.steps, args.warmup)
+        r = b - tr.apply(x)
+        xs[mode] = x
+        out["solves"][mode] = {"ms": ms, "iters": st["iters"], "rel_res": st["rel_res"],
+                               "explicit_rel_res": float(torch.linalg.norm(r) / torch.linalg.norm(b)),
+                               "sweep_dof_updates_per_s": st["sweep_dof_updates"] / (ms * 1e-3)}
+        print(mode, out["solves"][mode], file=sys.stderr, flush=True)
+    out["mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs["mixed"] - xs["f64"]) / torch.linalg.norm(xs["f64"]))
+    _, stt = tr.solve(b, timing=True)
+    out["breakdown_ms_fp64"] = {k: round(stt[k], 3) for k in ("ms_total", "ms_sweep", "ms_scatter", "ms_transfer",
+                                                              "ms_coarse", "ms_apply", "ms_orth", "ms_other")}
+    if prob.detector is not None:
+        w = tr.detector()
+        x = xs["f64"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gt, gs, lam, sta = tr.adjoint_grad(w, x, mode="mixed")
+        torch.cuda.synchronize()
+        out["adjoint"] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": sta["iters"], "rel_res": sta["rel_res"],
+                          "reciprocity_rel": abs(float(torch.dot(w, x)) - float(torch.dot(lam, b)))
+                          / abs(float(torch.dot(w, x)))}
+        # central differences (h = 1e-6 relative) on seeded cells, solves to 1e-13
+        gt13, gs13, _, _ = tr.adjoint_grad(w, tr.solve(b, tol=1e-13, mode="mixed")[0], tol=1e-13, mode="mixed")
+        gt13, gs13 = gt13.cpu().numpy(), gs13.cpu().numpy()
+        errs = []
+        cells = list(prob.fd_cells[:args.fd_cells])
+        st0, ss0 = prob.sigma_t.copy(), prob.sigma_s.copy()
+        for j in cells:
+            for which in ("t", "s"):
+                base = (st0 if which == "t" else ss0)[j]
+                h = 1e-6 * base
+                vals = []
+                for sgn in (1, -1):
+                    st_, ss_ = st0.copy(), ss0.copy()
+                    (st_ if which == "t" else ss_)[j] = base + sgn * h
+                    tr.set_sigma(st_, ss_)
+                    xs_, _ = tr.solve(b, tol=1e-13, mode="mixed")
+                    vals.append(float(torch.dot(w, xs_)))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                ref = gt13 if which == "t" else gs13
+                errs.append(abs(fd - ref[j]) / np.abs(ref).max())
+            print("fd cell", j, errs[-2:], file=sys.stderr, flush=True)
+        tr.set_sigma(st0, ss0)
+        out["fd_check"] = {"cells": [int(c) for c in cells], "max_err_rel_to_max_grad": max(errs),
+                           "h_rel": 1e-6, "solve_tol": 1e-13}
+    return out
 
 
 if __name__ == "__main__":

@@ -420,6 +420,30 @@ def scatter_matrix_addition(patches, moments):
     return B @ kern @ B.T
 
 
+def scatter_rows_addition(patches, moments, q, chunk=4096):
+    """Rows 3q..3q+2 of S~ through the addition theorem, accumulating the
+    Legendre sum by its three-term recurrence over chunks of quadrature
+    points (for meshes where the dense kernel would not fit in memory)."""
+    moments = np.asarray(moments, dtype=np.float64)
+    L = len(moments) - 1
+    coef = moments * (2 * np.arange(L + 1) + 1) / (4 * math.pi)
+    om_q, w_q = quad_accurate(patches[q], L)
+    bq = (lin_basis(patches[q], om_q) * w_q[:, None]).T          # (3, nq)
+    rows = np.zeros((3, 3 * len(patches)))
+    for p, patch in enumerate(patches):
+        om_p, w_p = quad_accurate(patch, L)
+        bp = (lin_basis(patch, om_p) * w_p[:, None]).T          # (3, np)
+        for c0 in range(0, len(w_p), chunk):
+            mu = np.clip(om_q @ om_p[c0:c0 + chunk].T, -1.0, 1.0)
+            p0, p1 = np.ones_like(mu), mu
+            kern = coef[0] * p0 + (coef[1] * p1 if L >= 1 else 0.0)
+            for n in range(1, L):
+                p0, p1 = p1, ((2 * n + 1) * mu * p1 - n * p0) / (n + 1)
+                kern = kern + coef[n + 1] * p1
+            rows[:, 3 * p:3 * p + 3] += bq @ kern @ bp[:, c0:c0 + chunk].T
+    return rows
+
+
 def hg_moments(g, order):
     """Henyey-Greenstein Legendre coefficients f_n = g^n, plain truncation."""
     return np.array([g ** n for n in range(order + 1)], dtype=np.float64)

@@ -414,7 +414,7 @@ void build(tr_handle *h, const tr_problem *p) {
     D.f64 = h->alloc<double>(n);
     D.u64 = h->alloc<double>(n);
     D.sa64 = h->alloc<double>(n);
-    D.sb64 = h->alloc<double>(n);
+    D.sb64 = p->nu_pre > 1 ? h->alloc<double>(n) : nullptr;  // second buffer only for nu_pre > 1
     tr::launch_fill<double>(D.f64, n, 0.0, nullptr);
     tr::launch_fill<double>(D.u64, n, 0.0, nullptr);
   }
@@ -434,7 +434,7 @@ void ensure_mixed(tr_handle *h) {
     D.f32 = h->alloc<float>(n);
     D.u32 = h->alloc<float>(n);
     D.sa32 = h->alloc<float>(n);
-    D.sb32 = h->alloc<float>(n);
+    D.sb32 = h->prob.nu_pre > 1 ? h->alloc<float>(n) : nullptr;
   }
   h->mixed_ready = true;
 }
@@ -719,7 +719,6 @@ void ensure_krylov(tr_handle *h, int m) {
     h->Z.clear();
   }
   if (!h->kw) h->kw = h->alloc<double>(n);
-  if (!h->kx) h->kx = h->alloc<double>(n);
   h->kry_m = m;
 }
 
@@ -1048,7 +1047,7 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
     DevLevel &D = h->lv[level];
     if (prec == TR_F64) {
       const double *St = outer ? h->Souter : D.St64;
-      double *t = level == h->top() ? h->tmp : D.sb64;
+      double *t = level == h->top() ? h->tmp : D.sa64;
       tr::launch_gemm<double>(St, (const double *)phi, t, D.A, (int)h->g.S, D.A, S(st));
       tr::launch_scale_sn<double>(t, (double *)s, h->sig_s, D.A, h->g, S(st));
     } else {

@@ -121,6 +121,15 @@ def test_scatter_matrix_addition_theorem():
         assert np.abs(a - a.T).max() < 1e-15
 
 
+def test_scatter_rows_by_recurrence_match_full_matrix():
+    pts = ang.AngularMesh.uniform(1).leaves()
+    mom = ang.hg_moments(0.9, 7)
+    full = ang.scatter_matrix(pts, mom)
+    for q in (0, 13):
+        rows = ang.scatter_rows_addition(pts, mom, q, chunk=50)
+        assert np.abs(rows - full[3 * q:3 * q + 3]).max() < 1e-12 * np.abs(full).max()
+
+
 def test_scatter_isotropic_cases():
     pts = ang.AngularMesh.uniform(1).leaves()
     ipsi = np.concatenate([(ang.lin_basis(p, om).T @ w) for p in pts
