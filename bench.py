@@ -56,13 +56,13 @@ def measured_traffic(kernel, digest):
 
 def cpu_baseline(prob):
     """The oracle's transport sweep on a bounded sample of the same workload:
-    the 48 patches of three octants on the 32^3 grid (3/8 of one
-    finest-level sweep), FP64 numpy on the host."""
+    one whole finest-level sweep (all 128 patches) on the 32^3 grid, FP64
+    numpy on the host."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import numpy as np
     from oracle import angular as ang, spatial as sp, transport as otr
     grid = sp.Grid(prob.dim, prob.n, prob.length)
-    patches = [p for p in ang.AngularMesh.uniform(prob.angular.base_level).leaves() if p.octant in (0, 1, 2)]
+    patches = ang.AngularMesh.uniform(prob.angular.base_level).leaves()
     lv = otr.Level(grid, patches, prob.sigma_t, prob.sigma_s, [1.0])
     g = np.random.default_rng(0).standard_normal(lv.A * grid.S)
     r0 = resource.getrusage(resource.RUSAGE_SELF)
@@ -74,8 +74,8 @@ def cpu_baseline(prob):
     dofs = lv.A * grid.S
     return {"value": dofs / (t1 - t0), "unit": "DoF-updates/s", "cores": max(1, round(cpu / (t1 - t0))),
             "kind": "oracle",
-            "sample": "oracle transport sweep (coupled 24x24 local solves) over the 48 patches of 3 of 8 "
-                      "octants on the 32^3 grid: %d DoF-updates in %.1f s" % (dofs, t1 - t0)}
+            "sample": "one oracle transport sweep (coupled 24x24 local solves) over all %d patches on the "
+                      "%d^3 grid: %d DoF-updates in %.1f s" % (len(patches), prob.n[0], dofs, t1 - t0)}
 
 
 def main():
@@ -90,6 +90,10 @@ def main():
                     help="cfg2 (default) is the headline line; the others print a measurement line of "
                          "their own (2-D square, 48^3 precision study, 32^3 beam gradient, cone mesh)")
     ap.add_argument("--fd-cells", type=int, default=6, help="finite-difference cells for cfg4/cfg5")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch the kernels whose hardware counters are recorded: a 1 GiB device copy "
+                         "(counter calibration), then the finest-level FP64 and FP32 sweeps (3 launches each) "
+                         "and FP64 scatter GEMMs (2 launches) of the headline problem")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
@@ -99,6 +103,9 @@ def main():
     from paper_2010_04559_amd import inputs
     from paper_2010_04559_amd.transport import Transport
 
+    if args.profile_kernels:
+        print(json.dumps(profile_kernels(args)))
+        return
     if args.workload != "cfg2":
         print(json.dumps(other_workload(args)))
         return
@@ -191,12 +198,45 @@ def main():
                          "fp32_ms": ms_sweep32},
         "scatter_gemm": {"fp64_ms": ms_gemm, "fp64_tflops": gemm_tfs, "fp64_frac": gemm_tfs / FP64_PEAK_TFS,
                          "fp32_ms": ms_gemm32, "fp32_tflops": gemm32_tfs, "fp32_frac": gemm32_tfs / FP32_PEAK_TFS},
+        "coarse_gs": coarse_gs_line(stt),
         "setup_s": t_setup,
     }
     if not args.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(line))
+
+
+def coarse_gs_line(stt):
+    """Latency figures of the coarsest-level Gauss-Seidel solve: time per
+    solve and per dependent step of its step schedule."""
+    if not stt["n_coarse"] or not stt["coarse_steps"]:
+        return None
+    ms = stt["ms_coarse"] / stt["n_coarse"]
+    return {"ms_per_solve": ms, "dependent_steps": stt["coarse_steps"],
+            "us_per_step": 1e3 * ms / stt["coarse_steps"]}
+
+
+def profile_kernels(args):
+    """A short program for rocprofv3 counter passes (see --profile-kernels)."""
+    import torch
+    from paper_2010_04559_amd import inputs
+    from paper_2010_04559_amd.transport import Transport
+    n_copy = 1 << 27
+    src = torch.ones(n_copy, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copy of %d bytes done" % (8 * n_copy), file=sys.stderr, flush=True)
+    prob = inputs.config2(args.n)
+    tr = Transport(prob)
+    L = tr.nlev - 1
+    out = {"copy_bytes": 8 * n_copy, "dofs": 3 * tr.patches[L] * tr.S,
+           "sweep_f64_ms": tr.time_sweep_kernel(L, "f64", reps=3),
+           "sweep_f32_ms": tr.time_sweep_kernel(L, "f32", reps=3),
+           "gemm_f64_ms": tr.time_scatter_kernel(L, outer=False, prec="f64", reps=2)}
+    torch.cuda.synchronize()
+    return out
 
 
 def _solve_timed(tr, b, mode, steps, warmup):

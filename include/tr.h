@@ -113,6 +113,7 @@ typedef struct {
   int n_sweep_finest;
   int n_precond;                /* preconditioner applications                    */
   double sweep_dof_updates;     /* sum over transport sweeps of (ordinates x spatial dofs) */
+  int coarse_steps;             /* dependent steps of one coarse Gauss-Seidel solve */
 } tr_solve_stats;
 
 /* Build the angular mesh, quadrature, level operators, prolongations and

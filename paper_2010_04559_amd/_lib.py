@@ -55,7 +55,7 @@ class TrSolveStats(ctypes.Structure):
                 ("ms_other", ctypes.c_double), ("n_sweep", ctypes.c_int), ("n_scatter", ctypes.c_int),
                 ("n_coarse", ctypes.c_int), ("ms_sweep_finest", ctypes.c_double),
                 ("n_sweep_finest", ctypes.c_int), ("n_precond", ctypes.c_int),
-                ("sweep_dof_updates", ctypes.c_double)]
+                ("sweep_dof_updates", ctypes.c_double), ("coarse_steps", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

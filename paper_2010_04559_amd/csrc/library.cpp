@@ -170,6 +170,7 @@ struct tr_handle {
   static constexpr int kMaxGsBlocks = 1024;
   long long n_precond = 0;
   double sweep_dofs = 0;
+  int coarse_steps = 0;
   std::vector<void *> allocs;
   size_t bytes = 0;
   EventTimer *timer = nullptr;
@@ -585,6 +586,7 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
                        tr_handle::kMaxGsBlocks, h->bar_gen, st);
   tend(h);
   h->bar_gen += (unsigned)sc.nsteps;
+  h->coarse_steps = sc.nsteps;
 }
 
 // Fig. lmg on level l >= 0 in ordinate form; f (level l's f buffer) is the
@@ -829,6 +831,7 @@ void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
   s->ms_total = ms_total;
   s->n_precond = (int)h->n_precond;
   s->sweep_dof_updates = h->sweep_dofs;
+  s->coarse_steps = h->coarse_steps;
   s->ms_sweep = s->ms_scatter = s->ms_transfer = s->ms_coarse = s->ms_apply = s->ms_orth = s->ms_other = 0;
   s->n_sweep = s->n_scatter = s->n_coarse = 0;
   s->ms_sweep_finest = 0;

@@ -87,3 +87,22 @@ def test_gradient_matches_central_differences_on_gpu():
             fd = (vals[0] - vals[1]) / (2 * h)
             ref = gt if which == "t" else gs
             assert abs(fd - ref[j]) < 1e-5 * np.abs(ref).max(), (which, j, fd, ref[j])
+
+
+def test_autograd_detector_response_matches_oracle():
+    """torch.autograd through DetectorResponse: R and both gradients against
+    the oracle's adjoint gradient on the same problem."""
+    torch = torch_mod()
+    from paper_2010_04559_amd.autograd import detector_response
+    prob = small(dim=2, n=4, level=1, order=6, g=0.85, c=0.9, seed=11)
+    prob.detector = ((2, 1, 0), (3, 2, 0))
+    pr = Pair(prob)
+    b_np, w_np = pr.op.rhs(), pr.op.detector()
+    R_ref, gt_ref, gs_ref, _, _ = adjoint.response_and_gradient(pr.op.outer, pr.op.mg, b_np, w_np, 1e-12)
+    st = torch.tensor(prob.sigma_t, dtype=torch.float64, device="cuda", requires_grad=True)
+    ss = torch.tensor(prob.sigma_s, dtype=torch.float64, device="cuda", requires_grad=True)
+    R = detector_response(pr.tr, st, ss, to_dev(b_np), to_dev(w_np), "f64", 1e-12)
+    assert abs(float(R) - R_ref) < 1e-10 * abs(R_ref)
+    (3.0 * R).backward()
+    assert rel(to_np(st.grad), 3.0 * gt_ref) < 1e-9
+    assert rel(to_np(ss.grad), 3.0 * gs_ref) < 1e-9
