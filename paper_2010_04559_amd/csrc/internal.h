@@ -31,6 +31,10 @@ struct Planes {
   const int *off;     // [nplanes + 1]
   int nplanes;
   int max_plane;
+  // Per cell-list entry: {packed cell, position of the neighbour along
+  // x, y, z within the adjacent plane, or -1 at the boundary}; link[0] the
+  // upwind neighbours (previous plane), link[1] the downwind ones (next plane).
+  const int4 *link[2];
 };
 
 template <typename T>

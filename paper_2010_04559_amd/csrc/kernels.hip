@@ -224,6 +224,220 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------ LDS sweep
+// The same sweep with the previous plane's solution kept in LDS (node-major,
+// [node][position in plane]), so that the dependence chain from one plane
+// to the next never leaves the CU: the upwind traces are LDS reads, the
+// global stores of the solution are not waited for, and the loads of the
+// next plane's right-hand side (and, one plane further ahead, of its cell
+// list entries) are in flight while the current plane is solved.  Each
+// plane needs two workgroup barriers that wait for LDS traffic only: one
+// before the plane's values overwrite the previous plane's, one before the
+// next plane reads them.
+constexpr int kSweepLdsThreads = 1024;
+
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ long long flipped_cell(int packed, int flip, const Grid &g) {
+  int ci[3], ix[3];
+  unpack_cell(packed, flip, g, ci, ix);
+  return cell_index(ix, g);
+}
+
+template <typename T, int DIM, bool ADJ, bool HAS_S, int R, int FLIP>
+__device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds) {
+  constexpr int NS = 1 << DIM;
+  constexpr int TH = kSweepLdsThreads;
+  constexpr int RS = HAS_S ? R : 1;
+  const OrdInfo o = a.ord[k];
+  const T c[3] = {T(o.c[0]), T(o.c[1]), T(o.c[2])};
+  const T av[3] = {T(o.a[0]), T(o.a[1]), T(o.a[2])};
+  const ModeConst<T, DIM> mc = mode_const<T, DIM>(c);
+  const long long S = a.g.S;
+  const T *fk = a.f + (long long)k * S;
+  const T *sk = HAS_S ? a.s + (long long)k * S : nullptr;
+  T *uk = a.u + (long long)k * S;
+  const int np = a.pl.nplanes;
+  const int maxp = a.pl.max_plane;
+  const int4 *link = a.pl.link[ADJ ? 1 : 0];
+  const int *off = a.pl.off;
+  const int tid = threadIdx.x;
+
+  auto load_link = [&](int pp, int4 (&lk)[R]) {
+    const int p = ADJ ? np - 1 - pp : pp;
+    const int beg = off[p], end = off[p + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int idx = beg + tid + r * TH;
+      lk[r] = idx < end ? link[idx] : make_int4(-1, -1, -1, -1);
+    }
+  };
+  auto load_rhs = [&](const int4 (&lk)[R], T (&fb)[R][NS], T (&sb)[RS][NS], T (&st)[R], T (&ss)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (lk[r].x >= 0) {
+        const long long j = flipped_cell(lk[r].x, FLIP, a.g);
+        load_node_vec<T, NS>(fk + j * NS, fb[r]);
+        if (HAS_S) load_node_vec<T, NS>(sk + j * NS, sb[HAS_S ? r : 0]);
+        st[r] = T(a.sig_t[j]);
+        if (HAS_S) ss[r] = T(a.sig_s[j]);
+      }
+    }
+  };
+
+  int4 lk_cur[R], lk_nxt[R];
+  T f_cur[R][NS], s_cur[RS][NS], st_cur[R], ss_cur[R];
+  load_link(0, lk_cur);
+  load_rhs(lk_cur, f_cur, s_cur, st_cur, ss_cur);
+  if (np > 1) load_link(1, lk_nxt);
+
+  const T ivn = T((double)(1 << DIM) / a.g.vol);  // N^{-1} = (2^DIM / vol) prod_xi [[2,-1],[-1,2]]
+  for (int pp = 0; pp < np; ++pp) {
+    // the part of the right-hand side that does not depend on the sweep,
+    // formed before the next plane's loads are issued so that f and s of
+    // this plane are dead by then:
+    //   forward  v = N^{-1} f + sigma_s s,   adjoint  v = f + sigma_s N s
+    T v[R][NS];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T *w = v[r];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) w[b] = f_cur[r][b];
+      if (!ADJ) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int b = 0; b < NS; ++b) {
+            if (b & (1 << d)) continue;
+            const T x0 = w[b], x1 = w[b | (1 << d)];
+            w[b] = T(2) * x0 - x1;
+            w[b | (1 << d)] = T(2) * x1 - x0;
+          }
+        if (HAS_S) {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) w[b] = w[b] * ivn + ss_cur[r] * s_cur[HAS_S ? r : 0][b];
+        } else {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) w[b] *= ivn;
+        }
+      } else if (HAS_S) {
+        T t[NS];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) t[b] = s_cur[HAS_S ? r : 0][b];
+        mass_shape<T, DIM, false>(t);
+        const T fs = ss_cur[r] * T(a.g.vol);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) w[b] += fs * t[b];
+      }
+    }
+
+    int4 lk_nn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) lk_nn[r] = make_int4(-1, -1, -1, -1);
+    T f_nxt[R][NS], s_nxt[RS][NS], st_nxt[R], ss_nxt[R];
+    if (pp + 1 < np) load_rhs(lk_nxt, f_nxt, s_nxt, st_nxt, ss_nxt);
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (lk_cur[r].x < 0) continue;
+      const int nbp[3] = {lk_cur[r].y, lk_cur[r].z, lk_cur[r].w};
+      // neighbour traces from LDS: forward, the upwind neighbour's outflow
+      // face; adjoint, the downwind neighbour's inflow face
+      T tr[DIM][NS / 2];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int fl = (FLIP >> d) & 1;
+        const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+        const int q = nbp[d] >= 0 ? nbp[d] : 0;
+#pragma unroll
+        for (int t = 0; t < NS / 2; ++t) tr[d][t] = nbp[d] >= 0 ? lds[insert_bit(t, d, nbit) * maxp + q] : T(0);
+      }
+      T *w = v[r];
+      if (!ADJ) {
+        // inflow: 4 c on the own inflow face, -2 c on the opposite face
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int own0 = (FLIP >> d) & 1;
+          const T c4 = T(4) * c[d], c2 = T(2) * c[d];
+#pragma unroll
+          for (int t = 0; t < NS / 2; ++t) {
+            w[insert_bit(t, d, own0)] += c4 * tr[d][t];
+            w[insert_bit(t, d, 1 - own0)] -= c2 * tr[d][t];
+          }
+        }
+      } else {
+        // outflow coupling a_xi (face mass) on the own outflow face
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int own1 = ((FLIP >> d) & 1) ? 0 : 1;
+          mass_shape<T, DIM - 1, false>(tr[d]);
+          T hs = av[d];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e)
+            if (e != d) hs *= T(a.g.h[e]);
+#pragma unroll
+          for (int t = 0; t < NS / 2; ++t) w[insert_bit(t, d, own1)] += hs * tr[d][t];
+        }
+      }
+      oriented_solve<T, DIM, ADJ, FLIP>(w, mc, st_cur[r]);
+      if (ADJ) {
+        mass_shape<T, DIM, true>(w);
+        const T iv = T(1.0 / a.g.vol);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) w[b] *= iv;
+      }
+    }
+    if (pp + 2 < np) load_link(pp + 2, lk_nn);
+    lds_barrier();  // every read of the previous plane is done
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (lk_cur[r].x < 0) continue;
+      const int q = tid + r * TH;  // position in the plane
+#pragma unroll
+      for (int b = 0; b < NS; ++b) lds[b * maxp + q] = v[r][b];
+      const long long j = flipped_cell(lk_cur[r].x, FLIP, a.g);
+      store_node_vec<T, NS>(uk + j * NS, v[r]);
+    }
+    lds_barrier();  // the plane is complete in LDS
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      lk_cur[r] = lk_nxt[r];
+      lk_nxt[r] = lk_nn[r];
+      st_cur[r] = st_nxt[r];
+      ss_cur[r] = ss_nxt[r];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) f_cur[r][b] = f_nxt[r][b];
+    }
+    if (HAS_S) {
+#pragma unroll
+      for (int r = 0; r < RS; ++r)
+#pragma unroll
+        for (int b = 0; b < NS; ++b) s_cur[r][b] = s_nxt[r][b];
+    }
+  }
+}
+
+template <typename T, int DIM, bool ADJ, bool HAS_S, int R>
+__global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char sweep_smem[];
+  T *lds = reinterpret_cast<T *>(sweep_smem);
+  const int k = blockIdx.x;
+  switch (a.ord[k].flip) {
+    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 0>(a, k, lds); break;
+    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 1>(a, k, lds); break;
+    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 2>(a, k, lds); break;
+    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 3>(a, k, lds); break;
+    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 4>(a, k, lds); break;
+    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 5>(a, k, lds); break;
+    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 6>(a, k, lds); break;
+    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 7>(a, k, lds); break;
+  }
+}
+
 // ------------------------------------------------------- coarse Gauss-Seidel
 // T_0 has one patch (three ordinates) per octant.  One launch handles one
 // diagonal plane of one octant: each (cell, octant) block is solved with
@@ -295,52 +509,76 @@ __device__ __forceinline__ double lane_backward(cx<double> U, int b, const AxisX
   return U.re;
 }
 
+// What a (cell, octant) update needs that does not depend on earlier
+// updates: cell indices, right-hand side and cross sections.  Loaded for
+// the next step before the grid barrier that ends the current one.
+template <int DIM>
+struct GsPrep {
+  long long j, jn[DIM];
+  double fv[3], st, ss;
+  int octant, flip;
+  bool has[DIM];
+};
+
+template <int DIM, bool ADJ>
+__device__ __forceinline__ GsPrep<DIM> gs_prepare(int item, const double *__restrict__ f,
+                                                  const double *__restrict__ sig_t, const double *__restrict__ sig_s,
+                                                  const OrdInfo *ord_lds, const Planes &pl, const Grid &g, int b) {
+  constexpr int NS = 1 << DIM;
+  GsPrep<DIM> q;
+  q.octant = item >> 28;
+  const int idx = item & ((1 << 28) - 1);
+  const int k0 = 3 * q.octant;
+  q.flip = ord_lds[k0].flip;
+  int ci[3], ix[3];
+  unpack_cell(pl.cells[idx], q.flip, g, ci, ix);
+  q.j = cell_index(ix, g);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int dir = ((q.flip >> d) & 1) ? -1 : 1;
+    q.has[d] = ADJ ? (ci[d] < g.n[d] - 1) : (ci[d] > 0);
+    int nx[3] = {ix[0], ix[1], ix[2]};
+    nx[d] += q.has[d] ? (ADJ ? dir : -dir) : 0;
+    q.jn[d] = cell_index(nx, g);
+  }
+  const long long S = g.S;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) q.fv[m] = f[(k0 + m) * S + q.j * NS + b];
+  q.st = sig_t[q.j];
+  q.ss = sig_s[q.j];
+  return q;
+}
+
 // Gauss-Seidel update of one (cell, octant) block by the 2^dim lanes of a
 // cell group; every lane of the wave must call it (idle groups pass
-// active = false with a valid cell and store nothing).
+// active = false with a valid cell and store nothing).  G_lds and ord_lds
+// are the level's 24 x 24 scatter block and ordinate data staged in LDS.
 template <int DIM, bool ADJ>
-__device__ __forceinline__ void gs_update(const double *__restrict__ f, double *__restrict__ u,
-                                          const double *__restrict__ G, const double *__restrict__ sig_t,
-                                          const double *__restrict__ sig_s, const OrdInfo *__restrict__ ord,
-                                          const Planes &pl, const Grid &g, int octant, int idx, bool active,
-                                          int b) {
+__device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restrict__ u, const double *G_lds,
+                                          const OrdInfo *ord_lds, const Grid &g, bool active, int b) {
   constexpr int NS = 1 << DIM;
+  const int octant = q.octant, flip = q.flip;
   const int k0 = 3 * octant;
-  const int flip = ord[k0].flip;
-  int ci[3], ix[3];
-  unpack_cell(pl.cells[idx], flip, g, ci, ix);
-  const long long j = cell_index(ix, g);
   const long long S = g.S;
-  const double st = sig_t[j], ss = sig_s[j];
+  const long long j = q.j;
+  const double st = q.st, ss = q.ss;
   const double *up = u + j * NS + b;
 
-  // gather everything the update reads before using any of it: all 24
-  // ordinate values at this node, the right-hand side and the upwind
-  // (adjoint: downwind) traces of the octant's three ordinates
+  // every value this update reads from earlier updates: all 24 ordinate
+  // values at this node and the upwind (adjoint: downwind) traces of the
+  // octant's three ordinates
   double uv[24];
 #pragma unroll
   for (int kp = 0; kp < 24; ++kp) uv[kp] = up[kp * S];
-  double fv[3], tr[3][DIM];
-  bool has[DIM];
-  long long jn[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const int fl = (flip >> d) & 1;
-    const int dir = fl ? -1 : 1;
-    has[d] = ADJ ? (ci[d] < g.n[d] - 1) : (ci[d] > 0);
-    int nx[3] = {ix[0], ix[1], ix[2]};
-    nx[d] += has[d] ? (ADJ ? dir : -dir) : 0;
-    jn[d] = cell_index(nx, g);
-  }
+  double tr[3][DIM];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    fv[m] = f[(k0 + m) * S + j * NS + b];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int fl = (flip >> d) & 1;
       const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
       const int bn = (b & ~(1 << d)) | (nbit << d);
-      tr[m][d] = u[(k0 + m) * S + jn[d] * NS + bn];
+      tr[m][d] = u[(k0 + m) * S + q.jn[d] * NS + bn];
     }
   }
   // scatter from the other octants' ordinates (latest values)
@@ -349,25 +587,25 @@ __device__ __forceinline__ void gs_update(const double *__restrict__ f, double *
   for (int kp = 0; kp < 24; ++kp) {
     const double w = (kp / 3 == octant) ? 0.0 : uv[kp];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) acc[m] += G[(k0 + m) * 24 + kp] * w;
+    for (int m = 0; m < 3; ++m) acc[m] += G_lds[(k0 + m) * 24 + kp] * w;
   }
   double v[3];
   double cc[3][3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    const OrdInfo o = ord[k0 + m];
+    const OrdInfo &o = ord_lds[k0 + m];
     cc[m][0] = o.c[0];
     cc[m][1] = o.c[1];
     cc[m][2] = o.c[2];
     if (!ADJ) {
-      v[m] = lane_mass<DIM>(fv[m], NS - 1, true) * (1.0 / g.vol) + ss * acc[m];
+      v[m] = lane_mass<DIM>(q.fv[m], NS - 1, true) * (1.0 / g.vol) + ss * acc[m];
     } else {
-      v[m] = fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false);
+      v[m] = q.fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false);
     }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int fl = (flip >> d) & 1;
-      double t = has[d] ? tr[m][d] : 0.0;
+      double t = q.has[d] ? tr[m][d] : 0.0;
       if (!ADJ) {
         const int own0 = fl ? 1 : 0;
         v[m] += (((b >> d) & 1) == own0 ? 4.0 : -2.0) * o.c[d] * t;
@@ -394,7 +632,7 @@ __device__ __forceinline__ void gs_update(const double *__restrict__ f, double *
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
 #pragma unroll
-    for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-ss * G[(k0 + m) * 24 + k0 + mp], 0.0};
+    for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-ss * G_lds[(k0 + m) * 24 + k0 + mp], 0.0};
     double re = st, im = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -430,58 +668,41 @@ __device__ __forceinline__ void gs_update(const double *__restrict__ f, double *
   }
 }
 
-
-// The whole coarse solve (nu sweeps over the octants) as one cooperative
-// launch.  The host orders the (sweep, octant, cell) updates into steps:
-// an update is placed one step after the latest of its upwind neighbours'
-// updates (same sweep and octant) and the same cell's previous update, so
-// every value it reads is final and the result equals the sequential
-// Gauss-Seidel sweep; items of one step touch distinct cells.  An item is
-// (octant << 28) | index into the plane-ordered cell list.  A grid-wide
-// barrier separates the steps.
 // Grid-wide barrier for a cooperative launch without contended atomics:
-// every block but 0 publishes its arrival generation in its own slot, block
-// 0 waits for all slots with one thread per slot, then publishes the
-// release generation.  Spins are bounded; on timeout the error word is set
-// and every block leaves its loops, so the kernel always terminates.
+// every block publishes its arrival generation in its own slot (after a
+// release fence that makes its stores visible device-wide), then thread i
+// of every block waits for slot i with relaxed loads, followed by one
+// acquire fence.  Spins are bounded; on timeout the error word is set and
+// every block leaves its loops, so the kernel always terminates.
 struct GridBarrier {
   unsigned *arrive;   // [blocks]
-  unsigned *release;  // [1]
+  unsigned *release;  // [1] (unused by the all-to-all form)
   int *err;           // [1]
 };
-
-__device__ __forceinline__ bool barrier_spin_done(const unsigned *p, unsigned gen, int *err, long &spins) {
-  if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= gen) return true;
-  if (++spins > (1L << 25) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-  }
-  return false;
-}
 
 __device__ bool grid_barrier(const GridBarrier &gb, unsigned gen) {
   __shared__ int ok;
   __syncthreads();
-  if (blockIdx.x == 0) {
-    for (unsigned i = threadIdx.x + 1; i < gridDim.x; i += blockDim.x) {
-      long spins = 0;
-      while (!barrier_spin_done(gb.arrive + i, gen, gb.err, spins)) {
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this block's stores, device-wide
+    __hip_atomic_store(gb.arrive + blockIdx.x, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  bool timeout = false;
+  for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+    long spins = 0;
+    while (__hip_atomic_load(gb.arrive + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      if (++spins > (1L << 25) || __hip_atomic_load(gb.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(gb.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        timeout = true;
+        break;
       }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      __hip_atomic_store(gb.release, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_store(gb.arrive + blockIdx.x, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    long spins = 0;
-    while (!barrier_spin_done(gb.release, gen, gb.err, spins)) {
-    }
-    __threadfence();
+    if (timeout) break;
   }
-  if (threadIdx.x == 0) ok = __hip_atomic_load(gb.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+  if (threadIdx.x < gridDim.x) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  if (timeout) ok = 0;
   __syncthreads();
   return ok;
 }
@@ -493,7 +714,8 @@ __device__ bool grid_barrier(const GridBarrier &gb, unsigned gen) {
 // every value it reads is final and the result equals the sequential
 // Gauss-Seidel sweep; items of one step touch distinct cells.  An item is
 // (octant << 28) | index into the plane-ordered cell list.  A grid-wide
-// barrier separates the steps.
+// barrier separates the steps; the first round of items of the next step
+// is prepared before it.
 template <int DIM, bool ADJ>
 __global__ __launch_bounds__(256) void k_gs_solve(const double *__restrict__ f, double *__restrict__ u,
                                                   const double *__restrict__ G, const double *__restrict__ sig_t,
@@ -503,16 +725,35 @@ __global__ __launch_bounds__(256) void k_gs_solve(const double *__restrict__ f, 
                                                   int nsteps, GridBarrier gb, unsigned gen0) {
   constexpr int NS = 1 << DIM;
   constexpr int CPB = 256 / NS;  // cells per block per round
+  __shared__ double G_lds[24 * 24];
+  __shared__ OrdInfo ord_lds[24];
+  for (int i = threadIdx.x; i < 24 * 24; i += blockDim.x) G_lds[i] = G[i];
+  if (threadIdx.x < 24) ord_lds[threadIdx.x] = ord[threadIdx.x];
+  __syncthreads();
   const int b = threadIdx.x & (NS - 1);
   const int slot = threadIdx.x / NS;
+  const int stride = gridDim.x * CPB;
+  auto first_item = [&](int t, bool &active) {
+    const int beg = step_off[t], end = step_off[t + 1];
+    const int it = beg + blockIdx.x * CPB + slot;
+    active = it < end;
+    return items[active ? it : beg];
+  };
+  bool act;
+  GsPrep<DIM> q = gs_prepare<DIM, ADJ>(first_item(0, act), f, sig_t, sig_s, ord_lds, pl, g, b);
   for (int t = 0; t < nsteps; ++t) {
     const int beg = step_off[t], end = step_off[t + 1];
-    for (int base = beg + blockIdx.x * CPB; base < end; base += gridDim.x * CPB) {
+    // the first round was prepared before the barrier; every block runs
+    // it so that the wave-wide shuffles see valid lanes
+    gs_update<DIM, ADJ>(q, u, G_lds, ord_lds, g, act, b);
+    for (int base = beg + blockIdx.x * CPB + stride; base < end; base += stride) {
       const int it = base + slot;
       const bool active = it < end;
-      const int item = items[active ? it : beg];
-      gs_update<DIM, ADJ>(f, u, G, sig_t, sig_s, ord, pl, g, item >> 28, item & ((1 << 28) - 1), active, b);
+      const GsPrep<DIM> q2 =
+          gs_prepare<DIM, ADJ>(items[active ? it : beg], f, sig_t, sig_s, ord_lds, pl, g, b);
+      gs_update<DIM, ADJ>(q2, u, G_lds, ord_lds, g, active, b);
     }
+    if (t + 1 < nsteps) q = gs_prepare<DIM, ADJ>(first_item(t + 1, act), f, sig_t, sig_s, ord_lds, pl, g, b);
     if (!grid_barrier(gb, gen0 + t + 1)) return;
   }
 }
@@ -919,8 +1160,21 @@ int grid_for(long long n, int block = kBlock) {
 }  // namespace
 
 // ------------------------------------------------------------- launchers
+// LDS variant when a thread owns one cell per plane (planes of at most
+// 1024 cells: 3-D grids up to about 36^3).  One 1024-thread workgroup per
+// CU (16 waves); the plane buffer is at most 64 KB.
+template <typename T, int DIM, bool ADJ, bool HAS_S>
+static bool launch_sweep_lds(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
+  if (a.pl.max_plane > kSweepLdsThreads) return false;
+  const size_t lds = sizeof(T) * (size_t)(1 << DIM) * (size_t)a.pl.max_plane;
+  hipLaunchKernelGGL((k_sweep_lds<T, DIM, ADJ, HAS_S, 1>), dim3(n_ord), dim3(kSweepLdsThreads), lds, st, a);
+  return true;
+}
+
 template <typename T, int DIM, bool ADJ>
 static void launch_sweep_r(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
+  if (a.s ? launch_sweep_lds<T, DIM, ADJ, true>(a, n_ord, st) : launch_sweep_lds<T, DIM, ADJ, false>(a, n_ord, st))
+    return;
   const int R = (a.pl.max_plane + kSweepThreads - 1) / kSweepThreads;
   // register prefetch of the next plane when a thread owns one cell per
   // plane; with more cells per thread the prefetch buffers would halve the

@@ -285,6 +285,38 @@ void build(tr_handle *h, const tr_problem *p) {
       off.push_back((int)cells.size());
       mx = std::max(mx, (int)b.size());
     }
+    // positions of each cell's neighbours in the adjacent planes
+    std::vector<int> pos(g.C);
+    auto lin = [&](int ix, int iy, int iz) { return ix + (long long)g.n[0] * (iy + (long long)g.n[1] * iz); };
+    for (int pl = 0; pl < np; ++pl)
+      for (int i = off[pl]; i < off[pl + 1]; ++i) {
+        const int c = cells[i];
+        pos[lin(c & 1023, (c >> 10) & 1023, (c >> 20) & 1023)] = i - off[pl];
+      }
+    std::vector<int> link_up(4 * cells.size()), link_dn(4 * cells.size());
+    for (size_t i = 0; i < cells.size(); ++i) {
+      const int c = cells[i];
+      const int ci[3] = {c & 1023, (c >> 10) & 1023, (c >> 20) & 1023};
+      link_up[4 * i] = link_dn[4 * i] = c;
+      for (int d = 0; d < 3; ++d) {
+        int up = -1, dn = -1;
+        if (d < g.dim) {
+          int q[3] = {ci[0], ci[1], ci[2]};
+          if (ci[d] > 0) {
+            q[d] = ci[d] - 1;
+            up = pos[lin(q[0], q[1], q[2])];
+          }
+          if (ci[d] < g.n[d] - 1) {
+            q[d] = ci[d] + 1;
+            dn = pos[lin(q[0], q[1], q[2])];
+          }
+        }
+        link_up[4 * i + 1 + d] = up;
+        link_dn[4 * i + 1 + d] = dn;
+      }
+    }
+    h->pl.link[0] = reinterpret_cast<const int4 *>(h->upload(link_up));
+    h->pl.link[1] = reinterpret_cast<const int4 *>(h->upload(link_dn));
     h->plane_off_host = off;
     h->d_cells = h->upload(cells);
     h->d_off = h->upload(off);

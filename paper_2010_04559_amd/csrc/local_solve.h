@@ -180,4 +180,164 @@ TR_HD void mass_shape(T *v) {
   }
 }
 
+// ------------------------------------------------------------------------
+// Specialised form of spectral_solve for an orientation known at compile
+// time.  The per-axis transforms are written out with their constant
+// coefficients (no multiplications by 0 or 1), and each forward or back
+// transform is taken without its factor q = 1/(2 sqrt 2) per axis; the
+// missing q^DIM, the factor 2 of the real part and the eigenvalue division
+// are applied together to each mode.  In oriented node order (x0 upstream,
+// x1 downstream) with s2 = sqrt 2:
+//   forward        m+- = s2 x0 -+ i (x0 + x1)            (times q)
+//   back           x0 = U+ + U-,  x1 = -(U+ + U-) + i s2 (U+ - U-)
+//   forward^T      m+- = (x0 - x1) +- i s2 x1
+//   back^T         x0 = s2 (U+ + U-) - i (U+ - U-),  x1 = -i (U+ - U-)   (times q)
+// On the first axis only the mu = + mode is formed (real input) and on the
+// last back transform only the real part is taken.
+
+// Per-ordinate constants of the mode eigenvalues D_k = sigma + c2 + i im[k].
+template <typename T, int DIM>
+struct ModeConst {
+  T c2;         // 2 (c_x + c_y + c_z)
+  T im[4];      // sqrt 2 (c_x +- c_y +- c_z), mode k = my * 2 + mz (3-D) or my (2-D)
+  T im2[4];     // im[k]^2
+};
+
+template <typename T, int DIM>
+TR_HD ModeConst<T, DIM> mode_const(const T *c) {
+  const T r2 = T(1.41421356237309504880);
+  ModeConst<T, DIM> m;
+  m.c2 = T(2) * (c[0] + c[1] + (DIM == 3 ? c[2] : T(0)));
+  for (int k = 0; k < (DIM == 3 ? 4 : 2); ++k) {
+    T sy = (DIM == 3 ? (k >> 1) : k) ? T(-1) : T(1);
+    T sz = (DIM == 3 && (k & 1)) ? T(-1) : T(1);
+    m.im[k] = r2 * (c[0] + sy * c[1] + (DIM == 3 ? sz * c[2] : T(0)));
+    m.im2[k] = m.im[k] * m.im[k];
+  }
+  return m;
+}
+
+// 1 / x for x > 0 in the normal range: hardware reciprocal estimate and two
+// Newton steps (double) or the estimate alone (float, 1 ulp).
+TR_HD double fast_rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+TR_HD float fast_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
+// forward pair, complex input (upstream x0, downstream x1) -> (m+, m-)
+template <typename T, bool TRANS>
+TR_HD void fwd_pair(cx<T> x0, cx<T> x1, cx<T> &mp, cx<T> &mm) {
+  const T r2 = T(1.41421356237309504880);
+  if (!TRANS) {
+    const cx<T> s{x0.re + x1.re, x0.im + x1.im}, t{r2 * x0.re, r2 * x0.im};
+    mp = {t.re + s.im, t.im - s.re};
+    mm = {t.re - s.im, t.im + s.re};
+  } else {
+    const cx<T> d{x0.re - x1.re, x0.im - x1.im}, e{r2 * x1.re, r2 * x1.im};
+    mp = {d.re - e.im, d.im + e.re};
+    mm = {d.re + e.im, d.im - e.re};
+  }
+}
+
+// back pair (U+, U-) -> complex node values (upstream x0, downstream x1)
+template <typename T, bool TRANS>
+TR_HD void bwd_pair(cx<T> up, cx<T> um, cx<T> &x0, cx<T> &x1) {
+  const T r2 = T(1.41421356237309504880);
+  const cx<T> P{up.re + um.re, up.im + um.im}, M{up.re - um.re, up.im - um.im};
+  if (!TRANS) {
+    x0 = P;
+    x1 = {-P.re - r2 * M.im, -P.im + r2 * M.re};
+  } else {
+    x0 = {r2 * P.re + M.im, r2 * P.im - M.re};
+    x1 = {M.im, -M.re};
+  }
+}
+
+// Solve (sum_xi c_xi E_xi + sigma I) u = v (TRANS: the transpose) in place
+// for the orientation FLIP; result identical to spectral_solve up to rounding.
+template <typename T, int DIM, bool TRANS, int FLIP>
+TR_HD void oriented_solve(T *v, const ModeConst<T, DIM> &mc, T sigma) {
+  const T r2 = T(1.41421356237309504880);
+  constexpr int fx = FLIP & 1, fy = (FLIP >> 1) & 1, fz = (FLIP >> 2) & 1;
+  // q^DIM times the factor 2 of the real part
+  const T kappa = DIM == 3 ? T(0.08838834764831844055) : T(0.25);
+  if (DIM == 3) {
+    cx<T> A[2][2];  // [by][bz], x-mode +
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bz = 0; bz < 2; ++bz) {
+        const T x0 = v[fx + 2 * by + 4 * bz], x1 = v[(1 - fx) + 2 * by + 4 * bz];
+        A[by][bz] = TRANS ? cx<T>{x0 - x1, r2 * x1} : cx<T>{r2 * x0, -(x0 + x1)};
+      }
+    cx<T> B[2][2];  // [my][bz]
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz) fwd_pair<T, TRANS>(A[fy][bz], A[1 - fy][bz], B[0][bz], B[1][bz]);
+    cx<T> m[4];
+#pragma unroll
+    for (int my = 0; my < 2; ++my) fwd_pair<T, TRANS>(B[my][fz], B[my][1 - fz], m[2 * my], m[2 * my + 1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T re = sigma + mc.c2;
+      const T f = kappa * fast_rcp(__builtin_fma(re, re, mc.im2[k]));
+      const T a = (m[k].re * re + m[k].im * mc.im[k]) * f;
+      const T b = (m[k].im * re - m[k].re * mc.im[k]) * f;
+      m[k] = {a, b};
+    }
+    cx<T> E[2][2];  // [my][bz]
+#pragma unroll
+    for (int my = 0; my < 2; ++my) bwd_pair<T, TRANS>(m[2 * my], m[2 * my + 1], E[my][fz], E[my][1 - fz]);
+    cx<T> F[2][2];  // [by][bz]
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz) bwd_pair<T, TRANS>(E[0][bz], E[1][bz], F[fy][bz], F[1 - fy][bz]);
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bz = 0; bz < 2; ++bz) {
+        const cx<T> f = F[by][bz];
+        v[fx + 2 * by + 4 * bz] = TRANS ? r2 * f.re + f.im : f.re;
+        v[(1 - fx) + 2 * by + 4 * bz] = TRANS ? f.im : -f.re - r2 * f.im;
+      }
+  } else {
+    cx<T> A[2];  // [by]
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      const T x0 = v[fx + 2 * by], x1 = v[(1 - fx) + 2 * by];
+      A[by] = TRANS ? cx<T>{x0 - x1, r2 * x1} : cx<T>{r2 * x0, -(x0 + x1)};
+    }
+    cx<T> m[2];
+    fwd_pair<T, TRANS>(A[fy], A[1 - fy], m[0], m[1]);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T re = sigma + mc.c2;
+      const T f = kappa * fast_rcp(__builtin_fma(re, re, mc.im2[k]));
+      const T a = (m[k].re * re + m[k].im * mc.im[k]) * f;
+      const T b = (m[k].im * re - m[k].re * mc.im[k]) * f;
+      m[k] = {a, b};
+    }
+    cx<T> F[2];
+    bwd_pair<T, TRANS>(m[0], m[1], F[fy], F[1 - fy]);
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      const cx<T> f = F[by];
+      v[fx + 2 * by] = TRANS ? r2 * f.re + f.im : f.re;
+      v[(1 - fx) + 2 * by] = TRANS ? f.im : -f.re - r2 * f.im;
+    }
+  }
+}
+
 }  // namespace tr
