@@ -672,7 +672,8 @@ __device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restri
 // every block publishes its arrival generation in its own slot (after a
 // release fence that makes its stores visible device-wide), then thread i
 // of every block waits for slot i with relaxed loads, followed by one
-// acquire fence.  Spins are bounded; on timeout the error word is set and
+// acquire fence.  Split in two halves so that independent loads can be
+// issued between them.  Spins are bounded; on timeout the error word is set and
 // every block leaves its loops, so the kernel always terminates.
 struct GridBarrier {
   unsigned *arrive;   // [blocks]
@@ -680,13 +681,19 @@ struct GridBarrier {
   int *err;           // [1]
 };
 
-__device__ bool grid_barrier(const GridBarrier &gb, unsigned gen) {
-  __shared__ int ok;
+// Arrival half of the barrier: the block's stores are made visible
+// device-wide and its slot is set to gen.
+__device__ __forceinline__ void grid_arrive(const GridBarrier &gb, unsigned gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this block's stores, device-wide
     __hip_atomic_store(gb.arrive + blockIdx.x, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// Waiting half: returns false (every thread) after a timeout anywhere.
+__device__ __forceinline__ bool grid_wait(const GridBarrier &gb, unsigned gen) {
+  __shared__ int ok;
   bool timeout = false;
   for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
     long spins = 0;
@@ -753,8 +760,11 @@ __global__ __launch_bounds__(256) void k_gs_solve(const double *__restrict__ f, 
           gs_prepare<DIM, ADJ>(items[active ? it : beg], f, sig_t, sig_s, ord_lds, pl, g, b);
       gs_update<DIM, ADJ>(q2, u, G_lds, ord_lds, g, active, b);
     }
+    // arrive, then load what the next step needs while the other blocks
+    // finish (it is read-only data, unaffected by the barrier's fences)
+    grid_arrive(gb, gen0 + t + 1);
     if (t + 1 < nsteps) q = gs_prepare<DIM, ADJ>(first_item(t + 1, act), f, sig_t, sig_s, ord_lds, pl, g, b);
-    if (!grid_barrier(gb, gen0 + t + 1)) return;
+    if (!grid_wait(gb, gen0 + t + 1)) return;
   }
 }
 
