@@ -43,10 +43,17 @@ struct SweepArgs {
   const T *s;           // [A][S] scatter moments G u (may be null)
   T *u;                 // [A][S] ordinate values (output)
   const double *sig_t, *sig_s;
+  // sigma_t and sigma_s per orientation in cell-list order:
+  // [2][8][cells], index [which][flip][list index]
+  const double *sig_pl;
   const OrdInfo *ord;
   Planes pl;
   Grid g;
 };
+
+// Fill SweepArgs::sig_pl from the per-cell cross sections.
+void launch_sigma_planes(const double *sig_t, const double *sig_s, const Planes &pl, const Grid &g, double *out,
+                         hipStream_t st);
 
 // ------------------------------------------------------------- launchers
 template <typename T>

@@ -227,13 +227,22 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs<T> a) {
 // ------------------------------------------------------------ LDS sweep
 // The same sweep with the previous plane's solution kept in LDS (node-major,
 // [node][position in plane]), so that the dependence chain from one plane
-// to the next never leaves the CU: the upwind traces are LDS reads, the
-// global stores of the solution are not waited for, and the loads of the
-// next plane's right-hand side (and, one plane further ahead, of its cell
-// list entries) are in flight while the current plane is solved.  Each
-// plane needs two workgroup barriers that wait for LDS traffic only: one
-// before the plane's values overwrite the previous plane's, one before the
-// next plane reads them.
+// to the next never leaves the CU.  A 1024-thread workgroup per ordinate is
+// split into compute waves (one cell per thread and plane) and store waves.
+//  * Global memory is accessed in whole cells: a 16-byte load or store of
+//    a wave covers 64 / Q cells completely (Q = 16-byte chunks per cell),
+//    instead of one chunk of 64 different cells.  Loaded chunks are moved
+//    to the thread that owns the cell through a per-wave LDS staging area.
+//  * Compute waves issue only loads: the next plane's right-hand side (and
+//    scatter source), cross sections and, one plane further ahead, its
+//    cell-list entries are loaded while the current plane is solved and
+//    awaited only after the plane's barriers.
+//  * Store waves copy each finished plane from LDS to global memory, so no
+//    compute wave ever waits for a store (gfx9 counts loads and stores on
+//    one counter, so a wait for a load would include every earlier store).
+// Each plane takes two workgroup barriers that wait for LDS traffic only:
+// one before the plane's values overwrite the previous plane's, one before
+// the next plane (and the store waves) read them.
 constexpr int kSweepLdsThreads = 1024;
 
 __device__ __forceinline__ void lds_barrier() {
@@ -248,11 +257,36 @@ __device__ __forceinline__ long long flipped_cell(int packed, int flip, const Gr
   return cell_index(ix, g);
 }
 
-template <typename T, int DIM, bool ADJ, bool HAS_S, int R, int FLIP>
-__device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds) {
+// Marks a register as used at this point (an empty asm statement): the
+// compiler must wait here for a load that produces it, and cannot move the
+// wait before an earlier barrier.
+__device__ __forceinline__ void pin_reg(float4 &x) {
+  asm volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w));
+}
+__device__ __forceinline__ void pin_reg(int4 &x) {
+  asm volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w));
+}
+__device__ __forceinline__ void pin_reg(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_reg(int &x) { asm volatile("" : "+v"(x)); }
+
+// Staged next-plane data of a compute lane: Q 16-byte chunks of f (and s)
+// as loaded (chunk l / CPI of the wave's cell CPI i + l % CPI for chunk
+// slot i), and the lane's own cross sections and cell-list entry.
+template <int Q, bool HAS_S>
+struct StageRegs {
+  float4 f[Q], s[HAS_S ? Q : 1];
+  double st, ss;
+  int4 lk;
+};
+
+template <typename T, int DIM, bool ADJ, bool HAS_S, int FLIP>
+__device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
+                                               float4 *stage, int tc) {
   constexpr int NS = 1 << DIM;
-  constexpr int TH = kSweepLdsThreads;
-  constexpr int RS = HAS_S ? R : 1;
+  constexpr int Q = NS * (int)sizeof(T) / 16;  // 16-byte chunks per cell
+  constexpr int CPI = 64 / Q;                   // cells per 16-byte wave access
+  constexpr int EPC = 16 / (int)sizeof(T);      // elements per chunk
+  using Regs = StageRegs<Q, HAS_S>;
   const OrdInfo o = a.ord[k];
   const T c[3] = {T(o.c[0]), T(o.c[1]), T(o.c[2])};
   const T av[3] = {T(o.a[0]), T(o.a[1]), T(o.a[2])};
@@ -261,92 +295,135 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
   const T *fk = a.f + (long long)k * S;
   const T *sk = HAS_S ? a.s + (long long)k * S : nullptr;
   T *uk = a.u + (long long)k * S;
+  const long long C = a.g.C;
+  const double *sgt = a.sig_pl + (long long)FLIP * C;
+  const double *sgs = a.sig_pl + (8LL + FLIP) * C;
   const int np = a.pl.nplanes;
   const int maxp = a.pl.max_plane;
   const int4 *link = a.pl.link[ADJ ? 1 : 0];
-  const int *off = a.pl.off;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const bool compute = tid < tc;
+  // this wave's staging area: Q KB for f, then Q KB for s
+  float4 *stg = stage + (size_t)(tid >> 6) * (HAS_S ? 2 : 1) * Q * 64;
+  const T ivn = T((double)(1 << DIM) / a.g.vol);  // N^{-1} = (2^DIM / vol) prod_xi [[2,-1],[-1,2]]
 
-  auto load_link = [&](int pp, int4 (&lk)[R]) {
-    const int p = ADJ ? np - 1 - pp : pp;
-    const int beg = off[p], end = off[p + 1];
+  auto plane_of = [&](int pp) { return ADJ ? np - 1 - pp : pp; };
+  // Every global load below is unconditional, from an address clamped to
+  // valid memory, and its validity is applied only after the wait: a load
+  // under a branch, or a select on its result, would make the compiler
+  // wait for it (and for everything issued before it) at once.
+  auto link_valid = [&](int pp) {
+    const int p = plane_of(pp);
+    return off[p] + tid < off[p + 1];
+  };
+  auto load_link = [&](int pp) {
+    const int p = plane_of(pp);
+    return link[min(off[p] + tid, (int)C - 1)];
+  };
+  // loads of plane pp for this wave's 64 cells; q.lk holds the lane's own
+  // entry (its cell index is shuffled to the lanes that load its chunks)
+  auto load_plane = [&](int pp, Regs &q) {
+    const int p = plane_of(pp);
+    const int idx = min(off[p] + tid, (int)C - 1);
+    const int j = q.lk.x >= 0 ? (int)flipped_cell(q.lk.x, FLIP, a.g) : 0;
+    const int ch = lane / CPI;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int idx = beg + tid + r * TH;
-      lk[r] = idx < end ? link[idx] : make_int4(-1, -1, -1, -1);
+    for (int i = 0; i < Q; ++i) {
+      const int jj = __shfl(j, CPI * i + lane % CPI, 64);
+      q.f[i] = *reinterpret_cast<const float4 *>(fk + (long long)jj * NS + ch * EPC);
+      if (HAS_S) q.s[HAS_S ? i : 0] = *reinterpret_cast<const float4 *>(sk + (long long)jj * NS + ch * EPC);
+    }
+    q.st = sgt[idx];
+    if (HAS_S) q.ss = sgs[idx];
+  };
+  // staged chunks -> LDS staging (same wave writes and reads it)
+  auto stage_plane = [&](Regs &q) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      stg[i * 64 + lane] = q.f[i];
+      if (HAS_S) stg[(Q + i) * 64 + lane] = q.s[HAS_S ? i : 0];
     }
   };
-  auto load_rhs = [&](const int4 (&lk)[R], T (&fb)[R][NS], T (&sb)[RS][NS], T (&st)[R], T (&ss)[R]) {
+  auto read_cell = [&](T *fv, T *sv) {
+    const int i = lane / CPI, cc = lane % CPI;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (lk[r].x >= 0) {
-        const long long j = flipped_cell(lk[r].x, FLIP, a.g);
-        load_node_vec<T, NS>(fk + j * NS, fb[r]);
-        if (HAS_S) load_node_vec<T, NS>(sk + j * NS, sb[HAS_S ? r : 0]);
-        st[r] = T(a.sig_t[j]);
-        if (HAS_S) ss[r] = T(a.sig_s[j]);
+    for (int ch = 0; ch < Q; ++ch) {
+      const float4 x = stg[i * 64 + ch * CPI + cc];
+      const T *xe = reinterpret_cast<const T *>(&x);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) fv[ch * EPC + e] = xe[e];
+      if (HAS_S) {
+        const float4 y = stg[(Q + i) * 64 + ch * CPI + cc];
+        const T *ye = reinterpret_cast<const T *>(&y);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) sv[ch * EPC + e] = ye[e];
       }
     }
   };
 
-  int4 lk_cur[R], lk_nxt[R];
-  T f_cur[R][NS], s_cur[RS][NS], st_cur[R], ss_cur[R];
-  load_link(0, lk_cur);
-  load_rhs(lk_cur, f_cur, s_cur, st_cur, ss_cur);
-  if (np > 1) load_link(1, lk_nxt);
+  Regs cur, nxt;
+  cur.lk = make_int4(-1, -1, -1, -1);
+  nxt.lk = make_int4(-1, -1, -1, -1);
+  if (compute) {
+    cur.lk = load_link(0);
+    pin_reg(cur.lk);
+    if (!link_valid(0)) cur.lk.x = -1;
+    load_plane(0, cur);
+    nxt.lk = load_link(min(1, np - 1));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      pin_reg(cur.f[i]);
+      if (HAS_S) pin_reg(cur.s[HAS_S ? i : 0]);
+    }
+    pin_reg(cur.st);
+    if (HAS_S) pin_reg(cur.ss);
+    pin_reg(nxt.lk);
+    if (np < 2 || !link_valid(1)) nxt.lk.x = -1;
+    stage_plane(cur);
+  }
 
-  const T ivn = T((double)(1 << DIM) / a.g.vol);  // N^{-1} = (2^DIM / vol) prod_xi [[2,-1],[-1,2]]
-  for (int pp = 0; pp < np; ++pp) {
-    // the part of the right-hand side that does not depend on the sweep,
-    // formed before the next plane's loads are issued so that f and s of
-    // this plane are dead by then:
-    //   forward  v = N^{-1} f + sigma_s s,   adjoint  v = f + sigma_s N s
-    T v[R][NS];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      T *w = v[r];
-#pragma unroll
-      for (int b = 0; b < NS; ++b) w[b] = f_cur[r][b];
+  // Compute and store waves run separate loops with the same two barriers
+  // per plane (a workgroup barrier counts waves, not program locations).
+  // Inside the compute loop nothing branches around the loads or between
+  // them and their waits, so no load is awaited early.
+  if (compute) {
+    for (int pp = 0; pp < np; ++pp) {
+      const bool mine = cur.lk.x >= 0;
+      // part of the right-hand side independent of the sweep:
+      //   forward  v = N^{-1} f + sigma_s s,   adjoint  v = f + sigma_s N s
+      T v[NS], sv[NS];
+      read_cell(v, sv);
       if (!ADJ) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
 #pragma unroll
           for (int b = 0; b < NS; ++b) {
             if (b & (1 << d)) continue;
-            const T x0 = w[b], x1 = w[b | (1 << d)];
-            w[b] = T(2) * x0 - x1;
-            w[b | (1 << d)] = T(2) * x1 - x0;
+            const T x0 = v[b], x1 = v[b | (1 << d)];
+            v[b] = T(2) * x0 - x1;
+            v[b | (1 << d)] = T(2) * x1 - x0;
           }
         if (HAS_S) {
 #pragma unroll
-          for (int b = 0; b < NS; ++b) w[b] = w[b] * ivn + ss_cur[r] * s_cur[HAS_S ? r : 0][b];
+          for (int b = 0; b < NS; ++b) v[b] = v[b] * ivn + T(cur.ss) * sv[b];
         } else {
 #pragma unroll
-          for (int b = 0; b < NS; ++b) w[b] *= ivn;
+          for (int b = 0; b < NS; ++b) v[b] *= ivn;
         }
       } else if (HAS_S) {
-        T t[NS];
+        mass_shape<T, DIM, false>(sv);
+        const T fs = T(cur.ss) * T(a.g.vol);
 #pragma unroll
-        for (int b = 0; b < NS; ++b) t[b] = s_cur[HAS_S ? r : 0][b];
-        mass_shape<T, DIM, false>(t);
-        const T fs = ss_cur[r] * T(a.g.vol);
-#pragma unroll
-        for (int b = 0; b < NS; ++b) w[b] += fs * t[b];
+        for (int b = 0; b < NS; ++b) v[b] += fs * sv[b];
       }
-    }
-
-    int4 lk_nn[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) lk_nn[r] = make_int4(-1, -1, -1, -1);
-    T f_nxt[R][NS], s_nxt[RS][NS], st_nxt[R], ss_nxt[R];
-    if (pp + 1 < np) load_rhs(lk_nxt, f_nxt, s_nxt, st_nxt, ss_nxt);
-
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (lk_cur[r].x < 0) continue;
-      const int nbp[3] = {lk_cur[r].y, lk_cur[r].z, lk_cur[r].w};
+      // (past the last plane the last one is loaded again, unused)
+      load_plane(min(pp + 1, np - 1), nxt);
+      int4 lk2 = load_link(min(pp + 2, np - 1));
       // neighbour traces from LDS: forward, the upwind neighbour's outflow
-      // face; adjoint, the downwind neighbour's inflow face
+      // face; adjoint, the downwind neighbour's inflow face (cells without
+      // a neighbour, or lanes without a cell, read position 0 and drop it)
+      const int nbp[3] = {cur.lk.y, cur.lk.z, cur.lk.w};
       T tr[DIM][NS / 2];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -354,9 +431,11 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
         const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
         const int q = nbp[d] >= 0 ? nbp[d] : 0;
 #pragma unroll
-        for (int t = 0; t < NS / 2; ++t) tr[d][t] = nbp[d] >= 0 ? lds[insert_bit(t, d, nbit) * maxp + q] : T(0);
+        for (int t = 0; t < NS / 2; ++t) {
+          const T x = lds[insert_bit(t, d, nbit) * maxp + q];  // may be uninitialised: select, not scale
+          tr[d][t] = nbp[d] >= 0 ? x : T(0);
+        }
       }
-      T *w = v[r];
       if (!ADJ) {
         // inflow: 4 c on the own inflow face, -2 c on the opposite face
 #pragma unroll
@@ -365,8 +444,8 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
           const T c4 = T(4) * c[d], c2 = T(2) * c[d];
 #pragma unroll
           for (int t = 0; t < NS / 2; ++t) {
-            w[insert_bit(t, d, own0)] += c4 * tr[d][t];
-            w[insert_bit(t, d, 1 - own0)] -= c2 * tr[d][t];
+            v[insert_bit(t, d, own0)] += c4 * tr[d][t];
+            v[insert_bit(t, d, 1 - own0)] -= c2 * tr[d][t];
           }
         }
       } else {
@@ -380,61 +459,97 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
           for (int e = 0; e < DIM; ++e)
             if (e != d) hs *= T(a.g.h[e]);
 #pragma unroll
-          for (int t = 0; t < NS / 2; ++t) w[insert_bit(t, d, own1)] += hs * tr[d][t];
+          for (int t = 0; t < NS / 2; ++t) v[insert_bit(t, d, own1)] += hs * tr[d][t];
         }
       }
-      oriented_solve<T, DIM, ADJ, FLIP>(w, mc, st_cur[r]);
+      oriented_solve<T, DIM, ADJ, FLIP>(v, mc, T(cur.st));
       if (ADJ) {
-        mass_shape<T, DIM, true>(w);
+        mass_shape<T, DIM, true>(v);
         const T iv = T(1.0 / a.g.vol);
 #pragma unroll
-        for (int b = 0; b < NS; ++b) w[b] *= iv;
+        for (int b = 0; b < NS; ++b) v[b] *= iv;
       }
+      lds_barrier();  // every read of the previous plane is done
+      if (mine) {
+#pragma unroll
+        for (int b = 0; b < NS; ++b) lds[b * maxp + tid] = v[b];
+        jbuf[tid] = (int)flipped_cell(cur.lk.x, FLIP, a.g);
+      }
+      lds_barrier();  // the plane is complete in LDS
+      // the next plane's loads are awaited only now, after both barriers
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        pin_reg(nxt.f[i]);
+        if (HAS_S) pin_reg(nxt.s[HAS_S ? i : 0]);
+      }
+      pin_reg(nxt.st);
+      if (HAS_S) pin_reg(nxt.ss);
+      pin_reg(lk2);
+      stage_plane(nxt);
+      if (pp + 2 >= np || !link_valid(pp + 2)) lk2.x = -1;
+      cur = nxt;
+      nxt.lk = lk2;
     }
-    if (pp + 2 < np) load_link(pp + 2, lk_nn);
-    lds_barrier();  // every read of the previous plane is done
+  } else {
+    // store waves: chunk lane / CPI of cell CPI i + lane % CPI of each
+    // group of 64 cells, whole cells per access
+    const int ch = lane / CPI;
+    for (int pp = 0; pp < np; ++pp) {
+      lds_barrier();
+      lds_barrier();
+      const int p = plane_of(pp);
+      const int n = off[p + 1] - off[p];
+      for (int base = (tid - tc) / 64 * CPI; base < n; base += (kSweepLdsThreads - tc) / 64 * CPI) {
+        const int q = base + lane % CPI;
+        if (q < n) {
+          T w[EPC];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (lk_cur[r].x < 0) continue;
-      const int q = tid + r * TH;  // position in the plane
-#pragma unroll
-      for (int b = 0; b < NS; ++b) lds[b * maxp + q] = v[r][b];
-      const long long j = flipped_cell(lk_cur[r].x, FLIP, a.g);
-      store_node_vec<T, NS>(uk + j * NS, v[r]);
-    }
-    lds_barrier();  // the plane is complete in LDS
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      lk_cur[r] = lk_nxt[r];
-      lk_nxt[r] = lk_nn[r];
-      st_cur[r] = st_nxt[r];
-      ss_cur[r] = ss_nxt[r];
-#pragma unroll
-      for (int b = 0; b < NS; ++b) f_cur[r][b] = f_nxt[r][b];
-    }
-    if (HAS_S) {
-#pragma unroll
-      for (int r = 0; r < RS; ++r)
-#pragma unroll
-        for (int b = 0; b < NS; ++b) s_cur[r][b] = s_nxt[r][b];
+          for (int e = 0; e < EPC; ++e) w[e] = lds[(ch * EPC + e) * maxp + q];
+          *reinterpret_cast<float4 *>(uk + (long long)jbuf[q] * NS + ch * EPC) = *reinterpret_cast<float4 *>(w);
+        }
+      }
     }
   }
 }
 
-template <typename T, int DIM, bool ADJ, bool HAS_S, int R>
-__global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a) {
+template <typename T, int DIM, bool ADJ, bool HAS_S>
+__global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a, int tc) {
   extern __shared__ __align__(16) unsigned char sweep_smem[];
-  T *lds = reinterpret_cast<T *>(sweep_smem);
+  constexpr int NS = 1 << DIM;
+  constexpr int Q = NS * (int)sizeof(T) / 16;
+  float4 *stage = reinterpret_cast<float4 *>(sweep_smem);
+  T *lds = reinterpret_cast<T *>(stage + (size_t)(tc / 64) * (HAS_S ? 2 : 1) * Q * 64);
+  int *jbuf = reinterpret_cast<int *>(lds + (size_t)NS * a.pl.max_plane);
+  // plane offsets in LDS: read with LDS loads, they never make a compute
+  // wave wait on the vector-memory counter
+  int *off = jbuf + a.pl.max_plane;
+  for (int i = threadIdx.x; i <= a.pl.nplanes; i += blockDim.x) off[i] = a.pl.off[i];
+  __syncthreads();
   const int k = blockIdx.x;
   switch (a.ord[k].flip) {
-    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 0>(a, k, lds); break;
-    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 1>(a, k, lds); break;
-    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 2>(a, k, lds); break;
-    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, R, 3>(a, k, lds); break;
-    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 4>(a, k, lds); break;
-    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 5>(a, k, lds); break;
-    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 6>(a, k, lds); break;
-    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, R, 7>(a, k, lds); break;
+    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, 0>(a, k, lds, jbuf, off, stage, tc); break;
+    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, 1>(a, k, lds, jbuf, off, stage, tc); break;
+    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, 2>(a, k, lds, jbuf, off, stage, tc); break;
+    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, 3>(a, k, lds, jbuf, off, stage, tc); break;
+    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 4>(a, k, lds, jbuf, off, stage, tc); break;
+    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 5>(a, k, lds, jbuf, off, stage, tc); break;
+    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 6>(a, k, lds, jbuf, off, stage, tc); break;
+    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 7>(a, k, lds, jbuf, off, stage, tc); break;
+  }
+}
+
+// Cross sections per orientation in cell-list order (coalesced reads in
+// the LDS sweep).
+__global__ void k_sigma_planes(const double *__restrict__ sig_t, const double *__restrict__ sig_s, Planes pl,
+                               Grid g, double *__restrict__ out) {
+  const long long C = g.C;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < 8 * C;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int flip = (int)(t / C);
+    const int idx = (int)(t - flip * C);
+    const long long j = flipped_cell(pl.cells[idx], flip, g);
+    out[t] = sig_t[j];
+    out[8 * C + t] = sig_s[j];
   }
 }
 
@@ -1170,14 +1285,25 @@ int grid_for(long long n, int block = kBlock) {
 }  // namespace
 
 // ------------------------------------------------------------- launchers
-// LDS variant when a thread owns one cell per plane (planes of at most
-// 1024 cells: 3-D grids up to about 36^3).  One 1024-thread workgroup per
-// CU (16 waves); the plane buffer is at most 64 KB.
+// LDS sweep: compute waves cover the largest plane (rounded up to whole
+// waves), the remaining waves of the 1024-thread workgroup store; needs at
+// least one store wave and at most 160 KB of LDS.
 template <typename T, int DIM, bool ADJ, bool HAS_S>
 static bool launch_sweep_lds(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
-  if (a.pl.max_plane > kSweepLdsThreads) return false;
-  const size_t lds = sizeof(T) * (size_t)(1 << DIM) * (size_t)a.pl.max_plane;
-  hipLaunchKernelGGL((k_sweep_lds<T, DIM, ADJ, HAS_S, 1>), dim3(n_ord), dim3(kSweepLdsThreads), lds, st, a);
+  const int tc = (a.pl.max_plane + 63) / 64 * 64;
+  if (tc > kSweepLdsThreads - 64 || !a.sig_pl) return false;
+  // whole-cell accesses are 16-byte vector loads and stores
+  auto aligned = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+  if (!aligned(a.f) || !aligned(a.u) || (a.s && !aligned(a.s))) return false;
+  const size_t stage = (size_t)(tc / 64) * (HAS_S ? 2 : 1) * 64 * sizeof(T) * (1 << DIM);
+  const size_t lds = stage + (sizeof(T) * (size_t)(1 << DIM) + sizeof(int)) * (size_t)a.pl.max_plane +
+                     sizeof(int) * (a.pl.nplanes + 1);
+  if (lds > 160 * 1024) return false;
+  auto fn = k_sweep_lds<T, DIM, ADJ, HAS_S>;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return false;
+  hipLaunchKernelGGL(fn, dim3(n_ord), dim3(kSweepLdsThreads), lds, st, a, tc);
   return true;
 }
 
@@ -1216,6 +1342,11 @@ void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st
   }
 }
 template void launch_sweep<double>(const SweepArgs<double> &, int, bool, hipStream_t);
+
+void launch_sigma_planes(const double *sig_t, const double *sig_s, const Planes &pl, const Grid &g, double *out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_sigma_planes, dim3(grid_for(8 * g.C)), dim3(kBlock), 0, st, sig_t, sig_s, pl, g, out);
+}
 template void launch_sweep<float>(const SweepArgs<float> &, int, bool, hipStream_t);
 
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,

@@ -144,6 +144,7 @@ struct tr_handle {
   std::vector<int> plane_off_host;
   int *d_cells = nullptr, *d_off = nullptr;
   double *sig_t = nullptr, *sig_s = nullptr;
+  double *sig_pl = nullptr;  // [2][8][cells] cross sections per orientation, cell-list order
   tr::HostAngular ang;
   std::vector<DevLevel> lv;
   double *Souter = nullptr;  // canonical S~ at the problem's order on the finest level
@@ -327,6 +328,9 @@ void build(tr_handle *h, const tr_problem *p) {
   }
   h->sig_t = h->upload(h->sig_t_host);
   h->sig_s = h->upload(h->sig_s_host);
+  h->sig_pl = h->alloc<double>(16 * g.C);
+  tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, g, h->sig_pl, nullptr);
+  HIPCHK(hipDeviceSynchronize());
 
   // levels
   h->lv.assign(nlev, DevLevel());
@@ -502,6 +506,7 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   a.u = u;
   a.sig_t = h->sig_t;
   a.sig_s = h->sig_s;
+  a.sig_pl = h->sig_pl;
   a.ord = h->lv[l].ord;
   a.pl = h->pl;
   a.g = h->g;
@@ -951,6 +956,7 @@ int tr_set_sigma(tr_handle *h, const double *sigma_t, const double *sigma_s, tr_
   return translate([&]() {
     HIPCHK(hipMemcpyAsync(h->sig_t, sigma_t, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
     HIPCHK(hipMemcpyAsync(h->sig_s, sigma_s, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
+    tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, h->g, h->sig_pl, S(st));
     return TR_OK;
   });
 }
