@@ -25,7 +25,9 @@
  *
  * Pointers documented as "device" must be device memory of the current HIP
  * device (for instance torch tensors' data_ptr()); the caller owns them and
- * the library never frees or retains them.  Every call is ordered on the
+ * the library never frees or retains them; they must be 16-byte aligned
+ * (vectors are accessed 16 bytes at a time; hipMalloc and torch
+ * allocations are), else the call fails with TR_ERR_ARG.  Every call is ordered on the
  * given stream (tr_stream is a hipStream_t; 0 = the null stream).  Calls
  * that return scalars (solves) synchronise that stream.
  *

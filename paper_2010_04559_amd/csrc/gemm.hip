@@ -6,14 +6,18 @@
 // out [angular][spatial] this is one GEMM  C[A][S] = G[A][A] * U[A][S]  with
 // a very long N = S dimension.
 //
-// Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) computes a BM x BN tile
-// of C; A and B tiles of depth BK are staged through LDS k-major, and each
-// wave issues 16x16x4 MFMAs: lane l supplies A[l%16][k0 + l/16] and
-// B[k0 + l/16][l%16]; accumulator element r of lane l is D[row][l%16] with
-// row = 4 (l/16) + r for the FP32 instruction and row = l/16 + 4 r for the
-// FP64 one (checked on gfx950).
-// Workgroup ids run over M fastest so the workgroups that share a B tile
-// (an N block) are dispatched together and hit it in L2.
+// Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) computes a 64 x 128 tile
+// of C; A and B tiles of depth 16 are staged through LDS k-major, the next
+// depth slice being loaded into registers (16-byte vector loads) while the
+// current one feeds the MFMAs.  Each wave issues 16x16x4 MFMAs: lane l
+// supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; accumulator element r
+// of lane l is D[row][l%16] with row = 4 (l/16) + r for the FP32
+// instruction and row = l/16 + 4 r for the FP64 one (checked on gfx950).
+//
+// Tile order: workgroups are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  Workgroup b runs on XCD b % 8; the tiles are assigned so
+// that every M block of one N block (which all read the same B tile) runs on
+// the same XCD, one after another, and B is fetched from HBM about once.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -46,18 +50,41 @@ struct Mma<float> {
   }
 };
 
+// 16-byte vector of T
+template <typename T>
+struct Vec16 {
+  static constexpr int n = 16 / sizeof(T);
+  T v[n];
+};
+
+constexpr int kXcds = 8;
+
+// C = G * U, optionally C = bias + diag-per-column(colscale) * (G * U) where
+// colscale[c / cell] scales column c (cell = spatial dofs per cell); bias has
+// C's layout.
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
-                                              int M, int N, int K, int mblocks) {
+                                              int M, int N, int K, int mblocks, int nblocks,
+                                              const T *__restrict__ bias, const double *__restrict__ colscale,
+                                              int cell) {
   using acc_t = typename Mma<T>::acc_t;
+  using V = Vec16<T>;
+  constexpr int VN = V::n;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int PAD = 4;
+  constexpr int PAD = 2;
+  // per-thread vectors of the A (BM x BK) and B (BK x BN) slices
+  constexpr int AV = BM * BK / VN / 256, BV = BK * BN / VN / 256;
+  static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
 
-  const int bid = blockIdx.x;
-  const int mb = bid % mblocks, nb = bid / mblocks;
+  // XCD-aware tile order (see the file comment)
+  const int b = blockIdx.x;
+  const int xcd = b % kXcds, slot = b / kXcds;
+  const int mb = slot % mblocks;
+  const int nb = xcd + kXcds * (slot / mblocks);
+  if (nb >= nblocks) return;
   const int m0 = mb * BM;
   const long long n0 = (long long)nb * BN;
   const int tid = threadIdx.x;
@@ -71,34 +98,68 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
     for (int jn = 0; jn < TN; ++jn) acc[i][jn] = acc_t{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // stage A[m0:m0+BM][k0:k0+BK] as As[k][m]
+  V ra[AV], rb[BV];
+  // A slice: vectors along k (A row-major [M][K]); B slice: along n
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int kk = e % BK, i = e / BK;
-      const int gm = m0 + i, gk = k0 + kk;
-      As[kk][i] = (gm < M && gk < K) ? A[(long long)gm * K + gk] : T(0);
+    for (int q = 0; q < AV; ++q) {
+      const int v = tid + 256 * q;
+      const int i = v / (BK / VN), kv = (v % (BK / VN)) * VN;
+      const int gm = m0 + i, gk = k0 + kv;
+      if (gm < M && gk + VN <= K) {
+        ra[q] = *reinterpret_cast<const V *>(A + (long long)gm * K + gk);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) ra[q].v[e] = (gm < M && gk + e < K) ? A[(long long)gm * K + gk + e] : T(0);
+      }
     }
-    // stage B[k0:k0+BK][n0:n0+BN] as Bs[k][n]
 #pragma unroll
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int jn = e % BN, kk = e / BN;
+    for (int q = 0; q < BV; ++q) {
+      const int v = tid + 256 * q;
+      const int kk = v / (BN / VN), nv = (v % (BN / VN)) * VN;
       const int gk = k0 + kk;
-      const long long gn = n0 + jn;
-      Bs[kk][jn] = (gk < K && gn < N) ? B[(long long)gk * N + gn] : T(0);
+      const long long gn = n0 + nv;
+      if (gk < K && gn + VN <= N) {
+        rb[q] = *reinterpret_cast<const V *>(B + (long long)gk * N + gn);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) rb[q].v[e] = (gk < K && gn + e < N) ? B[(long long)gk * N + gn + e] : T(0);
+      }
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < AV; ++q) {
+      const int v = tid + 256 * q;
+      const int i = v / (BK / VN), kv = (v % (BK / VN)) * VN;
+#pragma unroll
+      for (int e = 0; e < VN; ++e) As[kv + e][i] = ra[q].v[e];
+    }
+#pragma unroll
+    for (int q = 0; q < BV; ++q) {
+      const int v = tid + 256 * q;
+      const int kk = v / (BN / VN), nv = (v % (BN / VN)) * VN;
+#pragma unroll
+      for (int e = 0; e < VN; ++e) Bs[kk][nv + e] = rb[q].v[e];
+    }
+  };
+
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    store();
     __syncthreads();
+    if (k0 + BK < K) load(k0 + BK);  // next slice in flight during the MFMAs
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      T a[TM], b[TN];
+      T a[TM], bb[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) a[i] = As[ks + lk][wm0 + i * 16 + lrow];
 #pragma unroll
-      for (int jn = 0; jn < TN; ++jn) b[jn] = Bs[ks + lk][wn0 + jn * 16 + lrow];
+      for (int jn = 0; jn < TN; ++jn) bb[jn] = Bs[ks + lk][wn0 + jn * 16 + lrow];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int jn = 0; jn < TN; ++jn) acc[i][jn] = Mma<T>::op(a[i], b[jn], acc[i][jn]);
+        for (int jn = 0; jn < TN; ++jn) acc[i][jn] = Mma<T>::op(a[i], bb[jn], acc[i][jn]);
     }
     __syncthreads();
   }
@@ -107,10 +168,17 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
     for (int jn = 0; jn < TN; ++jn) {
       const long long gn = n0 + wn0 + jn * 16 + lrow;
+      const T cs = (colscale && gn < N) ? T(colscale[gn / cell]) : T(1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
-        if (gm < M && gn < N) C[(long long)gm * N + gn] = acc[i][jn][r];
+        if (gm < M && gn < N) {
+          const long long o = (long long)gm * N + gn;
+          T y = acc[i][jn][r];
+          if (colscale) y *= cs;
+          if (bias) y += bias[o];
+          C[o] = y;
+        }
       }
     }
 }
@@ -118,14 +186,19 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 }  // namespace
 
 template <typename T>
-void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
+                 const double *colscale, int cell) {
+  constexpr int BM = 64, BN = 128, BK = 16;
   const int mblocks = (M + BM - 1) / BM;
-  const long long nblocks = ((long long)N + BN - 1) / BN;
-  const long long grid = mblocks * nblocks;
-  hipLaunchKernelGGL((k_gemm<T, BM, BN, BK>), dim3((unsigned)grid), dim3(256), 0, st, A, B, C, M, N, K, mblocks);
+  const int nblocks = (int)(((long long)N + BN - 1) / BN);
+  const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
+  const long long grid = (long long)mblocks * nb_pad;
+  hipLaunchKernelGGL((k_gemm<T, BM, BN, BK>), dim3((unsigned)grid), dim3(256), 0, st, A, B, C, M, N, K, mblocks,
+                     nblocks, bias, colscale, cell);
 }
-template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t);
-template void launch_gemm<float>(const float *, const float *, float *, int, int, int, hipStream_t);
+template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t,
+                                  const double *, const double *, int);
+template void launch_gemm<float>(const float *, const float *, float *, int, int, int, hipStream_t, const float *,
+                                 const double *, int);
 
 }  // namespace tr

@@ -108,6 +108,9 @@ void launch_dot_partial(const double *x, const double *y, long long n, double *p
                         hipStream_t st);
 void launch_dot_final(const double *partial, int nblocks, double *out, hipStream_t st);
 void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st);
+// w -= a v, then partial sums of w.z per block (z may be w)
+void launch_axpy_dot(long long n, double a, const double *v, double *w, const double *z, double *partial,
+                     int nblocks, hipStream_t st);
 void launch_scal(long long n, double a, double *x, hipStream_t st);
 void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st);
 template <typename T>
@@ -116,7 +119,10 @@ template <typename Tin, typename Tout>
 void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st);
 
 // C[M][N] = A[M][K] * B[K][N]   (row-major; ld of B and C is N)
+// C[M][N] = A[M][K] B[K][N] on the matrix cores; with bias / colscale:
+// C = bias + colscale[c / cell] * (A B) per column c.
 template <typename T>
-void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st);
+void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
+                 const double *colscale = nullptr, int cell = 8);
 
 }  // namespace tr

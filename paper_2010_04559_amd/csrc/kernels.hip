@@ -1218,49 +1218,111 @@ __global__ void k_grad_s(const double *__restrict__ lam, const double *__restric
 }
 
 // ----------------------------------------------------------------- BLAS-1
+// BLAS-1 on long FP64 vectors: 16-byte accesses (two elements per lane),
+// a grid-stride loop over pairs with the odd tail done by one lane.
+__device__ __forceinline__ double block_sum(double acc) {
+  __shared__ double red[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+  return t;
+}
+
+// partial[block] = sum x.y over the block's share
 __global__ __launch_bounds__(kBlock) void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y,
                                                         long long n, double *__restrict__ partial) {
-  __shared__ double red[kBlock];
-  double acc = 0.0;
-  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
-    acc += x[i] * y[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+  const long long n2 = n / 2;
+  const double2 *x2 = reinterpret_cast<const double2 *>(x);
+  const double2 *y2 = reinterpret_cast<const double2 *>(y);
+  double a0 = 0.0, a1 = 0.0;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n2; i += (long long)gridDim.x * kBlock) {
+    const double2 u = x2[i], v = y2[i];
+    a0 += u.x * v.x;
+    a1 += u.y * v.y;
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) a0 += x[n - 1] * y[n - 1];
+  const double t = block_sum(a0 + a1);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// One modified Gram-Schmidt step fused with the next inner product:
+//   w -= a v;  partial[block] = sum w.z  (z = the next basis vector, or w)
+__global__ __launch_bounds__(kBlock) void k_axpy_dot(long long n, double a, const double *__restrict__ v,
+                                                     double *__restrict__ w, const double *__restrict__ z,
+                                                     double *__restrict__ partial) {
+  const long long n2 = n / 2;
+  const double2 *v2 = reinterpret_cast<const double2 *>(v);
+  double2 *w2 = reinterpret_cast<double2 *>(w);
+  const double2 *z2 = reinterpret_cast<const double2 *>(z);
+  const bool self = z == w;
+  double a0 = 0.0, a1 = 0.0;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n2; i += (long long)gridDim.x * kBlock) {
+    const double2 vv = v2[i];
+    double2 ww = w2[i];
+    ww.x -= a * vv.x;
+    ww.y -= a * vv.y;
+    w2[i] = ww;
+    const double2 zz = self ? ww : z2[i];
+    a0 += ww.x * zz.x;
+    a1 += ww.y * zz.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double t = w[n - 1] - a * v[n - 1];
+    w[n - 1] = t;
+    a0 += t * (self ? t : z[n - 1]);
+  }
+  const double t = block_sum(a0 + a1);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot_final(const double *__restrict__ partial, int nb,
                                                       double *__restrict__ out) {
-  __shared__ double red[kBlock];
   double acc = 0.0;
   for (int i = threadIdx.x; i < nb; i += kBlock) acc += partial[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) *out = t;
 }
 
 __global__ void k_axpy(long long n, double a, const double *__restrict__ x, double *__restrict__ y) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    y[i] += a * x[i];
+  const long long n2 = n / 2;
+  const double2 *x2 = reinterpret_cast<const double2 *>(x);
+  double2 *y2 = reinterpret_cast<double2 *>(y);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    const double2 u = x2[i];
+    double2 v = y2[i];
+    v.x += a * u.x;
+    v.y += a * u.y;
+    y2[i] = v;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) y[n - 1] += a * x[n - 1];
 }
 
 __global__ void k_scal(long long n, double a, double *__restrict__ x) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    x[i] *= a;
+  const long long n2 = n / 2;
+  double2 *x2 = reinterpret_cast<double2 *>(x);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    double2 v = x2[i];
+    v.x *= a;
+    v.y *= a;
+    x2[i] = v;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) x[n - 1] *= a;
 }
 
 __global__ void k_axpby(long long n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
                         double *__restrict__ z) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    z[i] = a * x[i] + b * y[i];
+  const long long n2 = n / 2;
+  const double2 *x2 = reinterpret_cast<const double2 *>(x);
+  const double2 *y2 = reinterpret_cast<const double2 *>(y);
+  double2 *z2 = reinterpret_cast<double2 *>(z);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    const double2 u = x2[i], v = y2[i];
+    z2[i] = double2{a * u.x + b * v.x, a * u.y + b * v.y};
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) z[n - 1] = a * x[n - 1] + b * y[n - 1];
 }
 
 template <typename T>
@@ -1491,14 +1553,25 @@ void launch_dot_partial(const double *x, const double *y, long long n, double *p
 void launch_dot_final(const double *partial, int nblocks, double *out, hipStream_t st) {
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, st, partial, nblocks, out);
 }
+// BLAS-1 launches: 16-byte accesses need 16-byte aligned vectors (every
+// vector the library passes here is a device allocation or a caller buffer
+// checked at the entry point)
+static int blas_grid(long long n) {
+  long long g = (n / 2 + kBlock - 1) / kBlock;
+  return (int)std::max(1LL, std::min(g, 8192LL));
+}
+void launch_axpy_dot(long long n, double a, const double *v, double *w, const double *z, double *partial,
+                     int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_dot, dim3(nblocks), dim3(kBlock), 0, st, n, a, v, w, z, partial);
+}
 void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(kBlock), 0, st, n, a, x, y);
+  hipLaunchKernelGGL(k_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x, y);
 }
 void launch_scal(long long n, double a, double *x, hipStream_t st) {
-  hipLaunchKernelGGL(k_scal, dim3(grid_for(n)), dim3(kBlock), 0, st, n, a, x);
+  hipLaunchKernelGGL(k_scal, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x);
 }
 void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kBlock), 0, st, n, a, x, b, y, z);
+  hipLaunchKernelGGL(k_axpby, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x, b, y, z);
 }
 template <typename T>
 void launch_fill(T *x, long long n, T v, hipStream_t st) {

@@ -152,7 +152,7 @@ struct tr_handle {
   double *dot_partial = nullptr, *dot_out = nullptr;
   double *tmp = nullptr;     // one finest-level FP64 vector
   double *tmp2 = nullptr;
-  int dot_blocks = 1024;
+  int dot_blocks = 2048;
   // Krylov workspace
   int kry_m = 0;
   std::vector<double *> V, Z;
@@ -744,6 +744,16 @@ double dot(tr_handle *h, const double *x, const double *y, long long n, hipStrea
   return v;
 }
 
+// w -= a v; returns w . z (z may be w)
+double axpy_dot(tr_handle *h, double a, const double *v, double *w, const double *z, long long n, hipStream_t st) {
+  tr::launch_axpy_dot(n, a, v, w, z, h->dot_partial, h->dot_blocks, st);
+  tr::launch_dot_final(h->dot_partial, h->dot_blocks, h->dot_out, st);
+  double r = 0;
+  HIPCHK(hipMemcpyAsync(&r, h->dot_out, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return r;
+}
+
 void ensure_krylov(tr_handle *h, int m) {
   if (h->kry_m >= m) return;
   const long long n = h->vec_len(h->top());
@@ -806,13 +816,15 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       precondition(h, o->prec_mode, adj, h->V[j], zj, st);
       apply_A(h, adj, zj, w, st);
       stats->iters++;
+      // modified Gram-Schmidt; each projection is fused with the next
+      // inner product (with V[i+1], and finally with w itself)
       tbegin(h, C_ORTH);
+      double hcur = dot(h, w, h->V[0], n, st);
       for (int i = 0; i <= j; ++i) {
-        const double hij = dot(h, w, h->V[i], n, st);
-        H[(size_t)i * m + j] = hij;
-        tr::launch_axpy(n, -hij, h->V[i], w, st);
+        H[(size_t)i * m + j] = hcur;
+        hcur = axpy_dot(h, hcur, h->V[i], w, i < j ? h->V[i + 1] : w, n, st);
       }
-      const double hn = std::sqrt(dot(h, w, w, n, st));
+      const double hn = std::sqrt(hcur);
       tend(h);
       H[(size_t)(j + 1) * m + j] = hn;
       for (int i = 0; i < j; ++i) {
@@ -904,6 +916,15 @@ int translate(const std::function<int()> &fn) {
   }
 }
 
+// Device vectors are read and written with 16-byte accesses.
+bool misaligned(const void *p) { return p && ((uintptr_t)p & 15) != 0; }
+template <typename... P>
+bool any_misaligned(P... p) {
+  return (misaligned(p) || ...);
+}
+#define TR_CHECK_ALIGNED(...) \
+  if (any_misaligned(__VA_ARGS__)) return fail(TR_ERR_ARG, "device buffers must be 16-byte aligned")
+
 int check_level(tr_handle *h, int level) {
   if (!h) return fail(TR_ERR_ARG, "null handle");
   if (level < 0 || level > h->top()) return fail(TR_ERR_ARG, "level out of range");
@@ -963,6 +984,7 @@ int tr_set_sigma(tr_handle *h, const double *sigma_t, const double *sigma_s, tr_
 
 int tr_rhs(tr_handle *h, const double *q_cell, const tr_inflow *in, double *b, tr_stream st) {
   if (!h || !b) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(b);
   return translate([&]() {
     const int L = h->top();
     DevLevel &D = h->lv[L];
@@ -1036,6 +1058,7 @@ int tr_rhs(tr_handle *h, const double *q_cell, const tr_inflow *in, double *b, t
 
 int tr_detector(tr_handle *h, const int lo[3], const int hi[3], double *w, tr_stream st) {
   if (!h || !lo || !hi || !w) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(w);
   return translate([&]() {
     DevLevel &D = h->lv[h->top()];
     tr::launch_detector(w, D.ipsi, D.A, h->g, lo, hi, S(st));
@@ -1047,6 +1070,7 @@ static int sweep_common(tr_handle *h, int level, int prec, const void *g, void *
   int rc = check_level(h, level);
   if (rc) return rc;
   if (!g || !phi) return fail(TR_ERR_ARG, "null buffer");
+  TR_CHECK_ALIGNED(g, phi);
   if (prec != TR_F64 && prec != TR_F32) return fail(TR_ERR_ARG, "bad precision");
   return translate([&]() {
     DevLevel &D = h->lv[level];
@@ -1081,6 +1105,7 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
   int rc = check_level(h, level);
   if (rc) return rc;
   if (!phi || !s) return fail(TR_ERR_ARG, "null buffer");
+  TR_CHECK_ALIGNED(phi, s);
   if (outer && level != h->top()) return fail(TR_ERR_ARG, "the problem operator lives on the finest level");
   if (prec != TR_F64 && prec != TR_F32) return fail(TR_ERR_ARG, "bad precision");
   if (outer && prec != TR_F64) return fail(TR_ERR_UNSUPPORTED, "the problem operator is FP64 only");
@@ -1104,6 +1129,7 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
 
 int tr_apply(tr_handle *h, const double *x, double *y, tr_stream st) {
   if (!h || !x || !y) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(x, y);
   return translate([&]() {
     apply_A(h, false, x, y, S(st));
     return TR_OK;
@@ -1115,6 +1141,7 @@ int tr_transfer(tr_handle *h, int level, int dir, int prec, const void *in, void
   if (rc) return rc;
   if (level < 1) return fail(TR_ERR_ARG, "transfers act between levels l-1 and l >= 1");
   if (!in || !out) return fail(TR_ERR_ARG, "null buffer");
+  TR_CHECK_ALIGNED(in, out);
   if (dir != TR_RESTRICT && dir != TR_PROLONG) return fail(TR_ERR_ARG, "bad direction");
   return translate([&]() {
     DevLevel &D = h->lv[level], &Dc = h->lv[level - 1];
@@ -1137,6 +1164,7 @@ int tr_transfer(tr_handle *h, int level, int dir, int prec, const void *in, void
 
 int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi, tr_stream st) {
   if (!h || !f || !phi) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(f, phi);
   if (nu < 1) return fail(TR_ERR_ARG, "nu must be >= 1");
   return translate([&]() {
     DevLevel &D = h->lv[0];
@@ -1151,6 +1179,7 @@ int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi
 
 int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, double *z, tr_stream st) {
   if (!h || !r || !z) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(r, z);
   if (prec_mode != TR_PREC_F64 && prec_mode != TR_PREC_MIXED && prec_mode != TR_PREC_SG)
     return fail(TR_ERR_ARG, "bad preconditioner mode");
   return translate([&]() {
@@ -1163,6 +1192,7 @@ int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, doub
 static int solve_common(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o,
                         tr_solve_stats *stats, tr_stream st) {
   if (!h || !b || !x || !o || !stats) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(b, x);
   if (o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->tol > 0))
     return fail(TR_ERR_ARG, "bad solver options");
   if (o->prec_mode != TR_PREC_F64 && o->prec_mode != TR_PREC_MIXED && o->prec_mode != TR_PREC_SG)
@@ -1206,6 +1236,7 @@ int tr_gmres_solve(tr_handle *h, const double *b, double *x, const tr_solve_opts
 int tr_adjoint_grad(tr_handle *h, const double *w, const double *phi, double *lambda, double *grad_t, double *grad_s,
                     const tr_solve_opts *o, tr_solve_stats *stats, tr_stream st) {
   if (!h || !w || !phi || !grad_t || !grad_s || !o || !stats) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(w, phi, lambda, grad_t, grad_s);
   double *lam = lambda;
   int rc = TR_OK;
   rc = translate([&]() {

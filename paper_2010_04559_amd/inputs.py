@@ -61,6 +61,12 @@ class Problem:
     nu_pre: int = 1
     nu_post: int = 1
     nu_coarse: int = 10
+    # Gauss-Seidel octant order on T_0 (octant id = [s_x<0] + 2[s_y<0] +
+    # 4[s_z<0]).  The method leaves it open; the default is the reflected
+    # Gray code, so consecutive octants (and the last and first) differ in
+    # one sign and each octant's sweep starts at a corner next to the
+    # previous one's start.
+    octant_order: Tuple[int, ...] = (0, 1, 3, 2, 6, 7, 5, 4)
     length: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     fd_cells: Optional[np.ndarray] = None
     extras: dict = field(default_factory=dict)

@@ -60,8 +60,10 @@ class Transport:
         p.n_levels = len(prob.mg_orders)
         p.mg_order = self._ord.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         p.nu_pre, p.nu_post, p.nu_coarse = prob.nu_pre, prob.nu_post, prob.nu_coarse
+        if sorted(prob.octant_order) != list(range(8)):
+            raise ValueError("octant_order must be a permutation of 0..7")
         for i in range(8):
-            p.octant_order[i] = i
+            p.octant_order[i] = int(prob.octant_order[i])
         h = ctypes.c_void_p()
         _lib.check(self.lib.tr_setup(ctypes.byref(p), ctypes.byref(h)))
         self.h = h

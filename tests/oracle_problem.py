@@ -31,7 +31,8 @@ class OracleProblem:
         if with_mg:
             full = prob.moments(max(prob.mg_orders))
             self.mg = mgm.AngularMG(self.grid, self.mesh, prob.sigma_t, prob.sigma_s, full,
-                                    prob.mg_orders, prob.nu_pre, prob.nu_post, prob.nu_coarse)
+                                    prob.mg_orders, prob.nu_pre, prob.nu_post, prob.nu_coarse,
+                                    octant_order=prob.octant_order)
 
     def rhs(self):
         p, lv = self.prob, self.outer
