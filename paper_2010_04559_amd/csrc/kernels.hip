@@ -797,11 +797,16 @@ struct GridBarrier {
 };
 
 // Arrival half of the barrier: the block's stores are made visible
-// device-wide and its slot is set to gen.
+// device-wide and its slot is set to gen.  A workgroup barrier does not wait
+// for other waves' stores to complete, so every wave first waits for its
+// own stores (vmcnt(0): acknowledged by the L2); then one thread's release
+// fence writes the L2 back and publishes the arrival.
 __device__ __forceinline__ void grid_arrive(const GridBarrier &gb, unsigned gen) {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters untouched
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this block's stores, device-wide
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(gb.arrive + blockIdx.x, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -838,15 +843,15 @@ __device__ __forceinline__ bool grid_wait(const GridBarrier &gb, unsigned gen) {
 // (octant << 28) | index into the plane-ordered cell list.  A grid-wide
 // barrier separates the steps; the first round of items of the next step
 // is prepared before it.
-template <int DIM, bool ADJ>
-__global__ __launch_bounds__(256) void k_gs_solve(const double *__restrict__ f, double *__restrict__ u,
+template <int DIM, bool ADJ, int TB>
+__global__ __launch_bounds__(TB) void k_gs_solve(const double *__restrict__ f, double *__restrict__ u,
                                                   const double *__restrict__ G, const double *__restrict__ sig_t,
                                                   const double *__restrict__ sig_s,
                                                   const OrdInfo *__restrict__ ord, Planes pl, Grid g,
                                                   const int *__restrict__ step_off, const int *__restrict__ items,
                                                   int nsteps, GridBarrier gb, unsigned gen0) {
   constexpr int NS = 1 << DIM;
-  constexpr int CPB = 256 / NS;  // cells per block per round
+  constexpr int CPB = TB / NS;  // cells per block per round
   __shared__ double G_lds[24 * 24];
   __shared__ OrdInfo ord_lds[24];
   for (int i = threadIdx.x; i < 24 * 24; i += blockDim.x) G_lds[i] = G[i];
@@ -1100,6 +1105,112 @@ __global__ void k_apply(const double *__restrict__ x, const double *__restrict__
       for (int b = 0; b < NS; ++b)
         out[b] = (yk[0][b] + yk[1][b] + yk[2][b] + 3.0 * yk[m][b]) * (1.0 / 6.0) - sig_s[j] * g.vol * sv[b];
       store_node_vec<double, NS>(y + (3LL * q + m) * S + j * NS, out);
+    }
+  }
+}
+
+// Same operator with one lane per Q1 node: the 2^dim lanes of a cell group
+// hold the cell's node values, so every global access of a wave covers
+// whole cells (x, s, y and the neighbours' faces are read and written
+// 64 / 2^dim cells at a time), and the per-axis 2 x 2 operators are lane
+// exchanges along the node bits.
+template <int DIM>
+__device__ __forceinline__ double lane_axis(double v, int b, int d, double m00, double m01, double m10,
+                                            double m11) {
+  const double p = __shfl_xor(v, 1 << d, 64);
+  return ((b >> d) & 1) ? m10 * p + m11 * v : m00 * v + m01 * p;
+}
+
+template <int DIM, bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_apply_lanes(const double *__restrict__ x, const double *__restrict__ s,
+                                                        double *__restrict__ y, const double *__restrict__ sig_t,
+                                                        const double *__restrict__ sig_s,
+                                                        const OrdInfo *__restrict__ ord, const double *__restrict__ w,
+                                                        int P, Grid g) {
+  constexpr int NS = 1 << DIM;
+  constexpr double m6 = 1.0 / 6.0, m3 = 1.0 / 3.0;
+  const long long C = g.C, S = g.S;
+  const int b = threadIdx.x & (NS - 1);
+  const long long groups = (long long)P * C;
+  const long long gstride = (long long)gridDim.x * (kBlock / NS);
+  // whole waves iterate together (the exchanges need every lane); lanes of
+  // a group past the end work on group 0 and store nothing
+  const long long gbase = blockIdx.x * (long long)(kBlock / NS) + threadIdx.x / NS;
+  const long long wave_first = gbase - (threadIdx.x & 63) / NS;
+  for (long long t0 = wave_first; t0 < groups; t0 += gstride) {
+    const long long t = t0 + (threadIdx.x & 63) / NS;
+    const bool active = t < groups;
+    const long long tt = active ? t : 0;
+    const int q = (int)(tt / C);
+    const long long j = tt - (long long)q * C;
+    const int ix[3] = {(int)(j % g.n[0]), (int)((j / g.n[0]) % g.n[1]), (int)(j / ((long long)g.n[0] * g.n[1]))};
+    const double st = sig_t[j], ss = sig_s[j];
+    double xv[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) xv[m] = x[(3LL * q + m) * S + j * NS + b];
+    // neighbour node values of the three patch dofs, one face per axis
+    double xn[DIM][3];
+    bool has[DIM];
+    int flip[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) flip[k] = ord[3 * q + k].flip;
+    const int fl0 = flip[0];  // the three ordinates of a patch share the octant
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int fl = (fl0 >> d) & 1;
+      const int step = (fl ? 1 : -1) * (ADJ ? -1 : 1);
+      has[d] = step > 0 ? (ix[d] < g.n[d] - 1) : (ix[d] > 0);
+      int nx[3] = {ix[0], ix[1], ix[2]};
+      if (has[d]) nx[d] += step;
+      const long long jn = nx[0] + (long long)g.n[0] * (nx[1] + (long long)g.n[1] * nx[2]);
+      const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
+      const int bn = (b & ~(1 << d)) | (nbit << d);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) xn[d][m] = x[(3LL * q + m) * S + jn * NS + bn];
+    }
+    double yk[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const OrdInfo &o = ord[3 * q + k];
+      const double wk = ADJ ? w[3 * q + k] : 1.0;
+      const double u = wk * (xv[0] + xv[1] + xv[2] + 3.0 * xv[k]) * m6;
+      // removal sigma_t N u
+      double r = u;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) r = lane_axis<DIM>(r, b, d, m3, m6, m6, m3);
+      r *= st * g.vol;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int fl = (fl0 >> d) & 1;
+        // streaming |Omega_d| T1_d (x) N on the other axes
+        double tv = (fl != (ADJ ? 1 : 0)) ? lane_axis<DIM>(u, b, d, 0.5, -0.5, 0.5, 0.5)
+                                          : lane_axis<DIM>(u, b, d, 0.5, 0.5, -0.5, 0.5);
+        double hs = 1.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+          if (e != d) {
+            tv = lane_axis<DIM>(tv, b, e, m3, m6, m6, m3);
+            hs *= g.h[e];
+          }
+        r += o.a[d] * hs * tv;
+        // minus the coupling to the upwind (adjoint: downwind) neighbour's
+        // face, applied on the own face
+        double tr = has[d] ? wk * (xn[d][0] + xn[d][1] + xn[d][2] + 3.0 * xn[d][k]) * m6 : 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+          if (e != d) tr = lane_axis<DIM>(tr, b, e, m3, m6, m6, m3);
+        const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
+        if (((b >> d) & 1) == 1 - nbit) r -= o.a[d] * hs * tr;
+      }
+      yk[k] = (ADJ ? 1.0 : w[3 * q + k]) * r;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      double sv = s[(3LL * q + m) * S + j * NS + b];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sv = lane_axis<DIM>(sv, b, d, m3, m6, m6, m3);
+      const double out = (yk[0] + yk[1] + yk[2] + 3.0 * yk[m]) * m6 - ss * g.vol * sv;
+      if (active) y[(3LL * q + m) * S + j * NS + b] = out;
     }
   }
 }
@@ -1411,28 +1522,35 @@ void launch_sigma_planes(const double *sig_t, const double *sig_s, const Planes 
 }
 template void launch_sweep<float>(const SweepArgs<float> &, int, bool, hipStream_t);
 
+// Threads per workgroup of the coarse Gauss-Seidel launch (cells per
+// workgroup and round = threads / 2^dim).
+static int g_gs_block_threads = 256;
+static int gs_block_threads() { return g_gs_block_threads; }
+
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                       const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
                       int *bar_err, int max_blocks, unsigned gen0, hipStream_t st) {
   launch_fill<double>(u, 24LL * g.S, 0.0, st);
+  const int tb = gs_block_threads();
   void *fn = nullptr;
-  if (g.dim == 3)
-    fn = adjoint ? (void *)k_gs_solve<3, true> : (void *)k_gs_solve<3, false>;
-  else
-    fn = adjoint ? (void *)k_gs_solve<2, true> : (void *)k_gs_solve<2, false>;
+#define TR_GS_FN(TB)                                                                  \
+  (g.dim == 3 ? (adjoint ? (void *)k_gs_solve<3, true, TB> : (void *)k_gs_solve<3, false, TB>) \
+              : (adjoint ? (void *)k_gs_solve<2, true, TB> : (void *)k_gs_solve<2, false, TB>))
+  fn = tb == 1024 ? TR_GS_FN(1024) : tb == 512 ? TR_GS_FN(512) : TR_GS_FN(256);
+#undef TR_GS_FN
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1)
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tb, 0) != hipSuccess || per_cu < 1)
     throw std::runtime_error("cannot size the cooperative Gauss-Seidel launch");
-  const int cpb = 256 / g.ns;
+  const int cpb = tb / g.ns;
   int blocks = (max_items + cpb - 1) / cpb;
   blocks = std::max(1, std::min(std::min(blocks, ncu * per_cu), max_blocks));
   GridBarrier gb{bar_arrive, bar_release, bar_err};
   void *args[] = {(void *)&f,    (void *)&u,     (void *)&G,        (void *)&sig_t, (void *)&sig_s,
                   (void *)&ord,  (void *)&pl,    (void *)&g,        (void *)&step_off, (void *)&items,
                   (void *)&nsteps, (void *)&gb, (void *)&gen0};
-  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st) != hipSuccess)
+  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(tb), args, 0, st) != hipSuccess)
     throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
 }
 
@@ -1487,17 +1605,21 @@ TR_INST_PROLONG(float, double)
 
 void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
                   const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
-  const int grid = grid_for((long long)P * g.C);
+  // one lane per node, kBlock / 2^dim cells per workgroup
+  const long long cells = (long long)P * g.C;
+  const int grid = (int)std::max(1LL, std::min((cells * g.ns + kBlock - 1) / kBlock, 16384LL));
   if (g.dim == 3) {
     if (adjoint)
-      hipLaunchKernelGGL((k_apply<3, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+      hipLaunchKernelGGL((k_apply_lanes<3, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
     else
-      hipLaunchKernelGGL((k_apply<3, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+      hipLaunchKernelGGL((k_apply_lanes<3, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P,
+                         g);
   } else {
     if (adjoint)
-      hipLaunchKernelGGL((k_apply<2, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+      hipLaunchKernelGGL((k_apply_lanes<2, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
     else
-      hipLaunchKernelGGL((k_apply<2, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+      hipLaunchKernelGGL((k_apply_lanes<2, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P,
+                         g);
   }
 }
 
