@@ -7,9 +7,10 @@
 // a very long N = S dimension.
 //
 // Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) computes a 64 x 128 tile
-// of C; A and B tiles of depth 16 are staged through LDS k-major, the next
-// depth slice being loaded into registers (16-byte vector loads) while the
-// current one feeds the MFMAs.  Each wave issues 16x16x4 MFMAs: lane l
+// of C; A and B slices of depth 16 are staged through two LDS buffers
+// k-major, the next slice being loaded into registers (16-byte vector loads)
+// and stored into the idle buffer while the current one feeds the MFMAs
+// (one workgroup barrier per slice).  Each wave issues 16x16x4 MFMAs: lane l
 // supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; accumulator element r
 // of lane l is D[row][l%16] with row = 4 (l/16) + r for the FP32
 // instruction and row = l/16 + 4 r for the FP64 one (checked on gfx950).
@@ -76,8 +77,8 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
   // per-thread vectors of the A (BM x BK) and B (BK x BN) slices
   constexpr int AV = BM * BK / VN / 256, BV = BK * BN / VN / 256;
   static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
 
   // XCD-aware tile order (see the file comment)
   const int b = blockIdx.x;
@@ -127,41 +128,47 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
       }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < AV; ++q) {
       const int v = tid + 256 * q;
       const int i = v / (BK / VN), kv = (v % (BK / VN)) * VN;
 #pragma unroll
-      for (int e = 0; e < VN; ++e) As[kv + e][i] = ra[q].v[e];
+      for (int e = 0; e < VN; ++e) As[buf][kv + e][i] = ra[q].v[e];
     }
 #pragma unroll
     for (int q = 0; q < BV; ++q) {
       const int v = tid + 256 * q;
       const int kk = v / (BN / VN), nv = (v % (BN / VN)) * VN;
 #pragma unroll
-      for (int e = 0; e < VN; ++e) Bs[kk][nv + e] = rb[q].v[e];
+      for (int e = 0; e < VN; ++e) Bs[buf][kk][nv + e] = rb[q].v[e];
     }
   };
 
+  // double-buffered: slice k+1 is loaded into registers during the MFMAs on
+  // slice k and stored into the other LDS buffer (last read one slice ago)
   load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
-    store();
-    __syncthreads();
-    if (k0 + BK < K) load(k0 + BK);  // next slice in flight during the MFMAs
+    const bool more = k0 + BK < K;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       T a[TM], bb[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[ks + lk][wm0 + i * 16 + lrow];
+      for (int i = 0; i < TM; ++i) a[i] = As[buf][ks + lk][wm0 + i * 16 + lrow];
 #pragma unroll
-      for (int jn = 0; jn < TN; ++jn) bb[jn] = Bs[ks + lk][wn0 + jn * 16 + lrow];
+      for (int jn = 0; jn < TN; ++jn) bb[jn] = Bs[buf][ks + lk][wn0 + jn * 16 + lrow];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int jn = 0; jn < TN; ++jn) acc[i][jn] = Mma<T>::op(a[i], bb[jn], acc[i][jn]);
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)

@@ -73,6 +73,12 @@ void launch_coarse_gs(const double *f, double *u, const double *G, const double 
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
                     hipStream_t st);
+// The same conversion followed by the inverse cell mass matrix per ordinate:
+// a forward right-hand side in prepared form f~ = N^{-1} f (the form every
+// forward sweep, forward coarse solve and forward restriction works in).
+template <typename Tin, typename Tout>
+void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
+                         hipStream_t st);
 
 // Restriction to level l-1: fc[p] = sum_children R_c (sigma_s N (s_new - s_prev))_c
 // (apply_sn = 0: plain fc[p] = sum_children R_c in_c).
@@ -112,6 +118,8 @@ void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t 
 void launch_axpy_dot(long long n, double a, const double *v, double *w, const double *z, double *partial,
                      int nblocks, hipStream_t st);
 void launch_scal(long long n, double a, double *x, hipStream_t st);
+// y += sum_q c[q] x[q] (host arrays of k device vectors and coefficients)
+void launch_multi_axpy(long long n, int k, const double *const *x, const double *c, double *y, hipStream_t st);
 void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st);
 template <typename T>
 void launch_fill(T *x, long long n, T v, hipStream_t st);

@@ -21,6 +21,7 @@ namespace tr {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxMulti = 16;
 
 __device__ __forceinline__ int insert_bit(int t, int d, int bit) {
   return (t & ((1 << d) - 1)) | (bit << d) | ((t >> d) << (d + 1));
@@ -52,7 +53,8 @@ __device__ __forceinline__ long long cell_index(const int ix[3], const Grid &g) 
 
 // Right-hand side of one ordinate's cell system, in the form solved by
 // spectral_solve, from the cell's preloaded f and (optional) s values:
-//   forward  v = N^{-1} f + sigma_s s + upwind inflow (scaled by N^{-1}),
+//   forward  v = f~ + sigma_s s + upwind inflow (scaled by N^{-1}), with the
+//            prepared right-hand side f~ = N^{-1} f,
 //   adjoint  v = f + sigma_s N s + downwind coupling.
 template <typename T, int DIM, bool ADJ, int FLIP>
 __device__ __forceinline__ void cell_rhs(T *v, const T *fv, const T *sv, bool has_s, const T *uk, const int ci[3],
@@ -80,10 +82,6 @@ __device__ __forceinline__ void cell_rhs(T *v, const T *fv, const T *sv, bool ha
 #pragma unroll
   for (int b = 0; b < NS; ++b) v[b] = fv[b];
   if (!ADJ) {
-    mass_shape<T, DIM, true>(v);
-    const T iv = T(1.0 / g.vol);
-#pragma unroll
-    for (int b = 0; b < NS; ++b) v[b] *= iv;
     if (has_s) {
 #pragma unroll
       for (int b = 0; b < NS; ++b) v[b] += T(sigs) * sv[b];
@@ -306,8 +304,6 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
   const bool compute = tid < tc;
   // this wave's staging area: Q KB for f, then Q KB for s
   float4 *stg = stage + (size_t)(tid >> 6) * (HAS_S ? 2 : 1) * Q * 64;
-  const T ivn = T((double)(1 << DIM) / a.g.vol);  // N^{-1} = (2^DIM / vol) prod_xi [[2,-1],[-1,2]]
-
   auto plane_of = [&](int pp) { return ADJ ? np - 1 - pp : pp; };
   // Every global load below is unconditional, from an address clamped to
   // valid memory, and its validity is applied only after the wait: a load
@@ -390,28 +386,15 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
   if (compute) {
     for (int pp = 0; pp < np; ++pp) {
       const bool mine = cur.lk.x >= 0;
-      // part of the right-hand side independent of the sweep:
-      //   forward  v = N^{-1} f + sigma_s s,   adjoint  v = f + sigma_s N s
+      // part of the right-hand side independent of the sweep: forward, the
+      // prepared right-hand side itself (f~ = N^{-1} f, or f~ + sigma_s G u
+      // formed by the scatter GEMM); adjoint  v = f + sigma_s N s
       T v[NS], sv[NS];
       read_cell(v, sv);
-      if (!ADJ) {
+      if (!ADJ && HAS_S) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d)
-#pragma unroll
-          for (int b = 0; b < NS; ++b) {
-            if (b & (1 << d)) continue;
-            const T x0 = v[b], x1 = v[b | (1 << d)];
-            v[b] = T(2) * x0 - x1;
-            v[b | (1 << d)] = T(2) * x1 - x0;
-          }
-        if (HAS_S) {
-#pragma unroll
-          for (int b = 0; b < NS; ++b) v[b] = v[b] * ivn + T(cur.ss) * sv[b];
-        } else {
-#pragma unroll
-          for (int b = 0; b < NS; ++b) v[b] *= ivn;
-        }
-      } else if (HAS_S) {
+        for (int b = 0; b < NS; ++b) v[b] += T(cur.ss) * sv[b];
+      } else if (ADJ && HAS_S) {
         mass_shape<T, DIM, false>(sv);
         const T fs = T(cur.ss) * T(a.g.vol);
 #pragma unroll
@@ -713,7 +696,7 @@ __device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restri
     cc[m][1] = o.c[1];
     cc[m][2] = o.c[2];
     if (!ADJ) {
-      v[m] = lane_mass<DIM>(q.fv[m], NS - 1, true) * (1.0 / g.vol) + ss * acc[m];
+      v[m] = q.fv[m] + ss * acc[m];  // prepared right-hand side f~ = N^{-1} f
     } else {
       v[m] = q.fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false);
     }
@@ -909,6 +892,40 @@ __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, in
       double y = 2.0 * x[k] - sum * (1.0 / 3.0);   // Psi^{-1} = 2 I - J / 3
       if (post) y *= post[3 * p + k];
       out[(3LL * p + k) * S + s] = (Tout)y;
+    }
+  }
+}
+
+// Conversion of a forward right-hand side into prepared ordinate form:
+// the ordinate conversion above, then the inverse cell mass matrix applied
+// per ordinate (f~ = N^{-1} f).  One thread per (patch, cell).
+template <typename Tin, typename Tout, int DIM>
+__global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ out, int P, Grid g,
+                               const double *__restrict__ pre, const double *__restrict__ post) {
+  constexpr int NS = 1 << DIM;
+  const long long C = g.C, S = g.S;
+  const long long total = (long long)P * C;
+  const double iv = 1.0 / g.vol;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(t / C);
+    const long long j = t - (long long)p * C;
+    double x[3][NS];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double sc = pre ? pre[3 * p + m] : 1.0;
+#pragma unroll
+      for (int b = 0; b < NS; ++b) x[m][b] = (double)in[(3LL * p + m) * S + j * NS + b] * sc;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double sc = post ? post[3 * p + k] : 1.0;
+      double y[NS];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) y[b] = (2.0 * x[k][b] - (x[0][b] + x[1][b] + x[2][b]) * (1.0 / 3.0)) * sc;
+      mass_shape<double, DIM, true>(y);
+#pragma unroll
+      for (int b = 0; b < NS; ++b) out[(3LL * p + k) * S + j * NS + b] = (Tout)(y[b] * iv);
     }
   }
 }
@@ -1411,6 +1428,29 @@ __global__ void k_axpy(long long n, double a, const double *__restrict__ x, doub
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) y[n - 1] += a * x[n - 1];
 }
 
+// y += sum_i c_i x_i for up to kMaxMulti vectors in one pass
+struct MultiAxpyArgs {
+  const double *x[kMaxMulti];
+  double c[kMaxMulti];
+  int k;
+};
+
+__global__ void k_multi_axpy(long long n, MultiAxpyArgs a, double *__restrict__ y) {
+  const long long n2 = n / 2;
+  double2 *y2 = reinterpret_cast<double2 *>(y);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    double2 v = y2[i];
+    for (int q = 0; q < a.k; ++q) {
+      const double2 u = reinterpret_cast<const double2 *>(a.x[q])[i];
+      v.x += a.c[q] * u.x;
+      v.y += a.c[q] * u.y;
+    }
+    y2[i] = v;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+    for (int q = 0; q < a.k; ++q) y[n - 1] += a.c[q] * a.x[q][n - 1];
+}
+
 __global__ void k_scal(long long n, double a, double *__restrict__ x) {
   const long long n2 = n / 2;
   double2 *x2 = reinterpret_cast<double2 *>(x);
@@ -1560,6 +1600,21 @@ void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *
   hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for((long long)P * S)), dim3(kBlock), 0, st, in, out, P, S,
                      pre, post);
 }
+template <typename Tin, typename Tout>
+void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
+                         hipStream_t st) {
+  const int grid = grid_for((long long)P * g.C);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post);
+  else
+    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post);
+}
+template void launch_convert_minv<double, double>(const double *, double *, int, const Grid &, const double *,
+                                                  const double *, hipStream_t);
+template void launch_convert_minv<double, float>(const double *, float *, int, const Grid &, const double *,
+                                                 const double *, hipStream_t);
+template void launch_convert_minv<float, float>(const float *, float *, int, const Grid &, const double *,
+                                                const double *, hipStream_t);
 template void launch_convert<double, double>(const double *, double *, int, long long, const double *,
                                              const double *, hipStream_t);
 template void launch_convert<double, float>(const double *, float *, int, long long, const double *, const double *,
@@ -1688,6 +1743,17 @@ void launch_axpy_dot(long long n, double a, const double *v, double *w, const do
 }
 void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x, y);
+}
+void launch_multi_axpy(long long n, int k, const double *const *x, const double *c, double *y, hipStream_t st) {
+  for (int q0 = 0; q0 < k; q0 += kMaxMulti) {
+    MultiAxpyArgs a{};
+    a.k = std::min(kMaxMulti, k - q0);
+    for (int q = 0; q < a.k; ++q) {
+      a.x[q] = x[q0 + q];
+      a.c[q] = c[q0 + q];
+    }
+    hipLaunchKernelGGL(k_multi_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, y);
+  }
 }
 void launch_scal(long long n, double a, double *x, hipStream_t st) {
   hipLaunchKernelGGL(k_scal, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x);

@@ -517,10 +517,13 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   tend(h);
 }
 
+// y = G x, or y = bias + sigma_s (G x) per cell with scale_sn (bias may be
+// null): the forward V-cycle's prepared right-hand sides.
 template <typename T>
-void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st) {
+void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st, bool scale_sn = false,
+             const T *bias = nullptr) {
   tbegin(h, C_SCATTER);
-  tr::launch_gemm<T>(G, x, y, A, (int)h->g.S, A, st);
+  tr::launch_gemm<T>(G, x, y, A, (int)h->g.S, A, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns);
   tend(h);
 }
 
@@ -641,25 +644,39 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   T *f = LevelBuf<T>::f(D), *u = LevelBuf<T>::u(D);
   T *sa = LevelBuf<T>::sa(D), *sb = LevelBuf<T>::sb(D);
   const T *G = LevelBuf<T>::G(D, adj);
+  DevLevel &Dc = h->lv[l - 1];
+  // Forward: f holds the prepared right-hand side f~ = N^{-1} f, every
+  // sweep reads one prepared vector (f~ itself, or f~ + sigma_s G u formed
+  // by the GEMM epilogue) and the restricted residual is R sigma_s G du
+  // (N commutes with the angular operators).  Adjoint: weak-form f, the
+  // sweep forms f + sigma_s N s itself.
   // pre-smoothing (source iteration from zero)
   do_sweep<T>(h, l, f, nullptr, u, adj, st);
   T *s_prev = nullptr;
   for (int it = 1; it < nu_pre; ++it) {
-    do_gemm<T>(h, G, u, sa, D.A, st);
-    do_sweep<T>(h, l, f, sa, u, adj, st);
+    if (!adj) {
+      do_gemm<T>(h, G, u, sa, D.A, st, true, f);
+      do_sweep<T>(h, l, sa, nullptr, u, adj, st);
+    } else {
+      do_gemm<T>(h, G, u, sa, D.A, st);
+      do_sweep<T>(h, l, f, sa, u, adj, st);
+    }
     s_prev = sa;
     std::swap(sa, sb);
   }
-  // residual S (u - u_prev), restricted to level l-1
-  do_gemm<T>(h, G, u, sa, D.A, st);
-  DevLevel &Dc = h->lv[l - 1];
+  // residual S (u - u_prev), restricted to level l-1 (forward: both terms
+  // carry the same f~, which cancels)
+  if (!adj)
+    do_gemm<T>(h, G, u, sa, D.A, st, true, s_prev ? f : nullptr);
+  else
+    do_gemm<T>(h, G, u, sa, D.A, st);
   tbegin(h, C_TRANSFER);
   if (l - 1 == 0)
     tr::launch_restrict<T, double>(sa, s_prev, Dc.f64, adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P, h->sig_s,
-                                   true, h->g, st);
+                                   adj, h->g, st);
   else
     tr::launch_restrict<T, T>(sa, s_prev, LevelBuf<T>::f(Dc), adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P,
-                              h->sig_s, true, h->g, st);
+                              h->sig_s, adj, h->g, st);
   tend(h);
   if (l - 1 == 0)
     do_coarse(h, Dc.f64, Dc.u64, h->prob.nu_coarse, adj, st);
@@ -672,21 +689,37 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
     tr::launch_prolong<T, T>(LevelBuf<T>::u(Dc), u, adj ? D.Pa : D.Pu, D.owner, D.P, h->g.S, true, st);
   tend(h);
   for (int it = 0; it < nu_post; ++it) {
-    do_gemm<T>(h, G, u, sa, D.A, st);
-    do_sweep<T>(h, l, f, sa, u, adj, st);
+    if (!adj) {
+      do_gemm<T>(h, G, u, sa, D.A, st, true, f);
+      do_sweep<T>(h, l, sa, nullptr, u, adj, st);
+    } else {
+      do_gemm<T>(h, G, u, sa, D.A, st);
+      do_sweep<T>(h, l, f, sa, u, adj, st);
+    }
   }
 }
 
 // z = M^{-1} r (canonical FP64 in and out)
+// Right-hand side of a preconditioner or sweep call in ordinate form:
+// prepared (N^{-1} applied) for the forward direction, weak form for the
+// adjoint.
+template <typename Tin, typename Tout>
+void convert_in(tr_handle *h, int level, bool adj, const Tin *r, Tout *f, hipStream_t st) {
+  DevLevel &D = h->lv[level];
+  if (adj)
+    tr::launch_convert<Tin, Tout>(r, f, D.P, h->g.S, nullptr, nullptr, st);
+  else
+    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st);
+}
+
 void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st) {
   const int L = h->top();
   h->n_precond++;
   DevLevel &D = h->lv[L];
-  const double *pre_in = nullptr, *post_in = adj ? nullptr : D.winv;
   const double *pre_out = adj ? D.winv : nullptr, *post_out = nullptr;
   if (mode == TR_PREC_SG) {
     tbegin(h, C_OTHER);
-    tr::launch_convert<double, double>(r, D.f64, D.P, h->g.S, pre_in, post_in, st);
+    convert_in<double, double>(h, L, adj, r, D.f64, st);
     tend(h);
     do_sweep<double>(h, L, D.f64, nullptr, D.u64, adj, st);
     tbegin(h, C_OTHER);
@@ -696,7 +729,7 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
   }
   if (L == 0) {
     tbegin(h, C_OTHER);
-    tr::launch_convert<double, double>(r, D.f64, D.P, h->g.S, pre_in, post_in, st);
+    convert_in<double, double>(h, L, adj, r, D.f64, st);
     tend(h);
     do_coarse(h, D.f64, D.u64, h->prob.nu_coarse, adj, st);
     tbegin(h, C_OTHER);
@@ -707,7 +740,7 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
   if (mode == TR_PREC_MIXED) {
     ensure_mixed(h);
     tbegin(h, C_OTHER);
-    tr::launch_convert<double, float>(r, D.f32, D.P, h->g.S, pre_in, post_in, st);
+    convert_in<double, float>(h, L, adj, r, D.f32, st);
     tend(h);
     mg_level<float>(h, L, adj, st);
     tbegin(h, C_OTHER);
@@ -715,7 +748,7 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
     tend(h);
   } else {
     tbegin(h, C_OTHER);
-    tr::launch_convert<double, double>(r, D.f64, D.P, h->g.S, pre_in, post_in, st);
+    convert_in<double, double>(h, L, adj, r, D.f64, st);
     tend(h);
     mg_level<double>(h, L, adj, st);
     tbegin(h, C_OTHER);
@@ -855,10 +888,10 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
     }
     tbegin(h, C_ORTH);
     if (keepZ) {
-      for (int i = 0; i < k; ++i) tr::launch_axpy(n, y[i], h->Z[i], x, st);
+      tr::launch_multi_axpy(n, k, h->Z.data(), y.data(), x, st);
     } else {
       tr::launch_fill<double>(w, n, 0.0, st);
-      for (int i = 0; i < k; ++i) tr::launch_axpy(n, y[i], h->V[i], w, st);
+      tr::launch_multi_axpy(n, k, h->V.data(), y.data(), w, st);
     }
     tend(h);
     if (!keepZ) {
@@ -1074,17 +1107,16 @@ static int sweep_common(tr_handle *h, int level, int prec, const void *g, void *
   if (prec != TR_F64 && prec != TR_F32) return fail(TR_ERR_ARG, "bad precision");
   return translate([&]() {
     DevLevel &D = h->lv[level];
-    const double *pre_in = nullptr, *post_in = adj ? nullptr : D.winv;
     const double *pre_out = adj ? D.winv : nullptr;
     if (prec == TR_F64) {
-      tr::launch_convert<double, double>((const double *)g, D.f64, D.P, h->g.S, pre_in, post_in, S(st));
+      convert_in<double, double>(h, level, adj, (const double *)g, D.f64, S(st));
       do_sweep<double>(h, level, D.f64, nullptr, D.u64, adj, S(st));
       tr::launch_convert<double, double>(D.u64, (double *)phi, D.P, h->g.S, pre_out, nullptr, S(st));
     } else {
       const size_t bytes = (size_t)h->vec_len(level) * sizeof(float);
       TmpBuf tf(bytes), tu(bytes);
       float *f = tf.as<float>(), *u = tu.as<float>();
-      tr::launch_convert<float, float>((const float *)g, f, D.P, h->g.S, pre_in, post_in, S(st));
+      convert_in<float, float>(h, level, adj, (const float *)g, f, S(st));
       do_sweep<float>(h, level, f, nullptr, u, adj, S(st));
       tr::launch_convert<float, float>(u, (float *)phi, D.P, h->g.S, pre_out, nullptr, S(st));
       HIPCHK(hipStreamSynchronize(S(st)));
@@ -1169,7 +1201,7 @@ int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi
   return translate([&]() {
     DevLevel &D = h->lv[0];
     const bool adj = adjoint != 0;
-    tr::launch_convert<double, double>(f, D.f64, D.P, h->g.S, nullptr, adj ? nullptr : D.winv, S(st));
+    convert_in<double, double>(h, 0, adj, f, D.f64, S(st));
     do_coarse(h, D.f64, D.u64, nu, adj, S(st));
     tr::launch_convert<double, double>(D.u64, phi, D.P, h->g.S, adj ? D.winv : nullptr, nullptr, S(st));
     check_barrier(h, S(st));
