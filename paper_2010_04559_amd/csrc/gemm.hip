@@ -6,8 +6,8 @@
 // out [angular][spatial] this is one GEMM  C[A][S] = G[A][A] * U[A][S]  with
 // a very long N = S dimension.
 //
-// Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) computes a 64 x 128 tile
-// of C; A and B slices of depth 16 are staged through two LDS buffers
+// Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) computes a BM x BN tile
+// of C; A and B slices of depth BK are staged through two LDS buffers
 // k-major, the next slice being loaded into registers (16-byte vector loads)
 // and stored into the idle buffer while the current one feeds the MFMAs
 // (one workgroup barrier per slice).  Each wave issues 16x16x4 MFMAs: lane l
@@ -63,8 +63,9 @@ constexpr int kXcds = 8;
 // C = G * U, optionally C = bias + diag-per-column(colscale) * (G * U) where
 // colscale[c / cell] scales column c (cell = spatial dofs per cell); bias has
 // C's layout.
-template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
+template <typename T, int BM, int BN, int BK, bool DB, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm(
+    const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
                                               int M, int N, int K, int mblocks, int nblocks,
                                               const T *__restrict__ bias, const double *__restrict__ colscale,
                                               int cell) {
@@ -75,10 +76,11 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int PAD = 2;
   // per-thread vectors of the A (BM x BK) and B (BK x BN) slices
-  constexpr int AV = BM * BK / VN / 256, BV = BK * BN / VN / 256;
-  static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
+  constexpr int AVT = BM * BK / VN, BVT = BK * BN / VN;  // vectors per slice
+  constexpr int AV = (AVT + 255) / 256, BV = (BVT + 255) / 256;
+  constexpr int NB = DB ? 2 : 1;
+  __shared__ T As[NB][BK][BM + PAD];
+  __shared__ T Bs[NB][BK][BN + PAD];
 
   // XCD-aware tile order (see the file comment)
   const int b = blockIdx.x;
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
     for (int q = 0; q < AV; ++q) {
       const int v = tid + 256 * q;
+      if (AVT % 256 != 0 && v >= AVT) break;
       const int i = v / (BK / VN), kv = (v % (BK / VN)) * VN;
       const int gm = m0 + i, gk = k0 + kv;
       if (gm < M && gk + VN <= K) {
@@ -117,6 +120,7 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
     for (int q = 0; q < BV; ++q) {
       const int v = tid + 256 * q;
+      if (BVT % 256 != 0 && v >= BVT) break;
       const int kk = v / (BN / VN), nv = (v % (BN / VN)) * VN;
       const int gk = k0 + kk;
       const long long gn = n0 + nv;
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
     for (int q = 0; q < AV; ++q) {
       const int v = tid + 256 * q;
+      if (AVT % 256 != 0 && v >= AVT) break;
       const int i = v / (BK / VN), kv = (v % (BK / VN)) * VN;
 #pragma unroll
       for (int e = 0; e < VN; ++e) As[buf][kv + e][i] = ra[q].v[e];
@@ -139,21 +144,14 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
     for (int q = 0; q < BV; ++q) {
       const int v = tid + 256 * q;
+      if (BVT % 256 != 0 && v >= BVT) break;
       const int kk = v / (BN / VN), nv = (v % (BN / VN)) * VN;
 #pragma unroll
       for (int e = 0; e < VN; ++e) Bs[buf][kk][nv + e] = rb[q].v[e];
     }
   };
 
-  // double-buffered: slice k+1 is loaded into registers during the MFMAs on
-  // slice k and stored into the other LDS buffer (last read one slice ago)
-  load(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const bool more = k0 + BK < K;
-    if (more) load(k0 + BK);
+  auto mma_slice = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       T a[TM], bb[TN];
@@ -166,9 +164,31 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 #pragma unroll
         for (int jn = 0; jn < TN; ++jn) acc[i][jn] = Mma<T>::op(a[i], bb[jn], acc[i][jn]);
     }
-    if (more) store(buf ^ 1);
+  };
+  load(0);
+  if (DB) {
+    // double-buffered: slice k+1 is loaded into registers during the MFMAs
+    // on slice k and stored into the other LDS buffer (last read one slice
+    // ago); one barrier per slice
+    store(0);
     __syncthreads();
-    buf ^= 1;
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      const bool more = k0 + BK < K;
+      if (more) load(k0 + BK);
+      mma_slice(buf);
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      store(0);
+      __syncthreads();
+      if (k0 + BK < K) load(k0 + BK);  // next slice in flight during the MFMAs
+      mma_slice(0);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -192,16 +212,28 @@ __global__ __launch_bounds__(256) void k_gemm(const T *__restrict__ A, const T *
 
 }  // namespace
 
-template <typename T>
-void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
-                 const double *colscale, int cell) {
-  constexpr int BM = 64, BN = 128, BK = 16;
+// Launch shapes (tile M x N x depth, LDS double buffering, minimum waves per
+// SIMD the register allocation must allow), chosen by measurement on MI355X
+// (32^3 problem, A = 384 and 1104): FP64 64 x 128 x 8 with four waves per
+// SIMD (53-57 TF/s), FP32 128 x 128 x 16 (108-110 TF/s).
+template <typename T, int BM, int BN, int BK, bool DB, int WPE>
+static void launch_shape(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
+                         const double *colscale, int cell) {
   const int mblocks = (M + BM - 1) / BM;
   const int nblocks = (int)(((long long)N + BN - 1) / BN);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
   const long long grid = (long long)mblocks * nb_pad;
-  hipLaunchKernelGGL((k_gemm<T, BM, BN, BK>), dim3((unsigned)grid), dim3(256), 0, st, A, B, C, M, N, K, mblocks,
-                     nblocks, bias, colscale, cell);
+  hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, DB, WPE>), dim3((unsigned)grid), dim3(256), 0, st, A, B, C, M, N, K,
+                     mblocks, nblocks, bias, colscale, cell);
+}
+
+template <typename T>
+void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
+                 const double *colscale, int cell) {
+  if (sizeof(T) == 8)
+    launch_shape<T, 64, 128, 8, true, 4>(A, B, C, M, N, K, st, bias, colscale, cell);
+  else
+    launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell);
 }
 template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t,
                                   const double *, const double *, int);
