@@ -232,7 +232,7 @@ void patch_x_integrals(const PatchNode &p, int order, std::vector<double> &X) {
 }
 
 void scatter_matrix(const HostAngular &ang, int level, const std::vector<double> &moments,
-                    std::vector<double> &St) {
+                    std::vector<double> &St, std::vector<double> *Xout) {
   const HostLevel &L = ang.lv[level];
   const int order = (int)moments.size() - 1;
   const int K = (order + 1) * (order + 1);
@@ -246,6 +246,7 @@ void scatter_matrix(const HostAngular &ang, int level, const std::vector<double>
   std::vector<double> F(K);
   for (int n = 0; n <= order; ++n)
     for (int o = -n; o <= n; ++o) F[n * n + n + o] = moments[n];
+  if (Xout) *Xout = X;
   St.assign((size_t)L.A * L.A, 0.0);
 #pragma omp parallel for schedule(dynamic)
   for (int a = 0; a < L.A; ++a) {

@@ -55,11 +55,12 @@ struct HostAngular {
 // Build the tree and levels.  Returns false with a message on bad input.
 bool build_angular(const RefineSpec &spec, HostAngular &out, std::string &err);
 
-// Dense canonical scatter matrix S~ (A x A, row-major) of a level for
-// moments f_0..f_L (sigma_{s,n} = sigma_s f_n), from accurately integrated
-// X integrals.  `threads` host threads.
+// Dense canonical scatter matrix S~ = X F X^T (A x A, row-major) of a level
+// for moments f_0..f_L (sigma_{s,n} = sigma_s f_n), from accurately
+// integrated X integrals (eq. X); Xout (optional) receives X (A x K,
+// K = (L+1)^2, harmonic index n^2 + n + o).
 void scatter_matrix(const HostAngular &ang, int level, const std::vector<double> &moments,
-                    std::vector<double> &St);
+                    std::vector<double> &St, std::vector<double> *Xout = nullptr);
 
 // Accurate integral of psi_m * Y_{n,o} over a patch for n <= order; used
 // for the X integrals.  X is [3][(order+1)^2].

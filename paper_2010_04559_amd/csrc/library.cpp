@@ -69,6 +69,13 @@ struct DevLevel {
   float *St32 = nullptr;
   double *G64 = nullptr, *Gt64 = nullptr;  // ordinate-form scatter and transpose
   float *G32 = nullptr, *Gt32 = nullptr;
+  // Factored ordinate-form scatter G = L R^T (levels >= 1 whose K = (order+1)^2
+  // harmonics are fewer than about A/2, where two GEMMs of 2AK flop per
+  // spatial dof beat one of 2A^2): L (A x K), R (A x K), and the transposes
+  // Lt, Rt (K x A); Kf = 0 when the dense G is used.
+  int Kf = 0;
+  double *L64 = nullptr, *R64 = nullptr, *Lt64 = nullptr, *Rt64 = nullptr;
+  float *L32 = nullptr, *R32 = nullptr, *Lt32 = nullptr, *Rt32 = nullptr;
   int *owner = nullptr;                    // level >= 1: owner patch on level l-1
   double *Pu = nullptr, *Ru = nullptr, *Pa = nullptr, *Ra = nullptr, *Pc = nullptr, *Rc = nullptr;
   int *first_child = nullptr, *n_child = nullptr;  // over level l-1 patches
@@ -171,6 +178,9 @@ struct tr_handle {
   static constexpr int kMaxGsBlocks = 1024;
   long long n_precond = 0;
   double sweep_dofs = 0;
+  long long fact_len = 0;        // K x S of the largest factored level scatter
+  double *fact64 = nullptr;      // R^T u (or L^T u) of a factored level
+  float *fact32 = nullptr;
   int coarse_steps = 0;
   std::vector<void *> allocs;
   size_t bytes = 0;
@@ -364,9 +374,39 @@ void build(tr_handle *h, const tr_problem *p) {
     D.ipsi = h->upload(H.ipsi);
     // scatter matrices at this level's order
     std::vector<double> mom(h->moments.begin(), h->moments.begin() + D.order + 1);
-    std::vector<double> St;
-    tr::scatter_matrix(h->ang, l, mom, St);
+    std::vector<double> St, X;
+    tr::scatter_matrix(h->ang, l, mom, St, &X);
     const int A = H.A;
+    const int K = (D.order + 1) * (D.order + 1);
+    if (l >= 1 && 20LL * K < 9LL * A) {
+      // G = L R^T with L_q = W_q^{-1} Psi^{-1} X_q F and R_p = Psi^{-1} X_p
+      std::vector<double> Lh((size_t)A * K), Rh((size_t)A * K), Lt((size_t)K * A), Rt((size_t)K * A);
+      for (int q = 0; q < H.P; ++q)
+        for (int k = 0; k < 3; ++k)
+          for (int c = 0; c < K; ++c) {
+            const int n = (int)std::floor(std::sqrt((double)c) + 1e-9);
+            double r = 0.0;
+            for (int m = 0; m < 3; ++m) r += kPsiInv[k][m] * X[(size_t)(3 * q + m) * K + c];
+            const int a = 3 * q + k;
+            Rh[(size_t)a * K + c] = r;
+            Rt[(size_t)c * A + a] = r;
+            const double lv = r * mom[n] / H.w[a];
+            Lh[(size_t)a * K + c] = lv;
+            Lt[(size_t)c * A + a] = lv;
+          }
+      D.Kf = K;
+      D.L64 = h->upload(Lh);
+      D.R64 = h->upload(Rh);
+      D.Lt64 = h->upload(Lt);
+      D.Rt64 = h->upload(Rt);
+      std::vector<float> l32(Lh.begin(), Lh.end()), r32(Rh.begin(), Rh.end()), lt32(Lt.begin(), Lt.end()),
+          rt32(Rt.begin(), Rt.end());
+      D.L32 = h->upload(l32);
+      D.R32 = h->upload(r32);
+      D.Lt32 = h->upload(lt32);
+      D.Rt32 = h->upload(rt32);
+      h->fact_len = std::max(h->fact_len, (long long)K * g.S);
+    }
     std::vector<double> G((size_t)A * A), Gt((size_t)A * A);
     for (int q = 0; q < H.P; ++q)
       for (int p2 = 0; p2 < H.P; ++p2) {
@@ -455,6 +495,7 @@ void build(tr_handle *h, const tr_problem *p) {
     tr::launch_fill<double>(D.f64, n, 0.0, nullptr);
     tr::launch_fill<double>(D.u64, n, 0.0, nullptr);
   }
+  if (h->fact_len > 0) h->fact64 = h->alloc<double>(h->fact_len);
   const long long nf = h->vec_len(h->top());
   h->tmp = h->alloc<double>(nf);
   h->tmp2 = h->alloc<double>(nf);
@@ -473,6 +514,7 @@ void ensure_mixed(tr_handle *h) {
     D.sa32 = h->alloc<float>(n);
     D.sb32 = h->prob.nu_pre > 1 ? h->alloc<float>(n) : nullptr;
   }
+  if (h->fact_len > 0) h->fact32 = h->alloc<float>(h->fact_len);
   h->mixed_ready = true;
 }
 
@@ -481,6 +523,9 @@ template <typename T>
 struct LevelBuf;
 template <>
 struct LevelBuf<double> {
+  static double *fact(tr_handle *h) { return h->fact64; }
+  static const double *Lf(DevLevel &D, bool adj) { return adj ? D.Lt64 : D.Rt64; }  // first factor (K x A)
+  static const double *Rf(DevLevel &D, bool adj) { return adj ? D.R64 : D.L64; }   // second factor (A x K)
   static double *f(DevLevel &D) { return D.f64; }
   static double *u(DevLevel &D) { return D.u64; }
   static double *sa(DevLevel &D) { return D.sa64; }
@@ -490,6 +535,9 @@ struct LevelBuf<double> {
 };
 template <>
 struct LevelBuf<float> {
+  static float *fact(tr_handle *h) { return h->fact32; }
+  static const float *Lf(DevLevel &D, bool adj) { return adj ? D.Lt32 : D.Rt32; }
+  static const float *Rf(DevLevel &D, bool adj) { return adj ? D.R32 : D.L32; }
   static float *f(DevLevel &D) { return D.f32; }
   static float *u(DevLevel &D) { return D.u32; }
   static float *sa(DevLevel &D) { return D.sa32; }
@@ -629,6 +677,26 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
   h->coarse_steps = sc.nsteps;
 }
 
+// Level scatter y = G_l u (transpose for the adjoint), with the forward
+// epilogue of do_gemm; factored levels take two GEMMs through a K x S
+// intermediate: G u = L (R^T u), G^T u = R (L^T u).
+template <typename T>
+void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t st, bool scale_sn = false,
+                   const T *bias = nullptr) {
+  DevLevel &D = h->lv[l];
+  if (!D.Kf) {
+    do_gemm<T>(h, LevelBuf<T>::G(D, adj), u, y, D.A, st, scale_sn, bias);
+    return;
+  }
+  T *tmp = LevelBuf<T>::fact(h);
+  const int S = (int)h->g.S;
+  tbegin(h, C_SCATTER);
+  tr::launch_gemm<T>(LevelBuf<T>::Lf(D, adj), u, tmp, D.Kf, S, D.A, st);
+  tr::launch_gemm<T>(LevelBuf<T>::Rf(D, adj), tmp, y, D.A, S, D.Kf, st, bias, scale_sn ? h->sig_s : nullptr,
+                     h->g.ns);
+  tend(h);
+}
+
 // Fig. lmg on level l >= 0 in ordinate form; f (level l's f buffer) is the
 // right-hand side, the result is left in level l's u buffer.
 template <typename T>
@@ -643,7 +711,6 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   const int nu_pre = h->prob.nu_pre, nu_post = h->prob.nu_post;
   T *f = LevelBuf<T>::f(D), *u = LevelBuf<T>::u(D);
   T *sa = LevelBuf<T>::sa(D), *sb = LevelBuf<T>::sb(D);
-  const T *G = LevelBuf<T>::G(D, adj);
   DevLevel &Dc = h->lv[l - 1];
   // Forward: f holds the prepared right-hand side f~ = N^{-1} f, every
   // sweep reads one prepared vector (f~ itself, or f~ + sigma_s G u formed
@@ -655,10 +722,10 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   T *s_prev = nullptr;
   for (int it = 1; it < nu_pre; ++it) {
     if (!adj) {
-      do_gemm<T>(h, G, u, sa, D.A, st, true, f);
+      level_scatter<T>(h, l, adj, u, sa, st, true, f);
       do_sweep<T>(h, l, sa, nullptr, u, adj, st);
     } else {
-      do_gemm<T>(h, G, u, sa, D.A, st);
+      level_scatter<T>(h, l, adj, u, sa, st);
       do_sweep<T>(h, l, f, sa, u, adj, st);
     }
     s_prev = sa;
@@ -667,9 +734,9 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   // residual S (u - u_prev), restricted to level l-1 (forward: both terms
   // carry the same f~, which cancels)
   if (!adj)
-    do_gemm<T>(h, G, u, sa, D.A, st, true, s_prev ? f : nullptr);
+    level_scatter<T>(h, l, adj, u, sa, st, true, s_prev ? f : nullptr);
   else
-    do_gemm<T>(h, G, u, sa, D.A, st);
+    level_scatter<T>(h, l, adj, u, sa, st);
   tbegin(h, C_TRANSFER);
   if (l - 1 == 0)
     tr::launch_restrict<T, double>(sa, s_prev, Dc.f64, adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P, h->sig_s,
@@ -690,10 +757,10 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   tend(h);
   for (int it = 0; it < nu_post; ++it) {
     if (!adj) {
-      do_gemm<T>(h, G, u, sa, D.A, st, true, f);
+      level_scatter<T>(h, l, adj, u, sa, st, true, f);
       do_sweep<T>(h, l, sa, nullptr, u, adj, st);
     } else {
-      do_gemm<T>(h, G, u, sa, D.A, st);
+      level_scatter<T>(h, l, adj, u, sa, st);
       do_sweep<T>(h, l, f, sa, u, adj, st);
     }
   }
