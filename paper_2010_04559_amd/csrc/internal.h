@@ -64,10 +64,16 @@ void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st
 // The grid barrier uses bar_arrive[max_blocks], bar_release[1] and bar_err[1]
 // (zeroed once); generations continue from gen0, which the caller advances
 // by nsteps per launch.  bar_err != 0 after the launch means a barrier timed out.
+// The same solve without grid barriers (per-cell update counters cnt[C],
+// zeroed here; err as above): wave w runs slots wave_off[w] .. wave_off[w+1]
+// of 64 / 2^dim items each (octant << 29 | count << 22 | list index, or -1).
+void launch_coarse_flow(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
+                        const OrdInfo *ord, const Planes &pl, const Grid &g, const int *wave_off, const int *slots,
+                        int waves, bool adjoint, unsigned *cnt, int *err, hipStream_t st);
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                       const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
-                      int *bar_err, int max_blocks, unsigned gen0, hipStream_t st);
+                      int *bar_err, int max_blocks, unsigned gen0, bool coh, hipStream_t st);
 
 // out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * in[3p+m][s]
 template <typename Tin, typename Tout>

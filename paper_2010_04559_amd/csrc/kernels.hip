@@ -647,11 +647,23 @@ __device__ __forceinline__ GsPrep<DIM> gs_prepare(int item, const double *__rest
   return q;
 }
 
+// Accesses of the Gauss-Seidel iterate that are coherent across the XCDs
+// without cache maintenance: device-scope relaxed atomics read and write
+// at the device coherence point, so a store acknowledged before a flag is
+// published is seen by any load issued after the flag is observed.
+__device__ __forceinline__ double ld_dev(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Gauss-Seidel update of one (cell, octant) block by the 2^dim lanes of a
 // cell group; every lane of the wave must call it (idle groups pass
 // active = false with a valid cell and store nothing).  G_lds and ord_lds
 // are the level's 24 x 24 scatter block and ordinate data staged in LDS.
-template <int DIM, bool ADJ>
+// COH: the iterate is read and written with device-coherent accesses.
+template <int DIM, bool ADJ, bool COH = false>
 __device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restrict__ u, const double *G_lds,
                                           const OrdInfo *ord_lds, const Grid &g, bool active, int b) {
   constexpr int NS = 1 << DIM;
@@ -667,7 +679,7 @@ __device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restri
   // octant's three ordinates
   double uv[24];
 #pragma unroll
-  for (int kp = 0; kp < 24; ++kp) uv[kp] = up[kp * S];
+  for (int kp = 0; kp < 24; ++kp) uv[kp] = COH ? ld_dev(up + kp * S) : up[kp * S];
   double tr[3][DIM];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
@@ -676,7 +688,8 @@ __device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restri
       const int fl = (flip >> d) & 1;
       const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
       const int bn = (b & ~(1 << d)) | (nbit << d);
-      tr[m][d] = u[(k0 + m) * S + q.jn[d] * NS + bn];
+      const double *tp = u + (k0 + m) * S + q.jn[d] * NS + bn;
+      tr[m][d] = COH ? ld_dev(tp) : *tp;
     }
   }
   // scatter from the other octants' ordinates (latest values)
@@ -762,7 +775,12 @@ __device__ __forceinline__ void gs_update(const GsPrep<DIM> &q, double *__restri
   for (int m = 0; m < 3; ++m) {
     double out = lane_backward<DIM>(r[m], b, ax);
     if (ADJ) out = lane_mass<DIM>(out, NS - 1, true) * (1.0 / g.vol);
-    if (active) u[(k0 + m) * S + j * NS + b] = out;
+    if (active) {
+      if (COH)
+        st_dev(u + (k0 + m) * S + j * NS + b, out);
+      else
+        u[(k0 + m) * S + j * NS + b] = out;
+    }
   }
 }
 
@@ -784,17 +802,23 @@ struct GridBarrier {
 // for other waves' stores to complete, so every wave first waits for its
 // own stores (vmcnt(0): acknowledged by the L2); then one thread's release
 // fence writes the L2 back and publishes the arrival.
+// COH: the data being published were written with device-coherent stores,
+// so their acknowledgement is all the release needs (no L2 write-back).
+template <bool COH>
 __device__ __forceinline__ void grid_arrive(const GridBarrier &gb, unsigned gen) {
   asm volatile("" ::: "memory");
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters untouched
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (!COH) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(gb.arrive + blockIdx.x, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 // Waiting half: returns false (every thread) after a timeout anywhere.
+// COH: the published data are read with device-coherent loads, so no L2
+// invalidation is needed after the wait.
+template <bool COH>
 __device__ __forceinline__ bool grid_wait(const GridBarrier &gb, unsigned gen) {
   __shared__ int ok;
   bool timeout = false;
@@ -809,7 +833,7 @@ __device__ __forceinline__ bool grid_wait(const GridBarrier &gb, unsigned gen) {
     }
     if (timeout) break;
   }
-  if (threadIdx.x < gridDim.x) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (!COH && threadIdx.x < gridDim.x) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (threadIdx.x == 0) ok = 1;
   __syncthreads();
   if (timeout) ok = 0;
@@ -826,7 +850,7 @@ __device__ __forceinline__ bool grid_wait(const GridBarrier &gb, unsigned gen) {
 // (octant << 28) | index into the plane-ordered cell list.  A grid-wide
 // barrier separates the steps; the first round of items of the next step
 // is prepared before it.
-template <int DIM, bool ADJ, int TB>
+template <int DIM, bool ADJ, int TB, bool COH>
 __global__ __launch_bounds__(TB) void k_gs_solve(const double *__restrict__ f, double *__restrict__ u,
                                                   const double *__restrict__ G, const double *__restrict__ sig_t,
                                                   const double *__restrict__ sig_s,
@@ -855,19 +879,102 @@ __global__ __launch_bounds__(TB) void k_gs_solve(const double *__restrict__ f, d
     const int beg = step_off[t], end = step_off[t + 1];
     // the first round was prepared before the barrier; every block runs
     // it so that the wave-wide shuffles see valid lanes
-    gs_update<DIM, ADJ>(q, u, G_lds, ord_lds, g, act, b);
+    gs_update<DIM, ADJ, COH>(q, u, G_lds, ord_lds, g, act, b);
     for (int base = beg + blockIdx.x * CPB + stride; base < end; base += stride) {
       const int it = base + slot;
       const bool active = it < end;
       const GsPrep<DIM> q2 =
           gs_prepare<DIM, ADJ>(items[active ? it : beg], f, sig_t, sig_s, ord_lds, pl, g, b);
-      gs_update<DIM, ADJ>(q2, u, G_lds, ord_lds, g, active, b);
+      gs_update<DIM, ADJ, COH>(q2, u, G_lds, ord_lds, g, active, b);
     }
     // arrive, then load what the next step needs while the other blocks
     // finish (it is read-only data, unaffected by the barrier's fences)
-    grid_arrive(gb, gen0 + t + 1);
+    grid_arrive<COH>(gb, gen0 + t + 1);
     if (t + 1 < nsteps) q = gs_prepare<DIM, ADJ>(first_item(t + 1, act), f, sig_t, sig_s, ord_lds, pl, g, b);
-    if (!grid_wait(gb, gen0 + t + 1)) return;
+    if (!grid_wait<COH>(gb, gen0 + t + 1)) return;
+    asm volatile("" ::: "memory");
+  }
+}
+
+// Dataflow form of the same coarse solve: no grid-wide barrier.  Every
+// cell j has a counter cnt[j] of completed updates; the update with count
+// c = 8 sweep + (octant's position in the order) may run once cnt[j] == c
+// (the cell's earlier updates are done) and cnt[n] >= c + 1 for each upwind
+// (adjoint: downwind) neighbour n (its update of the same sweep and octant
+// is done).  That is exactly the data each update reads; writes it could
+// race with are excluded too, since a neighbour cannot reach its next update
+// of this octant before this cell has passed the reflected octant, which
+// comes later in this cell's chain.  Each wave runs a list of slots of 8
+// updates (one per 2^dim-lane group) in step order of the pipelined
+// schedule, so the earliest unfinished step always has all its updates
+// runnable and the launch cannot deadlock (every wave is resident: it is a
+// cooperative launch).  Publishing: the wave's stores are released at
+// device scope (device-coherent stores, waited for), then each group's
+// leader stores c + 1 in cnt[j]; waiting: relaxed polls of the counters,
+// after which the iterate is read with device-coherent loads.  Spins are
+// bounded and set the error word, which every waiting wave checks.
+// Slot items: octant << 29 | c << 22 | cell-list index (all ones: empty;
+// c <= 126 for real items).
+template <int DIM, bool ADJ>
+__global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, double *u,
+                                                 const double *__restrict__ G, const double *__restrict__ sig_t,
+                                                 const double *__restrict__ sig_s,
+                                                 const OrdInfo *__restrict__ ord, Planes pl, Grid g,
+                                                 const int *__restrict__ wave_off, const int *__restrict__ slots,
+                                                 int nwaves, unsigned *cnt, int *err) {
+  constexpr int NS = 1 << DIM;
+  __shared__ double G_lds[24 * 24];
+  __shared__ OrdInfo ord_lds[24];
+  for (int i = threadIdx.x; i < 24 * 24; i += blockDim.x) G_lds[i] = G[i];
+  if (threadIdx.x < 24) ord_lds[threadIdx.x] = ord[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int b = lane & (NS - 1);
+  const int grp = lane / NS;  // 64 / 2^dim groups per wave (8 in 3-D)
+  const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (wave >= nwaves) return;
+  const int s0 = wave_off[wave], s1 = wave_off[wave + 1];
+  for (int sl = s0; sl < s1; ++sl) {
+    const int item = slots[(long long)sl * (64 / NS) + grp];
+    const bool active = item != -1;  // all ones: c = 127 never occurs
+    const int octant = active ? (item >> 29) & 7 : 0;
+    const unsigned c = active ? (unsigned)((item >> 22) & 127) : 0u;
+    const int idx = active ? item & ((1 << 22) - 1) : 0;
+    // read-only data of the update first (overlapping the waits), then the
+    // dependencies: lane 0 of the group polls the cell's own counter, lane
+    // 1 + d the upwind (adjoint: downwind) neighbour along axis d
+    const GsPrep<DIM> q = gs_prepare<DIM, ADJ>((octant << 28) | idx, f, sig_t, sig_s, ord_lds, pl, g, b);
+    const long long jself = q.j;
+    long long mydep = b == 0 ? jself : -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      if (q.has[d] && b == 1 + d) mydep = q.jn[d];
+    bool ready = !active || mydep < 0;
+    long spins = 0;
+    bool failed = false;
+    while (true) {
+      if (!ready) {
+        const unsigned v = __hip_atomic_load(cnt + mydep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ready = b == 0 ? v == c : v >= c + 1;
+      }
+      if (__ballot(!ready) == 0) break;
+      if (++spins > (1L << 22) ||
+          (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        failed = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (__ballot(failed)) return;  // wave-uniform
+    asm volatile("" ::: "memory");  // iterate loads stay after the waits
+    gs_update<DIM, ADJ, true>(q, u, G_lds, ord_lds, g, active, b);
+    // the group's iterate stores are acknowledged at the device coherence
+    // point before its counter moves
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    asm volatile("" ::: "memory");
+    if (active && b == 0) __hip_atomic_store(cnt + jself, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1476,6 +1583,11 @@ __global__ void k_axpby(long long n, double a, const double *__restrict__ x, dou
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) z[n - 1] = a * x[n - 1] + b * y[n - 1];
 }
 
+__global__ void k_fill_u32(unsigned *x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = 0u;
+}
+
 template <typename T>
 __global__ void k_fill(T *x, long long n, T v) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1567,17 +1679,35 @@ template void launch_sweep<float>(const SweepArgs<float> &, int, bool, hipStream
 static int g_gs_block_threads = 256;
 static int gs_block_threads() { return g_gs_block_threads; }
 
+void launch_coarse_flow(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
+                        const OrdInfo *ord, const Planes &pl, const Grid &g, const int *wave_off, const int *slots,
+                        int waves, bool adjoint, unsigned *cnt, int *err, hipStream_t st) {
+  launch_fill<double>(u, 24LL * g.S, 0.0, st);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(g.C)), dim3(kBlock), 0, st, cnt, g.C);
+  void *fn = g.dim == 3 ? (adjoint ? (void *)k_gs_flow<3, true> : (void *)k_gs_flow<3, false>)
+                        : (adjoint ? (void *)k_gs_flow<2, true> : (void *)k_gs_flow<2, false>);
+  const int blocks = (waves + 3) / 4;
+  void *args[] = {(void *)&f,     (void *)&u,     (void *)&G,   (void *)&sig_t, (void *)&sig_s,
+                  (void *)&ord,   (void *)&pl,    (void *)&g,   (void *)&wave_off, (void *)&slots,
+                  (void *)&waves, (void *)&cnt,   (void *)&err};
+  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st) != hipSuccess)
+    throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
+}
+
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                       const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
-                      int *bar_err, int max_blocks, unsigned gen0, hipStream_t st) {
+                      int *bar_err, int max_blocks, unsigned gen0, bool coh, hipStream_t st) {
   launch_fill<double>(u, 24LL * g.S, 0.0, st);
   const int tb = gs_block_threads();
   void *fn = nullptr;
-#define TR_GS_FN(TB)                                                                  \
-  (g.dim == 3 ? (adjoint ? (void *)k_gs_solve<3, true, TB> : (void *)k_gs_solve<3, false, TB>) \
-              : (adjoint ? (void *)k_gs_solve<2, true, TB> : (void *)k_gs_solve<2, false, TB>))
-  fn = tb == 1024 ? TR_GS_FN(1024) : tb == 512 ? TR_GS_FN(512) : TR_GS_FN(256);
+#define TR_GS_FN(TB, COH)                                                                          \
+  (g.dim == 3 ? (adjoint ? (void *)k_gs_solve<3, true, TB, COH> : (void *)k_gs_solve<3, false, TB, COH>) \
+              : (adjoint ? (void *)k_gs_solve<2, true, TB, COH> : (void *)k_gs_solve<2, false, TB, COH>))
+  if (coh)
+    fn = tb == 1024 ? TR_GS_FN(1024, true) : tb == 512 ? TR_GS_FN(512, true) : TR_GS_FN(256, true);
+  else
+    fn = tb == 1024 ? TR_GS_FN(1024, false) : tb == 512 ? TR_GS_FN(512, false) : TR_GS_FN(256, false);
 #undef TR_GS_FN
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

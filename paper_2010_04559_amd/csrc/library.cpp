@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -170,7 +171,13 @@ struct tr_handle {
     bool adj = false;
     int nsteps = 0, max_items = 0;
     int *step_off = nullptr, *items = nullptr;
+    // dataflow form: per-wave slot lists (empty when not applicable)
+    int waves = 0;
+    int *wave_off = nullptr, *slots = nullptr;
   };
+  bool gs_flow = true;        // coarse solve without grid barriers
+  bool gs_coh = true;         // barrier form: device-coherent iterate accesses
+  unsigned *gs_cnt = nullptr;  // [cells] update counters of the dataflow solve
   std::vector<GsSchedule> gs_sched;
   unsigned *bar_arrive = nullptr, *bar_release = nullptr;
   int *bar_err = nullptr;
@@ -586,16 +593,18 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
   const Grid &g = h->g;
   const long long C = g.C;
   std::vector<int> last(C, -1), to(C, -1);
-  std::vector<std::vector<int>> steps;
+  std::vector<std::vector<int>> steps, fsteps;
   const int np = h->pl.nplanes;
   std::vector<int> cells_host;
   {
     cells_host.resize(h->plane_off_host.back());
     HIPCHK(hipMemcpy(cells_host.data(), h->d_cells, cells_host.size() * sizeof(int), hipMemcpyDeviceToHost));
   }
+  const bool flow_ok = 8 * nu <= 127 && C < (1LL << 22);
   for (int sweep = 0; sweep < nu; ++sweep)
     for (int oi = 0; oi < 8; ++oi) {
       const int o = h->octant_order[oi];
+      const int cnt_before = 8 * sweep + oi;  // updates every cell has had before this octant sweep
       for (int pp = 0; pp < np; ++pp) {
         const int p = adj ? np - 1 - pp : pp;
         for (int idx = h->plane_off_host[p]; idx < h->plane_off_host[p + 1]; ++idx) {
@@ -615,8 +624,12 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
           }
           to[j] = t;
           last[j] = t;
-          if ((int)steps.size() <= t) steps.resize(t + 1);
+          if ((int)steps.size() <= t) {
+            steps.resize(t + 1);
+            fsteps.resize(t + 1);
+          }
           steps[t].push_back((o << 28) | idx);
+          if (flow_ok) fsteps[t].push_back((int)(((unsigned)o << 29) | ((unsigned)cnt_before << 22) | (unsigned)idx));
         }
       }
     }
@@ -634,6 +647,32 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
   sc.max_items = mx;
   sc.step_off = h->upload(off);
   sc.items = h->upload(items);
+  if (flow_ok) {
+    // slots of 64 / 2^dim updates dealt round-robin to the waves, step by
+    // step, so every wave's list is in step order.  Four waves per slot of
+    // the widest step: a wave is busy with one slot for about four steps
+    // (waits, coherent loads, store acknowledgement), measured best on the
+    // 32^3 problem (512 waves: 12.2 ms per 10-sweep solve; 256: 13.0;
+    // 1024: 12.6); at most 1024 waves, which stay co-resident.
+    const int per = 64 / g.ns;
+    const int W = 4 * std::max(1, std::min(256, (mx + per - 1) / per));
+    std::vector<std::vector<int>> lists(W);
+    int next = 0;
+    for (auto &st : fsteps)
+      for (size_t i0 = 0; i0 < st.size(); i0 += per) {
+        auto &L = lists[next];
+        for (int k = 0; k < per; ++k) L.push_back(i0 + k < st.size() ? st[i0 + k] : -1);
+        next = (next + 1) % W;
+      }
+    std::vector<int> woff{0}, sl;
+    for (auto &L : lists) {
+      sl.insert(sl.end(), L.begin(), L.end());
+      woff.push_back((int)(sl.size() / per));
+    }
+    sc.waves = W;
+    sc.wave_off = h->upload(woff);
+    sc.slots = h->upload(sl);
+  }
   h->gs_sched.push_back(sc);
   return h->gs_sched.back();
 }
@@ -643,7 +682,7 @@ void check_barrier(tr_handle *h, hipStream_t st) {
   int e = 0;
   HIPCHK(hipMemcpyAsync(&e, h->bar_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (e) throw std::runtime_error("coarse Gauss-Seidel grid barrier timed out");
+  if (e) throw std::runtime_error("coarse Gauss-Seidel solve timed out waiting for a grid barrier or an upwind update");
 }
 
 void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipStream_t st) {
@@ -668,10 +707,19 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
     HIPCHK(hipDeviceSynchronize());
     h->bar_gen = 0;
   }
+  if (h->gs_flow && sc.waves > 0) {
+    if (!h->gs_cnt) h->gs_cnt = h->alloc<unsigned>(h->g.C);
+    tbegin(h, C_COARSE);
+    tr::launch_coarse_flow(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->g, sc.wave_off,
+                           sc.slots, sc.waves, adj, h->gs_cnt, h->bar_err, st);
+    tend(h);
+    h->coarse_steps = sc.nsteps;
+    return;
+  }
   tbegin(h, C_COARSE);
   tr::launch_coarse_gs(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->g, sc.step_off, sc.items,
                        sc.nsteps, sc.max_items, adj, h->bar_arrive, h->bar_release, h->bar_err,
-                       tr_handle::kMaxGsBlocks, h->bar_gen, st);
+                       tr_handle::kMaxGsBlocks, h->bar_gen, h->gs_coh, st);
   tend(h);
   h->bar_gen += (unsigned)sc.nsteps;
   h->coarse_steps = sc.nsteps;
@@ -1046,6 +1094,12 @@ int tr_setup(const tr_problem *prob, tr_handle **out) {
   tr_handle *h = nullptr;
   int rc = translate([&]() {
     h = new tr_handle();
+    // TR_COARSE_GS=barrier (barrier_fence: with cache maintenance fences)
+    // selects the step-synchronous coarse solve, for comparison; the default
+    // is the dataflow form
+    const char *gs = std::getenv("TR_COARSE_GS");
+    h->gs_flow = !(gs && std::strncmp(gs, "barrier", 7) == 0);
+    h->gs_coh = !(gs && std::strcmp(gs, "barrier_fence") == 0);
     build(h, prob);
     return TR_OK;
   });
