@@ -120,12 +120,16 @@ void launch_dot_partial(const double *x, const double *y, long long n, double *p
                         hipStream_t st);
 void launch_dot_final(const double *partial, int nblocks, double *out, hipStream_t st);
 void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st);
-// w -= a v, then partial sums of w.z per block (z may be w)
-void launch_axpy_dot(long long n, double a, const double *v, double *w, const double *z, double *partial,
-                     int nblocks, hipStream_t st);
 void launch_scal(long long n, double a, double *x, hipStream_t st);
 // y += sum_q c[q] x[q] (host arrays of k device vectors and coefficients)
 void launch_multi_axpy(long long n, int k, const double *const *x, const double *c, double *y, hipStream_t st);
+// inner products x_q . y (q < k) and x_q . z (q < kz), k <= 16, into
+// out[0..k) and out[k..k+kz); partial holds (k + kz) x nblocks doubles
+void launch_multi_dot(long long n, int k, const double *const *x, const double *y, int kz, const double *z,
+                      double *partial, int nblocks, double *out, hipStream_t st);
+// y += sum_q c_q x_q (any k >= 1), then out[0] = |y|^2; partial holds nblocks doubles
+void launch_multi_axpy_norm(long long n, int k, const double *const *x, const double *c, double *y,
+                            double *partial, int nblocks, double *out, hipStream_t st);
 void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st);
 template <typename T>
 void launch_fill(T *x, long long n, T v, hipStream_t st);

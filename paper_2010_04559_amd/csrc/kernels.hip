@@ -1483,36 +1483,6 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const double *__restrict
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// One modified Gram-Schmidt step fused with the next inner product:
-//   w -= a v;  partial[block] = sum w.z  (z = the next basis vector, or w)
-__global__ __launch_bounds__(kBlock) void k_axpy_dot(long long n, double a, const double *__restrict__ v,
-                                                     double *__restrict__ w, const double *__restrict__ z,
-                                                     double *__restrict__ partial) {
-  const long long n2 = n / 2;
-  const double2 *v2 = reinterpret_cast<const double2 *>(v);
-  double2 *w2 = reinterpret_cast<double2 *>(w);
-  const double2 *z2 = reinterpret_cast<const double2 *>(z);
-  const bool self = z == w;
-  double a0 = 0.0, a1 = 0.0;
-  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n2; i += (long long)gridDim.x * kBlock) {
-    const double2 vv = v2[i];
-    double2 ww = w2[i];
-    ww.x -= a * vv.x;
-    ww.y -= a * vv.y;
-    w2[i] = ww;
-    const double2 zz = self ? ww : z2[i];
-    a0 += ww.x * zz.x;
-    a1 += ww.y * zz.y;
-  }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    const double t = w[n - 1] - a * v[n - 1];
-    w[n - 1] = t;
-    a0 += t * (self ? t : z[n - 1]);
-  }
-  const double t = block_sum(a0 + a1);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
 __global__ __launch_bounds__(kBlock) void k_dot_final(const double *__restrict__ partial, int nb,
                                                       double *__restrict__ out) {
   double acc = 0.0;
@@ -1556,6 +1526,121 @@ __global__ void k_multi_axpy(long long n, MultiAxpyArgs a, double *__restrict__ 
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
     for (int q = 0; q < a.k; ++q) y[n - 1] += a.c[q] * a.x[q][n - 1];
+}
+
+// Several inner products in one pass (the projections of one Arnoldi step
+// computed together, see the GMRES driver):
+//   partial[q][block]     = x_q . y   (q < k)
+//   partial[k + q][block] = x_q . z   (q < kz; with zlast, z is x_{k-1} and
+//                                      is not read a second time)
+struct MultiDotArgs {
+  const double *x[kMaxMulti];
+  const double *y, *z;
+  int k, kz;
+  bool zlast;
+};
+
+__global__ __launch_bounds__(kBlock) void k_multi_dot(long long n, MultiDotArgs a, double *__restrict__ partial) {
+  const long long n2 = n / 2;
+  double sy[kMaxMulti], sz[kMaxMulti];
+#pragma unroll
+  for (int q = 0; q < kMaxMulti; ++q) sy[q] = sz[q] = 0.0;
+  const double2 *y2 = reinterpret_cast<const double2 *>(a.y);
+  const double2 *z2 = reinterpret_cast<const double2 *>(a.z);
+  const bool zsep = a.kz > 0 && !a.zlast;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n2; i += (long long)gridDim.x * kBlock) {
+    const double2 yy = y2[i];
+    double2 xv[kMaxMulti];
+#pragma unroll
+    for (int q = 0; q < kMaxMulti; ++q)
+      if (q < a.k) xv[q] = reinterpret_cast<const double2 *>(a.x[q])[i];
+    double2 zz = make_double2(0.0, 0.0);
+    if (zsep) zz = z2[i];
+#pragma unroll
+    for (int q = 0; q < kMaxMulti; ++q)
+      if (a.zlast && q == a.k - 1) zz = xv[q];
+#pragma unroll
+    for (int q = 0; q < kMaxMulti; ++q)
+      if (q < a.k) {
+        sy[q] += xv[q].x * yy.x + xv[q].y * yy.y;
+        if (q < a.kz) sz[q] += xv[q].x * zz.x + xv[q].y * zz.y;
+      }
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double yl = a.y[n - 1];
+    const double zl = a.kz > 0 ? (a.zlast ? a.x[a.k - 1][n - 1] : a.z[n - 1]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxMulti; ++q)
+      if (q < a.k) {
+        const double xl = a.x[q][n - 1];
+        sy[q] += xl * yl;
+        if (q < a.kz) sz[q] += xl * zl;
+      }
+  }
+  double v[2 * kMaxMulti];
+#pragma unroll
+  for (int q = 0; q < kMaxMulti; ++q) {
+    v[q] = sy[q];
+    v[kMaxMulti + q] = sz[q];
+  }
+  // rows 0..k-1 then k..k+kz-1 of the partial table
+  __shared__ double red[kBlock / 64][2 * kMaxMulti];
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxMulti; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 2 * kMaxMulti; ++q) red[threadIdx.x >> 6][q] = v[q];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < a.k + a.kz) {
+    const int col = t < a.k ? t : kMaxMulti + (t - a.k);
+    double r = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) r += red[w][col];
+    partial[(long long)t * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// out[r] = sum of row r of a [rows][nb] partial table (one block per row)
+__global__ __launch_bounds__(kBlock) void k_rows_final(const double *__restrict__ partial, int nb,
+                                                       double *__restrict__ out) {
+  const double *row = partial + (long long)blockIdx.x * nb;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) acc += row[i];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// y += sum_i c_i x_i (up to kMaxMulti vectors), and partial[block] = the
+// block's share of |y|^2 after the update
+__global__ __launch_bounds__(kBlock) void k_multi_axpy_norm(long long n, MultiAxpyArgs a, double *__restrict__ y,
+                                                            double *__restrict__ partial) {
+  const long long n2 = n / 2;
+  double2 *y2 = reinterpret_cast<double2 *>(y);
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n2; i += (long long)gridDim.x * kBlock) {
+    double2 v = y2[i];
+    double2 xv[kMaxMulti];
+#pragma unroll
+    for (int q = 0; q < kMaxMulti; ++q)
+      if (q < a.k) xv[q] = reinterpret_cast<const double2 *>(a.x[q])[i];
+#pragma unroll
+    for (int q = 0; q < kMaxMulti; ++q)
+      if (q < a.k) {
+        v.x += a.c[q] * xv[q].x;
+        v.y += a.c[q] * xv[q].y;
+      }
+    y2[i] = v;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double t = y[n - 1];
+    for (int q = 0; q < a.k; ++q) t += a.c[q] * a.x[q][n - 1];
+    y[n - 1] = t;
+    acc += t * t;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 __global__ void k_scal(long long n, double a, double *__restrict__ x) {
@@ -1867,10 +1952,6 @@ static int blas_grid(long long n) {
   long long g = (n / 2 + kBlock - 1) / kBlock;
   return (int)std::max(1LL, std::min(g, 8192LL));
 }
-void launch_axpy_dot(long long n, double a, const double *v, double *w, const double *z, double *partial,
-                     int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_dot, dim3(nblocks), dim3(kBlock), 0, st, n, a, v, w, z, partial);
-}
 void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x, y);
 }
@@ -1884,6 +1965,33 @@ void launch_multi_axpy(long long n, int k, const double *const *x, const double 
     }
     hipLaunchKernelGGL(k_multi_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, y);
   }
+}
+void launch_multi_dot(long long n, int k, const double *const *x, const double *y, int kz, const double *z,
+                      double *partial, int nblocks, double *out, hipStream_t st) {
+  if (k < 1 || k > kMaxMulti || kz < 0 || kz > k) throw std::runtime_error("multi-dot: bad vector count");
+  MultiDotArgs a{};
+  a.k = k;
+  a.kz = kz;
+  for (int q = 0; q < k; ++q) a.x[q] = x[q];
+  a.y = y;
+  a.z = z;
+  a.zlast = kz > 0 && z == x[k - 1];
+  hipLaunchKernelGGL(k_multi_dot, dim3(nblocks), dim3(kBlock), 0, st, n, a, partial);
+  hipLaunchKernelGGL(k_rows_final, dim3(k + kz), dim3(kBlock), 0, st, partial, nblocks, out);
+}
+void launch_multi_axpy_norm(long long n, int k, const double *const *x, const double *c, double *y,
+                            double *partial, int nblocks, double *out, hipStream_t st) {
+  // all but the last group of vectors without the norm
+  int q0 = 0;
+  for (; k - q0 > kMaxMulti; q0 += kMaxMulti) launch_multi_axpy(n, kMaxMulti, x + q0, c + q0, y, st);
+  MultiAxpyArgs a{};
+  a.k = k - q0;
+  for (int q = 0; q < a.k; ++q) {
+    a.x[q] = x[q0 + q];
+    a.c[q] = c[q0 + q];
+  }
+  hipLaunchKernelGGL(k_multi_axpy_norm, dim3(nblocks), dim3(kBlock), 0, st, n, a, y, partial);
+  hipLaunchKernelGGL(k_rows_final, dim3(1), dim3(kBlock), 0, st, partial, nblocks, out);
 }
 void launch_scal(long long n, double a, double *x, hipStream_t st) {
   hipLaunchKernelGGL(k_scal, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, x);

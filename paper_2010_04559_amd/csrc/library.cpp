@@ -158,6 +158,8 @@ struct tr_handle {
   double *Souter = nullptr;  // canonical S~ at the problem's order on the finest level
   double *iom = nullptr;     // [A][3] int Omega^xi psi on the finest level
   double *dot_partial = nullptr, *dot_out = nullptr;
+  double *mdot_partial = nullptr, *mdot_out = nullptr;  // [32][dot_blocks], [2 m + 4]
+  int mdot_len = 0;
   double *tmp = nullptr;     // one finest-level FP64 vector
   double *tmp2 = nullptr;
   int dot_blocks = 2048;
@@ -892,16 +894,6 @@ double dot(tr_handle *h, const double *x, const double *y, long long n, hipStrea
   return v;
 }
 
-// w -= a v; returns w . z (z may be w)
-double axpy_dot(tr_handle *h, double a, const double *v, double *w, const double *z, long long n, hipStream_t st) {
-  tr::launch_axpy_dot(n, a, v, w, z, h->dot_partial, h->dot_blocks, st);
-  tr::launch_dot_final(h->dot_partial, h->dot_blocks, h->dot_out, st);
-  double r = 0;
-  HIPCHK(hipMemcpyAsync(&r, h->dot_out, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return r;
-}
-
 void ensure_krylov(tr_handle *h, int m) {
   if (h->kry_m >= m) return;
   const long long n = h->vec_len(h->top());
@@ -916,7 +908,57 @@ void ensure_krylov(tr_handle *h, int m) {
     h->Z.clear();
   }
   if (!h->kw) h->kw = h->alloc<double>(n);
+  if (!h->mdot_partial) h->mdot_partial = h->alloc<double>(32LL * h->dot_blocks);
+  if (h->mdot_len < 2 * m + 4) {
+    h->mdot_len = 2 * m + 4;
+    h->mdot_out = h->alloc<double>(h->mdot_len);
+  }
   h->kry_m = m;
+}
+
+// One Arnoldi orthogonalisation in two passes over the basis (modified
+// Gram-Schmidt in its inverse compact WY form, Swirydowicz et al. 2020):
+//   pass 1: s_i = v_i . w (i <= j) and the new Gram row l_i = v_j . v_i (i < j)
+//   host:   h = (I + L)^{-1} s, L strictly lower with the Gram rows, which
+//           reproduces the sequential projections of modified Gram-Schmidt
+//   pass 2: w -= sum_i h_i v_i, returning |w|^2.
+// Lg holds the Gram rows (row j written here); hcol receives h.
+double arnoldi_orth(tr_handle *h, int j, double *w, std::vector<double> &Lg, int m, double *hcol, long long n,
+                    hipStream_t st) {
+  const int k = j + 1;
+  std::vector<const double *> X(h->V.begin(), h->V.begin() + k);
+  int off = 0;
+  std::vector<std::array<int, 3>> chunks;  // q0, c, kz
+  for (int q0 = 0; q0 < k; q0 += 16) {
+    const int c = std::min(16, k - q0);
+    const int kz = std::min(c, std::max(0, j - q0));
+    tr::launch_multi_dot(n, c, X.data() + q0, w, kz, h->V[j], h->mdot_partial, h->dot_blocks, h->mdot_out + off,
+                         st);
+    chunks.push_back({q0, c, kz});
+    off += c + kz;
+  }
+  std::vector<double> r(off);
+  HIPCHK(hipMemcpyAsync(r.data(), h->mdot_out, off * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> sv(k);
+  off = 0;
+  for (auto &ch : chunks) {
+    for (int q = 0; q < ch[1]; ++q) sv[ch[0] + q] = r[off + q];
+    for (int q = 0; q < ch[2]; ++q) Lg[(size_t)j * m + ch[0] + q] = r[off + ch[1] + q];
+    off += ch[1] + ch[2];
+  }
+  std::vector<double> c(k);
+  for (int i = 0; i < k; ++i) {
+    double t = sv[i];
+    for (int q = 0; q < i; ++q) t -= Lg[(size_t)i * m + q] * hcol[q];
+    hcol[i] = t;
+    c[i] = -t;
+  }
+  tr::launch_multi_axpy_norm(n, k, X.data(), c.data(), w, h->dot_partial, h->dot_blocks, h->dot_out, st);
+  double nrm2 = 0;
+  HIPCHK(hipMemcpyAsync(&nrm2, h->dot_out, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return nrm2;
 }
 
 // Restarted right-preconditioned GMRES(m), x0 = 0, modified Gram-Schmidt.
@@ -940,7 +982,7 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
     return TR_OK;
   }
   HIPCHK(hipMemcpyAsync(h->V[0], b, n * sizeof(double), hipMemcpyDeviceToDevice, st));  // r0 = b
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), Lg((size_t)m * m), hcol(m + 1);
   for (int cycle = 0; cycle <= o->max_restarts; ++cycle) {
     tbegin(h, C_ORTH);
     const double beta = std::sqrt(dot(h, h->V[0], h->V[0], n, st));
@@ -964,15 +1006,10 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       precondition(h, o->prec_mode, adj, h->V[j], zj, st);
       apply_A(h, adj, zj, w, st);
       stats->iters++;
-      // modified Gram-Schmidt; each projection is fused with the next
-      // inner product (with V[i+1], and finally with w itself)
+      // modified Gram-Schmidt (two passes over the basis, see arnoldi_orth)
       tbegin(h, C_ORTH);
-      double hcur = dot(h, w, h->V[0], n, st);
-      for (int i = 0; i <= j; ++i) {
-        H[(size_t)i * m + j] = hcur;
-        hcur = axpy_dot(h, hcur, h->V[i], w, i < j ? h->V[i + 1] : w, n, st);
-      }
-      const double hn = std::sqrt(hcur);
+      const double hn = std::sqrt(arnoldi_orth(h, j, w, Lg, m, hcol.data(), n, st));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
       tend(h);
       H[(size_t)(j + 1) * m + j] = hn;
       for (int i = 0; i < j; ++i) {
