@@ -70,6 +70,9 @@ void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st
 void launch_coarse_flow(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                         const OrdInfo *ord, const Planes &pl, const Grid &g, const int *wave_off, const int *slots,
                         int waves, bool adjoint, unsigned *cnt, int *err, hipStream_t st);
+void launch_coarse_brick(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
+                         const OrdInfo *ord, const Grid &g, const int *wave_off, const int *slots, int waves,
+                         bool adjoint, unsigned *cnt, long long nbricks, int *err, hipStream_t st);
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                       const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,

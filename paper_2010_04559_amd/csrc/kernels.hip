@@ -545,11 +545,30 @@ __global__ void k_sigma_planes(const double *__restrict__ sig_t, const double *_
 // butterflies (__shfl_xor over the node bits), after which lane b holds
 // spectral mode b and solves that mode's complex 3x3 system (the three
 // ordinates coupled by the self-scatter block) on its own.
-__device__ __forceinline__ double shx(double v, int mask) { return __shfl_xor(v, mask, 64); }
-
-__device__ __forceinline__ cx<double> shx(cx<double> v, int mask) {
-  return {__shfl_xor(v.re, mask, 64), __shfl_xor(v.im, mask, 64)};
+//
+// Exchanges across the node bits 1, 2 and 4 stay inside 8-lane groups and
+// use DPP moves (VALU, no LDS round trip): quad permutations for bits 1
+// and 2; for bit 4 the half-row mirror (lane i of 8 takes lane 7 - i)
+// followed by the quad reversal (i takes i ^ 3), together i ^ 4.
+__device__ __forceinline__ int dpp_xor(int v, int mask) {
+  switch (mask) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    case 4: {
+      const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+      return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);         // quad_perm 3,2,1,0
+    }
+    default: return __shfl_xor(v, mask, 64);
+  }
 }
+
+__device__ __forceinline__ double shx(double v, int mask) {
+  const long long x = __double_as_longlong(v);
+  const int lo = dpp_xor((int)(x & 0xFFFFFFFFLL), mask), hi = dpp_xor((int)(x >> 32), mask);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ cx<double> shx(cx<double> v, int mask) { return {shx(v.re, mask), shx(v.im, mask)}; }
 
 // Node-space 2x2 operator along axis d: out = m_same * own + m_other * partner
 // (used for the symmetric mass shapes).
@@ -978,6 +997,220 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
   }
 }
 
+// Brick form of the dataflow solve (3-D, even cell counts): one wave
+// updates a 2 x 2 x 2 brick of cells for one (sweep, octant), 8 lanes per
+// cell.  Dependencies and counters are per brick, exactly as the cell form
+// has them per cell, so fewer dependent steps cross the device (the brick
+// grid is half as wide).  Inside the brick the cells are taken in the four
+// diagonal planes of the sweep direction; the inflow a cell takes from a
+// neighbour in the same brick comes from that cell's lanes by a shuffle,
+// from a neighbour outside it by a device-coherent load after the wait.
+// The part of each cell's right-hand side that does not depend on the
+// inflow (source and scatter from the other octants' values), and the
+// factorised 3 x 3 mode systems, are formed once per brick.
+// Slot items: octant << 29 | c << 22 | brick index (one brick per slot).
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, double *u,
+                                                  const double *__restrict__ G, const double *__restrict__ sig_t,
+                                                  const double *__restrict__ sig_s,
+                                                  const OrdInfo *__restrict__ ord, Grid g,
+                                                  const int *__restrict__ wave_off, const int *__restrict__ slots,
+                                                  int nwaves, unsigned *cnt, int *err) {
+  constexpr int DIM = 3, NS = 8;
+  __shared__ double G_lds[24 * 24];
+  __shared__ OrdInfo ord_lds[24];
+  for (int i = threadIdx.x; i < 24 * 24; i += blockDim.x) G_lds[i] = G[i];
+  if (threadIdx.x < 24) ord_lds[threadIdx.x] = ord[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int b = lane & 7;    // Q1 node of the lane's cell
+  const int grp = lane >> 3; // cell of the brick: bit d = position along d in sweep order
+  const int sub = (grp & 1) + ((grp >> 1) & 1) + ((grp >> 2) & 1);  // its diagonal plane in the brick
+  const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (wave >= nwaves) return;
+  const int nb[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+  const long long S = g.S;
+  const int s0 = wave_off[wave], s1 = wave_off[wave + 1];
+  for (int sl = s0; sl < s1; ++sl) {
+    const int item = __builtin_amdgcn_readfirstlane(slots[sl]);
+    const int octant = (item >> 29) & 7;
+    const unsigned c = (unsigned)((item >> 22) & 127);
+    const int B = item & ((1 << 22) - 1);
+    const int k0 = 3 * octant;
+    const int flip = ord_lds[k0].flip;
+    const int bx[3] = {B % nb[0], (B / nb[0]) % nb[1], B / (nb[0] * nb[1])};
+    int ix[3], pc[3], nbr[3];
+    long long jn[3];
+    bool ext[3];
+    long long mydep = -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const bool rev = (((flip >> d) & 1) != 0) != ADJ;  // sweep runs towards lower indices
+      const int pb = rev ? nb[d] - 1 - bx[d] : bx[d];
+      const int lp = (grp >> d) & 1;
+      pc[d] = 2 * pb + lp;
+      ix[d] = rev ? g.n[d] - 1 - pc[d] : pc[d];
+      ext[d] = lp == 0 && pc[d] > 0;  // inflow from the neighbouring brick
+      nbr[d] = rev ? ix[d] + 1 : ix[d] - 1;
+      if (grp == 0 && b == 1 + d && pb > 0) {
+        int by[3] = {bx[0], bx[1], bx[2]};
+        by[d] += rev ? 1 : -1;
+        mydep = by[0] + (long long)nb[0] * (by[1] + (long long)nb[1] * by[2]);
+      }
+    }
+    if (lane == 0) mydep = B;
+    const long long j = cell_index(ix, g);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int nx[3] = {ix[0], ix[1], ix[2]};
+      nx[d] = ext[d] ? nbr[d] : ix[d];
+      jn[d] = cell_index(nx, g);
+    }
+    double fv[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fv[m] = f[(k0 + m) * S + j * NS + b];
+    const double st = sig_t[j], ss = sig_s[j];
+
+    bool ready = mydep < 0;
+    long spins = 0;
+    bool failed = false;
+    while (true) {
+      if (!ready) {
+        const unsigned v = __hip_atomic_load(cnt + mydep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ready = lane == 0 ? v == c : v >= c + 1;
+      }
+      if (__ballot(!ready) == 0) break;
+      if (++spins > (1L << 22) ||
+          (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        failed = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (__ballot(failed)) return;  // wave-uniform
+    asm volatile("" ::: "memory");
+
+    // values of earlier updates: all 24 ordinates at the lane's node and
+    // the inflow traces from outside the brick
+    const double *up = u + j * NS + b;
+    double uv[24];
+#pragma unroll
+    for (int kp = 0; kp < 24; ++kp) uv[kp] = ld_dev(up + kp * S);
+    double tex[3][DIM];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int fl = (flip >> d) & 1;
+        const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+        const int bn = (b & ~(1 << d)) | (nbit << d);
+        tex[m][d] = ext[d] ? ld_dev(u + (k0 + m) * S + jn[d] * NS + bn) : 0.0;
+      }
+    // inflow-independent right-hand side
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kp = 0; kp < 24; ++kp) {
+      const double w = (kp / 3 == octant) ? 0.0 : uv[kp];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) acc[m] += G_lds[(k0 + m) * 24 + kp] * w;
+    }
+    double vb[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      vb[m] = ADJ ? fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false) : fv[m] + ss * acc[m];
+    // this lane's mode system, factorised: M = L U (unit L)
+    cx<double> M[3][3];
+    const double r2 = 1.41421356237309504880;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const OrdInfo &o = ord_lds[k0 + m];
+#pragma unroll
+      for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-ss * G_lds[(k0 + m) * 24 + k0 + mp], 0.0};
+      double re = st, im = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        re += 2.0 * o.c[d];
+        im += (((b >> d) & 1) ? -r2 : r2) * o.c[d];
+      }
+      M[m][m].re += re;
+      M[m][m].im += im;
+    }
+    cx<double> Lf[3][3], dinv[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      dinv[p] = cinv(M[p][p]);
+#pragma unroll
+      for (int i = p + 1; i < 3; ++i) {
+        Lf[i][p] = cmul(M[i][p], dinv[p]);
+#pragma unroll
+        for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(Lf[i][p], M[p][jj]));
+      }
+    }
+    AxisXf<double> ax[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ax[d] = axis_xf<double>((flip >> d) & 1, ADJ);
+
+    double res[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      double v[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const OrdInfo &o = ord_lds[k0 + m];
+        v[m] = vb[m];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int fl = (flip >> d) & 1;
+          const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+          const int bn = (b & ~(1 << d)) | (nbit << d);
+          // the upwind cell inside the brick finished in the previous plane
+          const double tin = __shfl(res[m], ((grp ^ (1 << d)) << 3) | bn, 64);
+          double t = ((grp >> d) & 1) ? tin : tex[m][d];
+          if (!ADJ) {
+            const int own0 = fl ? 1 : 0;
+            v[m] += (((b >> d) & 1) == own0 ? 4.0 : -2.0) * o.c[d] * t;
+          } else {
+            double hs = 1.0;
+#pragma unroll
+            for (int e = 0; e < DIM; ++e)
+              if (e != d) hs *= g.h[e];
+            t = lane_mass<DIM>(t, (NS - 1) & ~(1 << d), false);
+            const int own1 = fl ? 0 : 1;
+            if (((b >> d) & 1) == own1) v[m] += o.a[d] * hs * t;
+          }
+        }
+      }
+      cx<double> r[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) r[m] = lane_forward<DIM>(v[m], b, ax);
+#pragma unroll
+      for (int i = 1; i < 3; ++i)
+#pragma unroll
+        for (int q = 0; q < i; ++q) r[i] = csub(r[i], cmul(Lf[i][q], r[q]));
+#pragma unroll
+      for (int q = 2; q >= 0; --q) {
+        cx<double> t = r[q];
+#pragma unroll
+        for (int jj = q + 1; jj < 3; ++jj) t = csub(t, cmul(M[q][jj], r[jj]));
+        r[q] = cmul(t, dinv[q]);
+      }
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        double out = lane_backward<DIM>(r[m], b, ax);
+        if (ADJ) out = lane_mass<DIM>(out, NS - 1, true) * (1.0 / g.vol);
+        if (sub == p) res[m] = out;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) st_dev(u + (k0 + m) * S + j * NS + b, res[m]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the brick's stores are acknowledged
+    asm volatile("" ::: "memory");
+    if (lane == 0) __hip_atomic_store(cnt + B, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // ------------------------------------------------------------- conversions
 template <typename Tin, typename Tout>
 __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, int P, long long S,
@@ -1241,7 +1474,7 @@ __global__ void k_apply(const double *__restrict__ x, const double *__restrict__
 template <int DIM>
 __device__ __forceinline__ double lane_axis(double v, int b, int d, double m00, double m01, double m10,
                                             double m11) {
-  const double p = __shfl_xor(v, 1 << d, 64);
+  const double p = shx(v, 1 << d);
   return ((b >> d) & 1) ? m10 * p + m11 * v : m00 * v + m01 * p;
 }
 
@@ -1775,6 +2008,21 @@ void launch_coarse_flow(const double *f, double *u, const double *G, const doubl
   void *args[] = {(void *)&f,     (void *)&u,     (void *)&G,   (void *)&sig_t, (void *)&sig_s,
                   (void *)&ord,   (void *)&pl,    (void *)&g,   (void *)&wave_off, (void *)&slots,
                   (void *)&waves, (void *)&cnt,   (void *)&err};
+  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st) != hipSuccess)
+    throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
+}
+
+void launch_coarse_brick(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
+                         const OrdInfo *ord, const Grid &g, const int *wave_off, const int *slots, int waves,
+                         bool adjoint, unsigned *cnt, long long nbricks, int *err, hipStream_t st) {
+  if (g.dim != 3 || (g.n[0] | g.n[1] | g.n[2]) & 1) throw std::runtime_error("brick Gauss-Seidel needs even 3-D grids");
+  launch_fill<double>(u, 24LL * g.S, 0.0, st);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nbricks)), dim3(kBlock), 0, st, cnt, nbricks);
+  void *fn = adjoint ? (void *)k_gs_brick<true> : (void *)k_gs_brick<false>;
+  const int blocks = (waves + 3) / 4;
+  void *args[] = {(void *)&f,   (void *)&u,        (void *)&G,     (void *)&sig_t, (void *)&sig_s,
+                  (void *)&ord, (void *)&g,        (void *)&wave_off, (void *)&slots, (void *)&waves,
+                  (void *)&cnt, (void *)&err};
   if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st) != hipSuccess)
     throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
 }

@@ -176,7 +176,12 @@ struct tr_handle {
     // dataflow form: per-wave slot lists (empty when not applicable)
     int waves = 0;
     int *wave_off = nullptr, *slots = nullptr;
+    // brick form (3-D, even grids): one 2 x 2 x 2 brick per slot
+    bool brick = false;
+    long long nbricks = 0;
+    int brick_steps = 0;
   };
+  bool gs_brick = true;       // dataflow solve over 2 x 2 x 2 bricks where the grid allows
   bool gs_flow = true;        // coarse solve without grid barriers
   bool gs_coh = true;         // barrier form: device-coherent iterate accesses
   unsigned *gs_cnt = nullptr;  // [cells] update counters of the dataflow solve
@@ -675,6 +680,71 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
     sc.wave_off = h->upload(woff);
     sc.slots = h->upload(sl);
   }
+  if (flow_ok && h->gs_brick && !adj && g.dim == 3 && !((g.n[0] | g.n[1] | g.n[2]) & 1)) {
+    // the same schedule on the grid of 2 x 2 x 2 bricks, in each sweep's
+    // direction.  Forward only: the adjoint's inflow terms carry face mass
+    // exchanges that make the four in-brick planes slower than the cell
+    // form's extra dependent steps (32^3, 10 sweeps: 13.8 against 13.3 ms;
+    // forward 9.3 against 11.6 ms).
+    const int nb[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+    const long long NB = (long long)nb[0] * nb[1] * nb[2];
+    std::vector<std::array<int, 3>> pbs;
+    for (int z = 0; z < nb[2]; ++z)
+      for (int y = 0; y < nb[1]; ++y)
+        for (int x = 0; x < nb[0]; ++x) pbs.push_back({x, y, z});
+    std::stable_sort(pbs.begin(), pbs.end(), [](const std::array<int, 3> &a, const std::array<int, 3> &b) {
+      return a[0] + a[1] + a[2] < b[0] + b[1] + b[2];
+    });
+    auto bidx = [&](const int *bx) { return bx[0] + (long long)nb[0] * (bx[1] + (long long)nb[1] * bx[2]); };
+    std::vector<int> lastb(NB, -1);
+    std::vector<std::vector<int>> bsteps;
+    for (int sweep = 0; sweep < nu; ++sweep)
+      for (int oi = 0; oi < 8; ++oi) {
+        const int o = h->octant_order[oi];
+        const unsigned c = 8u * sweep + oi;
+        for (auto &pb : pbs) {
+          int bx[3];
+          bool rev[3];
+          for (int d = 0; d < 3; ++d) {
+            rev[d] = (((o >> d) & 1) != 0) != adj;
+            bx[d] = rev[d] ? nb[d] - 1 - pb[d] : pb[d];
+          }
+          const long long B = bidx(bx);
+          int t = lastb[B] + 1;
+          for (int d = 0; d < 3; ++d) {
+            if (pb[d] == 0) continue;
+            int by[3] = {bx[0], bx[1], bx[2]};
+            by[d] += rev[d] ? 1 : -1;
+            t = std::max(t, lastb[bidx(by)] + 1);
+          }
+          lastb[B] = t;
+          if ((int)bsteps.size() <= t) bsteps.resize(t + 1);
+          bsteps[t].push_back((int)(((unsigned)o << 29) | (c << 22) | (unsigned)B));
+        }
+      }
+    int bmx = 0;
+    for (auto &st : bsteps) bmx = std::max(bmx, (int)st.size());
+    // four waves per brick of the widest step, at most 1024 (co-resident)
+    const int W = 4 * std::max(1, std::min(256, bmx));
+    std::vector<std::vector<int>> lists(W);
+    int next = 0;
+    for (auto &st : bsteps)
+      for (int it : st) {
+        lists[next].push_back(it);
+        next = (next + 1) % W;
+      }
+    std::vector<int> woff{0}, sl;
+    for (auto &L : lists) {
+      sl.insert(sl.end(), L.begin(), L.end());
+      woff.push_back((int)sl.size());
+    }
+    sc.brick = true;
+    sc.nbricks = NB;
+    sc.brick_steps = (int)bsteps.size();
+    sc.waves = W;
+    sc.wave_off = h->upload(woff);
+    sc.slots = h->upload(sl);
+  }
   h->gs_sched.push_back(sc);
   return h->gs_sched.back();
 }
@@ -708,6 +778,15 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
     HIPCHK(hipMemset(h->bar_release, 0, sizeof(unsigned)));
     HIPCHK(hipDeviceSynchronize());
     h->bar_gen = 0;
+  }
+  if (h->gs_flow && sc.brick) {
+    if (!h->gs_cnt) h->gs_cnt = h->alloc<unsigned>(h->g.C);
+    tbegin(h, C_COARSE);
+    tr::launch_coarse_brick(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->g, sc.wave_off, sc.slots,
+                            sc.waves, adj, h->gs_cnt, sc.nbricks, h->bar_err, st);
+    tend(h);
+    h->coarse_steps = sc.brick_steps;
+    return;
   }
   if (h->gs_flow && sc.waves > 0) {
     if (!h->gs_cnt) h->gs_cnt = h->alloc<unsigned>(h->g.C);
@@ -1132,11 +1211,13 @@ int tr_setup(const tr_problem *prob, tr_handle **out) {
   int rc = translate([&]() {
     h = new tr_handle();
     // TR_COARSE_GS=barrier (barrier_fence: with cache maintenance fences)
-    // selects the step-synchronous coarse solve, for comparison; the default
-    // is the dataflow form
+    // selects the step-synchronous coarse solve, TR_COARSE_GS=cell the
+    // dataflow form per cell, for comparison; the default is the dataflow
+    // form per brick where the grid allows it, else per cell
     const char *gs = std::getenv("TR_COARSE_GS");
     h->gs_flow = !(gs && std::strncmp(gs, "barrier", 7) == 0);
     h->gs_coh = !(gs && std::strcmp(gs, "barrier_fence") == 0);
+    h->gs_brick = !(gs && std::strcmp(gs, "cell") == 0);
     build(h, prob);
     return TR_OK;
   });

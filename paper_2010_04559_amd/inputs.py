@@ -189,8 +189,13 @@ def config5(n=32):
 
 def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=True, source=True,
                   mg_orders=None, restart=10):
-    """Small random heterogeneous problem for parity tests."""
-    nn = (n, n, n if dim == 3 else 1)
+    """Small random heterogeneous problem for parity tests (n: cells per
+    axis, or a tuple of per-axis counts)."""
+    if isinstance(n, (tuple, list)):
+        nn = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+        n = "x".join(str(v) for v in n)
+    else:
+        nn = (n, n, n if dim == 3 else 1)
     C = int(np.prod(nn[:dim]))
     rng = np.random.default_rng(seed)
     st = rng.uniform(0.5, 4.0, C)

@@ -166,3 +166,17 @@ def test_coarse_gs_multiblock_planes():
     f = _rand(lv0.A * lv0.grid.S, 16)
     assert rel(to_np(pr.tr.coarse_gs(to_dev(f), 2)), pr.op.mg.coarse_gs(f, 2)) < 1e-11
     assert rel(to_np(pr.tr.coarse_gs(to_dev(f), 2, adjoint=True)), pr.op.mg.coarse_gs(f, 2, adjoint=True)) < 1e-11
+
+
+def test_coarse_gs_bricks_noncubic():
+    """An even 6 x 4 x 8 grid: the forward solve runs over 2 x 2 x 2 bricks
+    (brick counts differ per axis); the adjoint over cells."""
+    prob = small(dim=3, n=(6, 4, 8), level=0, order=3, seed=17)
+    print("case 6x4x8 level 0", flush=True)
+    pr = Pair(prob)
+    lv0 = pr.op.mg.levels[0]
+    f = _rand(lv0.A * lv0.grid.S, 18)
+    for nu in (1, 3):
+        assert rel(to_np(pr.tr.coarse_gs(to_dev(f), nu)), pr.op.mg.coarse_gs(f, nu)) < 1e-11
+        assert rel(to_np(pr.tr.coarse_gs(to_dev(f), nu, adjoint=True)),
+                   pr.op.mg.coarse_gs(f, nu, adjoint=True)) < 1e-11
