@@ -915,6 +915,140 @@ __global__ __launch_bounds__(TB) void k_gs_solve(const double *__restrict__ f, d
   }
 }
 
+// Bounded wait of a wave on update counters: each lane with dep >= 0 waits
+// for cnt[dep] == c (own = true) or cnt[dep] >= c + 1.  Returns false for
+// the whole wave after a timeout anywhere (the error word is set).
+__device__ __forceinline__ bool wait_counters(unsigned *cnt, long long dep, unsigned c, bool own, int *err) {
+  bool ready = dep < 0;
+  long spins = 0;
+  bool failed = false;
+  while (true) {
+    if (!ready) {
+      const unsigned v = __hip_atomic_load(cnt + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ready = own ? v == c : v >= c + 1;
+    }
+    if (__ballot(!ready) == 0) break;
+    if (++spins > (1L << 22) ||
+        (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      failed = true;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return __ballot(failed) == 0;
+}
+
+// Per-cell pieces of a Gauss-Seidel update shared by the dataflow
+// kernels.  gs_cell_setup forms what depends only on the cell's own values
+// (the 24 ordinates at the lane's node): the right-hand side without the
+// inflow, and the factorised 3 x 3 system of the lane's spectral mode.
+// gs_cell_solve adds the inflow traces t (zero where there is no upwind
+// neighbour) and solves.
+template <int DIM>
+struct GsCell {
+  double vb[3];
+  cx<double> U[3][3], Lf[3][3], dinv[3];
+};
+
+template <int DIM, bool ADJ>
+__device__ __forceinline__ void gs_cell_setup(GsCell<DIM> &cs, const double *uv, const double *fv, double st,
+                                              double ss, int octant, int b, const double *G_lds,
+                                              const OrdInfo *ord_lds, const Grid &g) {
+  constexpr int NS = 1 << DIM;
+  const int k0 = 3 * octant;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kp = 0; kp < 24; ++kp) {
+    const double w = (kp / 3 == octant) ? 0.0 : uv[kp];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc[m] += G_lds[(k0 + m) * 24 + kp] * w;
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    cs.vb[m] = ADJ ? fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false) : fv[m] + ss * acc[m];
+  // this lane's mode system M = L U (unit L)
+  cx<double> (&M)[3][3] = cs.U;
+  const double r2 = 1.41421356237309504880;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const OrdInfo &o = ord_lds[k0 + m];
+#pragma unroll
+    for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-ss * G_lds[(k0 + m) * 24 + k0 + mp], 0.0};
+    double re = st, im = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      re += 2.0 * o.c[d];
+      im += (((b >> d) & 1) ? -r2 : r2) * o.c[d];
+    }
+    M[m][m].re += re;
+    M[m][m].im += im;
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    cs.dinv[p] = cinv(M[p][p]);
+#pragma unroll
+    for (int i = p + 1; i < 3; ++i) {
+      cs.Lf[i][p] = cmul(M[i][p], cs.dinv[p]);
+#pragma unroll
+      for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(cs.Lf[i][p], M[p][jj]));
+    }
+  }
+}
+
+template <int DIM, bool ADJ>
+__device__ __forceinline__ void gs_cell_solve(const GsCell<DIM> &cs, const double (&t)[3][DIM], int octant,
+                                              int flip, int b, const OrdInfo *ord_lds, const Grid &g,
+                                              double *out) {
+  constexpr int NS = 1 << DIM;
+  const int k0 = 3 * octant;
+  double v[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const OrdInfo &o = ord_lds[k0 + m];
+    v[m] = cs.vb[m];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int fl = (flip >> d) & 1;
+      if (!ADJ) {
+        const int own0 = fl ? 1 : 0;
+        v[m] += (((b >> d) & 1) == own0 ? 4.0 : -2.0) * o.c[d] * t[m][d];
+      } else {
+        double hs = 1.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+          if (e != d) hs *= g.h[e];
+        const double tm = lane_mass<DIM>(t[m][d], (NS - 1) & ~(1 << d), false);
+        const int own1 = fl ? 0 : 1;
+        if (((b >> d) & 1) == own1) v[m] += o.a[d] * hs * tm;
+      }
+    }
+  }
+  AxisXf<double> ax[3];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ax[d] = axis_xf<double>((flip >> d) & 1, ADJ);
+  cx<double> r[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) r[m] = lane_forward<DIM>(v[m], b, ax);
+#pragma unroll
+  for (int i = 1; i < 3; ++i)
+#pragma unroll
+    for (int q = 0; q < i; ++q) r[i] = csub(r[i], cmul(cs.Lf[i][q], r[q]));
+#pragma unroll
+  for (int q = 2; q >= 0; --q) {
+    cx<double> x = r[q];
+#pragma unroll
+    for (int jj = q + 1; jj < 3; ++jj) x = csub(x, cmul(cs.U[q][jj], r[jj]));
+    r[q] = cmul(x, cs.dinv[q]);
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double o = lane_backward<DIM>(r[m], b, ax);
+    if (ADJ) o = lane_mass<DIM>(o, NS - 1, true) * (1.0 / g.vol);
+    out[m] = o;
+  }
+}
+
 // Dataflow form of the same coarse solve: no grid-wide barrier.  Every
 // cell j has a counter cnt[j] of completed updates; the update with count
 // c = 8 sweep + (octant's position in the order) may run once cnt[j] == c
@@ -930,8 +1064,11 @@ __global__ __launch_bounds__(TB) void k_gs_solve(const double *__restrict__ f, d
 // cooperative launch).  Publishing: the wave's stores are released at
 // device scope (device-coherent stores, waited for), then each group's
 // leader stores c + 1 in cnt[j]; waiting: relaxed polls of the counters,
-// after which the iterate is read with device-coherent loads.  Spins are
-// bounded and set the error word, which every waiting wave checks.
+// after which the iterate is read with device-coherent loads.  The wait is
+// in two parts: the cell's own counter first, after which the scatter from
+// the other octants and the factorised mode systems are formed, then the
+// neighbours' counters and the inflow traces.  Spins are bounded and set
+// the error word, which every waiting wave checks.
 // Slot items: octant << 29 | c << 22 | cell-list index (all ones: empty;
 // c <= 126 for real items).
 template <int DIM, bool ADJ>
@@ -952,6 +1089,7 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
   const int grp = lane / NS;  // 64 / 2^dim groups per wave (8 in 3-D)
   const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (wave >= nwaves) return;
+  const long long S = g.S;
   const int s0 = wave_off[wave], s1 = wave_off[wave + 1];
   for (int sl = s0; sl < s1; ++sl) {
     const int item = slots[(long long)sl * (64 / NS) + grp];
@@ -959,35 +1097,42 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
     const int octant = active ? (item >> 29) & 7 : 0;
     const unsigned c = active ? (unsigned)((item >> 22) & 127) : 0u;
     const int idx = active ? item & ((1 << 22) - 1) : 0;
-    // read-only data of the update first (overlapping the waits), then the
-    // dependencies: lane 0 of the group polls the cell's own counter, lane
-    // 1 + d the upwind (adjoint: downwind) neighbour along axis d
+    const int k0 = 3 * octant;
+    // read-only data of the update first (overlapping the waits)
     const GsPrep<DIM> q = gs_prepare<DIM, ADJ>((octant << 28) | idx, f, sig_t, sig_s, ord_lds, pl, g, b);
     const long long jself = q.j;
-    long long mydep = b == 0 ? jself : -1;
+    // wait for the cell's own earlier updates (lane 0 of each group), form
+    // what depends on them only, then wait for the upwind (adjoint:
+    // downwind) neighbours (lane 1 + d polls axis d)
+    if (!wait_counters(cnt, active && b == 0 ? jself : -1, c, true, err)) return;
+    asm volatile("" ::: "memory");
+    const double *up = u + jself * NS + b;
+    double uv[24];
+#pragma unroll
+    for (int kp = 0; kp < 24; ++kp) uv[kp] = ld_dev(up + kp * S);
+    GsCell<DIM> cs;
+    gs_cell_setup<DIM, ADJ>(cs, uv, q.fv, q.st, q.ss, octant, b, G_lds, ord_lds, g);
+    long long dep = -1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
-      if (q.has[d] && b == 1 + d) mydep = q.jn[d];
-    bool ready = !active || mydep < 0;
-    long spins = 0;
-    bool failed = false;
-    while (true) {
-      if (!ready) {
-        const unsigned v = __hip_atomic_load(cnt + mydep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ready = b == 0 ? v == c : v >= c + 1;
+      if (active && q.has[d] && b == 1 + d) dep = q.jn[d];
+    if (!wait_counters(cnt, dep, c, false, err)) return;
+    asm volatile("" ::: "memory");
+    double t[3][DIM];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int fl = (q.flip >> d) & 1;
+        const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+        const int bn = (b & ~(1 << d)) | (nbit << d);
+        t[m][d] = q.has[d] ? ld_dev(u + (k0 + m) * S + q.jn[d] * NS + bn) : 0.0;
       }
-      if (__ballot(!ready) == 0) break;
-      if (++spins > (1L << 22) ||
-          (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        failed = true;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    if (__ballot(failed)) return;  // wave-uniform
-    asm volatile("" ::: "memory");  // iterate loads stay after the waits
-    gs_update<DIM, ADJ, true>(q, u, G_lds, ord_lds, g, active, b);
+    double out[3];
+    gs_cell_solve<DIM, ADJ>(cs, t, octant, q.flip, b, ord_lds, g, out);
+    if (active)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) st_dev(u + (k0 + m) * S + jself * NS + b, out[m]);
     // the group's iterate stores are acknowledged at the device coherence
     // point before its counter moves
     asm volatile("" ::: "memory");
@@ -1007,7 +1152,9 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
 // from a neighbour outside it by a device-coherent load after the wait.
 // The part of each cell's right-hand side that does not depend on the
 // inflow (source and scatter from the other octants' values), and the
-// factorised 3 x 3 mode systems, are formed once per brick.
+// factorised 3 x 3 mode systems, are formed once per brick, between the
+// wait for the brick's own earlier update and the wait for the upwind
+// bricks.
 // Slot items: octant << 29 | c << 22 | brick index (one brick per slot).
 template <bool ADJ>
 __global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, double *u,
@@ -1071,32 +1218,21 @@ __global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, 
     for (int m = 0; m < 3; ++m) fv[m] = f[(k0 + m) * S + j * NS + b];
     const double st = sig_t[j], ss = sig_s[j];
 
-    bool ready = mydep < 0;
-    long spins = 0;
-    bool failed = false;
-    while (true) {
-      if (!ready) {
-        const unsigned v = __hip_atomic_load(cnt + mydep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ready = lane == 0 ? v == c : v >= c + 1;
-      }
-      if (__ballot(!ready) == 0) break;
-      if (++spins > (1L << 22) ||
-          (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        failed = true;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    if (__ballot(failed)) return;  // wave-uniform
+    // wait for the brick's own earlier updates (lane 0), then form what
+    // depends on them only; then wait for the upwind bricks (lanes 1..3)
+    if (!wait_counters(cnt, lane == 0 ? mydep : -1, c, true, err)) return;
     asm volatile("" ::: "memory");
-
-    // values of earlier updates: all 24 ordinates at the lane's node and
-    // the inflow traces from outside the brick
+    // the brick's own values: all 24 ordinates at the lane's node
     const double *up = u + j * NS + b;
     double uv[24];
 #pragma unroll
     for (int kp = 0; kp < 24; ++kp) uv[kp] = ld_dev(up + kp * S);
+    GsCell<DIM> cs;
+    gs_cell_setup<DIM, ADJ>(cs, uv, fv, st, ss, octant, b, G_lds, ord_lds, g);
+
+    if (!wait_counters(cnt, lane != 0 ? mydep : -1, c, false, err)) return;
+    asm volatile("" ::: "memory");
+    // inflow traces from outside the brick
     double tex[3][DIM];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
@@ -1107,58 +1243,13 @@ __global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, 
         const int bn = (b & ~(1 << d)) | (nbit << d);
         tex[m][d] = ext[d] ? ld_dev(u + (k0 + m) * S + jn[d] * NS + bn) : 0.0;
       }
-    // inflow-independent right-hand side
-    double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kp = 0; kp < 24; ++kp) {
-      const double w = (kp / 3 == octant) ? 0.0 : uv[kp];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) acc[m] += G_lds[(k0 + m) * 24 + kp] * w;
-    }
-    double vb[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-      vb[m] = ADJ ? fv[m] + ss * g.vol * lane_mass<DIM>(acc[m], NS - 1, false) : fv[m] + ss * acc[m];
-    // this lane's mode system, factorised: M = L U (unit L)
-    cx<double> M[3][3];
-    const double r2 = 1.41421356237309504880;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const OrdInfo &o = ord_lds[k0 + m];
-#pragma unroll
-      for (int mp = 0; mp < 3; ++mp) M[m][mp] = cx<double>{-ss * G_lds[(k0 + m) * 24 + k0 + mp], 0.0};
-      double re = st, im = 0.0;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        re += 2.0 * o.c[d];
-        im += (((b >> d) & 1) ? -r2 : r2) * o.c[d];
-      }
-      M[m][m].re += re;
-      M[m][m].im += im;
-    }
-    cx<double> Lf[3][3], dinv[3];
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      dinv[p] = cinv(M[p][p]);
-#pragma unroll
-      for (int i = p + 1; i < 3; ++i) {
-        Lf[i][p] = cmul(M[i][p], dinv[p]);
-#pragma unroll
-        for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(Lf[i][p], M[p][jj]));
-      }
-    }
-    AxisXf<double> ax[3];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) ax[d] = axis_xf<double>((flip >> d) & 1, ADJ);
 
     double res[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      double v[3];
+      double t[3][DIM];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const OrdInfo &o = ord_lds[k0 + m];
-        v[m] = vb[m];
+      for (int m = 0; m < 3; ++m)
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
           const int fl = (flip >> d) & 1;
@@ -1166,41 +1257,13 @@ __global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, 
           const int bn = (b & ~(1 << d)) | (nbit << d);
           // the upwind cell inside the brick finished in the previous plane
           const double tin = __shfl(res[m], ((grp ^ (1 << d)) << 3) | bn, 64);
-          double t = ((grp >> d) & 1) ? tin : tex[m][d];
-          if (!ADJ) {
-            const int own0 = fl ? 1 : 0;
-            v[m] += (((b >> d) & 1) == own0 ? 4.0 : -2.0) * o.c[d] * t;
-          } else {
-            double hs = 1.0;
-#pragma unroll
-            for (int e = 0; e < DIM; ++e)
-              if (e != d) hs *= g.h[e];
-            t = lane_mass<DIM>(t, (NS - 1) & ~(1 << d), false);
-            const int own1 = fl ? 0 : 1;
-            if (((b >> d) & 1) == own1) v[m] += o.a[d] * hs * t;
-          }
+          t[m][d] = ((grp >> d) & 1) ? tin : tex[m][d];
         }
-      }
-      cx<double> r[3];
+      double out[3];
+      gs_cell_solve<DIM, ADJ>(cs, t, octant, flip, b, ord_lds, g, out);
 #pragma unroll
-      for (int m = 0; m < 3; ++m) r[m] = lane_forward<DIM>(v[m], b, ax);
-#pragma unroll
-      for (int i = 1; i < 3; ++i)
-#pragma unroll
-        for (int q = 0; q < i; ++q) r[i] = csub(r[i], cmul(Lf[i][q], r[q]));
-#pragma unroll
-      for (int q = 2; q >= 0; --q) {
-        cx<double> t = r[q];
-#pragma unroll
-        for (int jj = q + 1; jj < 3; ++jj) t = csub(t, cmul(M[q][jj], r[jj]));
-        r[q] = cmul(t, dinv[q]);
-      }
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        double out = lane_backward<DIM>(r[m], b, ax);
-        if (ADJ) out = lane_mass<DIM>(out, NS - 1, true) * (1.0 / g.vol);
-        if (sub == p) res[m] = out;
-      }
+      for (int m = 0; m < 3; ++m)
+        if (sub == p) res[m] = out[m];
     }
 #pragma unroll
     for (int m = 0; m < 3; ++m) st_dev(u + (k0 + m) * S + j * NS + b, res[m]);

@@ -724,8 +724,10 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
       }
     int bmx = 0;
     for (auto &st : bsteps) bmx = std::max(bmx, (int)st.size());
-    // four waves per brick of the widest step, at most 1024 (co-resident)
-    const int W = 4 * std::max(1, std::min(256, bmx));
+    // two waves per brick of the widest step, at most 512 (co-resident at
+    // one wave per SIMD on 128 CUs); 512 to 1024 waves measured alike on
+    // the 32^3 problem
+    const int W = 2 * std::max(2, std::min(256, bmx));
     std::vector<std::vector<int>> lists(W);
     int next = 0;
     for (auto &st : bsteps)
