@@ -238,9 +238,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs<T> a) {
 //  * Store waves copy each finished plane from LDS to global memory, so no
 //    compute wave ever waits for a store (gfx9 counts loads and stores on
 //    one counter, so a wait for a load would include every earlier store).
-// Each plane takes two workgroup barriers that wait for LDS traffic only:
-// one before the plane's values overwrite the previous plane's, one before
-// the next plane (and the store waves) read them.
+// Planes alternate between two LDS buffers where they fit, and each plane
+// then takes one workgroup barrier (waiting for LDS traffic only) before
+// the next plane and the store waves read it: a plane's values overwrite
+// those of two planes back, whose readers all passed the barrier between.
+// With one buffer a second barrier precedes the overwrite.
 constexpr int kSweepLdsThreads = 1024;
 
 __device__ __forceinline__ void lds_barrier() {
@@ -277,7 +279,7 @@ struct StageRegs {
   int4 lk;
 };
 
-template <typename T, int DIM, bool ADJ, bool HAS_S, int FLIP>
+template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, int FLIP>
 __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
                                                float4 *stage, int tc) {
   constexpr int NS = 1 << DIM;
@@ -407,6 +409,7 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
       // face; adjoint, the downwind neighbour's inflow face (cells without
       // a neighbour, or lanes without a cell, read position 0 and drop it)
       const int nbp[3] = {cur.lk.y, cur.lk.z, cur.lk.w};
+      const T *rd = lds + (DBUF ? ((pp + 1) & 1) : 0) * NS * maxp;  // previous plane
       T tr[DIM][NS / 2];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
@@ -415,7 +418,7 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
         const int q = nbp[d] >= 0 ? nbp[d] : 0;
 #pragma unroll
         for (int t = 0; t < NS / 2; ++t) {
-          const T x = lds[insert_bit(t, d, nbit) * maxp + q];  // may be uninitialised: select, not scale
+          const T x = rd[insert_bit(t, d, nbit) * maxp + q];  // may be uninitialised: select, not scale
           tr[d][t] = nbp[d] >= 0 ? x : T(0);
         }
       }
@@ -452,11 +455,14 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
 #pragma unroll
         for (int b = 0; b < NS; ++b) v[b] *= iv;
       }
-      lds_barrier();  // every read of the previous plane is done
+      // single buffer: every read of the previous plane must be done first;
+      // double buffer: the plane goes to the other buffer
+      if (!DBUF) lds_barrier();
       if (mine) {
+        T *wr = lds + (DBUF ? (pp & 1) : 0) * NS * maxp;
 #pragma unroll
-        for (int b = 0; b < NS; ++b) lds[b * maxp + tid] = v[b];
-        jbuf[tid] = (int)flipped_cell(cur.lk.x, FLIP, a.g);
+        for (int b = 0; b < NS; ++b) wr[b * maxp + tid] = v[b];
+        jbuf[(DBUF ? (pp & 1) : 0) * maxp + tid] = (int)flipped_cell(cur.lk.x, FLIP, a.g);
       }
       lds_barrier();  // the plane is complete in LDS
       // the next plane's loads are awaited only now, after both barriers
@@ -478,46 +484,49 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
     // group of 64 cells, whole cells per access
     const int ch = lane / CPI;
     for (int pp = 0; pp < np; ++pp) {
-      lds_barrier();
+      if (!DBUF) lds_barrier();
       lds_barrier();
       const int p = plane_of(pp);
       const int n = off[p + 1] - off[p];
+      const T *pb = lds + (DBUF ? (pp & 1) : 0) * NS * maxp;
+      const int *jb = jbuf + (DBUF ? (pp & 1) : 0) * maxp;
       for (int base = (tid - tc) / 64 * CPI; base < n; base += (kSweepLdsThreads - tc) / 64 * CPI) {
         const int q = base + lane % CPI;
         if (q < n) {
           T w[EPC];
 #pragma unroll
-          for (int e = 0; e < EPC; ++e) w[e] = lds[(ch * EPC + e) * maxp + q];
-          *reinterpret_cast<float4 *>(uk + (long long)jbuf[q] * NS + ch * EPC) = *reinterpret_cast<float4 *>(w);
+          for (int e = 0; e < EPC; ++e) w[e] = pb[(ch * EPC + e) * maxp + q];
+          *reinterpret_cast<float4 *>(uk + (long long)jb[q] * NS + ch * EPC) = *reinterpret_cast<float4 *>(w);
         }
       }
     }
   }
 }
 
-template <typename T, int DIM, bool ADJ, bool HAS_S>
+template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF>
 __global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a, int tc) {
   extern __shared__ __align__(16) unsigned char sweep_smem[];
   constexpr int NS = 1 << DIM;
   constexpr int Q = NS * (int)sizeof(T) / 16;
   float4 *stage = reinterpret_cast<float4 *>(sweep_smem);
   T *lds = reinterpret_cast<T *>(stage + (size_t)(tc / 64) * (HAS_S ? 2 : 1) * Q * 64);
-  int *jbuf = reinterpret_cast<int *>(lds + (size_t)NS * a.pl.max_plane);
+  constexpr int NB = DBUF ? 2 : 1;  // plane buffers
+  int *jbuf = reinterpret_cast<int *>(lds + (size_t)NB * NS * a.pl.max_plane);
   // plane offsets in LDS: read with LDS loads, they never make a compute
   // wave wait on the vector-memory counter
-  int *off = jbuf + a.pl.max_plane;
+  int *off = jbuf + NB * a.pl.max_plane;
   for (int i = threadIdx.x; i <= a.pl.nplanes; i += blockDim.x) off[i] = a.pl.off[i];
   __syncthreads();
   const int k = blockIdx.x;
   switch (a.ord[k].flip) {
-    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, 0>(a, k, lds, jbuf, off, stage, tc); break;
-    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, 1>(a, k, lds, jbuf, off, stage, tc); break;
-    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, 2>(a, k, lds, jbuf, off, stage, tc); break;
-    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, 3>(a, k, lds, jbuf, off, stage, tc); break;
-    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 4>(a, k, lds, jbuf, off, stage, tc); break;
-    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 5>(a, k, lds, jbuf, off, stage, tc); break;
-    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 6>(a, k, lds, jbuf, off, stage, tc); break;
-    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, 7>(a, k, lds, jbuf, off, stage, tc); break;
+    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 0>(a, k, lds, jbuf, off, stage, tc); break;
+    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 1>(a, k, lds, jbuf, off, stage, tc); break;
+    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 2>(a, k, lds, jbuf, off, stage, tc); break;
+    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 3>(a, k, lds, jbuf, off, stage, tc); break;
+    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 4>(a, k, lds, jbuf, off, stage, tc); break;
+    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 5>(a, k, lds, jbuf, off, stage, tc); break;
+    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 6>(a, k, lds, jbuf, off, stage, tc); break;
+    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 7>(a, k, lds, jbuf, off, stage, tc); break;
   }
 }
 
@@ -2002,10 +2011,13 @@ static bool launch_sweep_lds(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
   auto aligned = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
   if (!aligned(a.f) || !aligned(a.u) || (a.s && !aligned(a.s))) return false;
   const size_t stage = (size_t)(tc / 64) * (HAS_S ? 2 : 1) * 64 * sizeof(T) * (1 << DIM);
-  const size_t lds = stage + (sizeof(T) * (size_t)(1 << DIM) + sizeof(int)) * (size_t)a.pl.max_plane +
-                     sizeof(int) * (a.pl.nplanes + 1);
+  const size_t plane = (sizeof(T) * (size_t)(1 << DIM) + sizeof(int)) * (size_t)a.pl.max_plane;
+  const size_t tail = sizeof(int) * (a.pl.nplanes + 1);
+  // two plane buffers (one barrier per plane) where they fit, else one
+  const bool dbuf = stage + 2 * plane + tail <= 160 * 1024;
+  const size_t lds = stage + (dbuf ? 2 : 1) * plane + tail;
   if (lds > 160 * 1024) return false;
-  auto fn = k_sweep_lds<T, DIM, ADJ, HAS_S>;
+  auto fn = dbuf ? k_sweep_lds<T, DIM, ADJ, HAS_S, true> : k_sweep_lds<T, DIM, ADJ, HAS_S, false>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return false;
