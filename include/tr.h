@@ -56,8 +56,10 @@ enum {
   TR_ERR_NOCONV = 5        /* solver hit its iteration limit (x is written) */
 };
 
-enum { TR_F64 = 0, TR_F32 = 1 };                      /* buffer precision */
-enum { TR_PREC_F64 = 0, TR_PREC_MIXED = 1, TR_PREC_SG = 2 };
+/* buffer precision; TR_F32_SPLIT: FP32 buffers whose scatter product uses
+ * split-BF16 operands (tr_scatter and the scatter timer only) */
+enum { TR_F64 = 0, TR_F32 = 1, TR_F32_SPLIT = 2 };
+enum { TR_PREC_F64 = 0, TR_PREC_MIXED = 1, TR_PREC_SG = 2, TR_PREC_MIXED_BF16 = 3 };
 enum { TR_INFLOW_NONE = 0, TR_INFLOW_ISO = 1, TR_INFLOW_BEAM = 2 };
 enum { TR_RESTRICT = 0, TR_PROLONG = 1 };
 
@@ -102,7 +104,7 @@ typedef struct {
   double tol;                   /* stop when ||b - A x|| / ||b|| < tol             */
   int restart;                  /* GMRES(m)                                        */
   int max_restarts;
-  int prec_mode;                /* TR_PREC_F64, TR_PREC_MIXED or TR_PREC_SG        */
+  int prec_mode;                /* TR_PREC_F64, _MIXED, _SG or _MIXED_BF16         */
   int timing;                   /* 1: time components with HIP events              */
 } tr_solve_opts;
 
@@ -156,7 +158,10 @@ int tr_sweep_adjoint(tr_handle *h, int level, int prec, const void *g, void *lam
 /* Scatter source s = S phi = sigma_s N (x) S~ phi on level l (Section 5.2,
  * discrete source Q with the X integrals of eq. X).  outer = 1 selects the
  * problem operator (finest level, order L); outer = 0 the multigrid level
- * operator (order mg_order[l]).  Device buffers of precision prec. */
+ * operator (order mg_order[l]).  Device buffers of precision prec
+ * (TR_F32_SPLIT: FP32 buffers, the product S~ phi formed from split-BF16
+ * operands, x = bf16(x) + bf16(x - bf16(x)), as three BF16 matrix-core
+ * products with FP32 accumulation; relative error about 2^-16 per term). */
 int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, void *s, tr_stream st);
 
 /* y = A x = (L - S) x, the problem operator on the finest level (FP64). */
@@ -173,8 +178,10 @@ int tr_transfer(tr_handle *h, int level, int dir, int prec, const void *in, void
 int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi, tr_stream st);
 
 /* Preconditioner z = M^{-1} r: the V-cycle of Fig. lmg (TR_PREC_F64: all
- * levels FP64; TR_PREC_MIXED: levels >= 1 in FP32, T_0 in FP64), or one
- * transport sweep (TR_PREC_SG).  adjoint = 1 builds the cycle from the
+ * levels FP64; TR_PREC_MIXED: levels >= 1 in FP32, T_0 in FP64;
+ * TR_PREC_MIXED_BF16: as TR_PREC_MIXED with the FP32 scatter products
+ * formed from split-BF16 operands, see tr_scatter), or one transport sweep
+ * (TR_PREC_SG).  adjoint = 1 builds the cycle from the
  * transposed level operators.  r, z: device FP64 canonical finest level. */
 int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, double *z, tr_stream st);
 

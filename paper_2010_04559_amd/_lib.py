@@ -11,8 +11,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtr.so")
 
 TR_OK, TR_ERR_ARG, TR_ERR_UNSUPPORTED, TR_ERR_ALLOC, TR_ERR_HIP, TR_ERR_NOCONV = range(6)
-TR_F64, TR_F32 = 0, 1
-TR_PREC_F64, TR_PREC_MIXED, TR_PREC_SG = 0, 1, 2
+TR_F64, TR_F32, TR_F32_SPLIT = 0, 1, 2
+TR_PREC_F64, TR_PREC_MIXED, TR_PREC_SG, TR_PREC_MIXED_BF16 = 0, 1, 2, 3
 TR_INFLOW_NONE, TR_INFLOW_ISO, TR_INFLOW_BEAM = 0, 1, 2
 TR_RESTRICT, TR_PROLONG = 0, 1
 

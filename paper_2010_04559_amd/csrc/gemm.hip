@@ -210,6 +210,154 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     }
 }
 
+// Split-BF16 product for FP32 operands (the preconditioner's scatter when
+// its accuracy suffices): every operand element is split x = x_hi + x_lo
+// with x_hi = bf16(x) and x_lo = bf16(x - x_hi) while it is staged into LDS,
+// and C = A_hi B_hi + A_hi B_lo + A_lo B_hi is accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16 (the dropped A_lo B_lo and the split's own
+// rounding leave a relative error of about 2^-16 per product).
+// Tile 128 x 128 x 32, 256 threads as 2 x 2 waves of 64 x 64 (4 x 4 MFMA
+// tiles).  Lane l of an MFMA supplies A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16], i < 8, as 16-byte vectors; both operands are
+// therefore kept k-contiguous in LDS ([row][k] and [column][k], padded to
+// 40 elements so that 16-byte accesses of consecutive rows spread over the
+// banks).  Accumulator element r of lane l is D[4 (l / 16) + r][l % 16].
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned pack_bf16(__bf16 a, __bf16 b) {
+  return (unsigned)__builtin_bit_cast(unsigned short, a) | ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
+}
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_bf16x3(
+    const float *__restrict__ A, const float *__restrict__ B, float *__restrict__ C, int M, int N, int K,
+    int mblocks, int nblocks, const float *__restrict__ bias, const double *__restrict__ colscale, int cell) {
+  constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][KP], Al[2][BM][KP], Bh[2][BN][KP], Bl[2][BN][KP];
+  const int b = blockIdx.x;
+  const int xcd = b % kXcds, slot = b / kXcds;
+  const int mb = slot % mblocks;
+  const int nb = xcd + kXcds * (slot / mblocks);
+  if (nb >= nblocks) return;
+  const int m0 = mb * BM;
+  const long long n0 = (long long)nb * BN;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // staging: A as four float4 per thread (rows t / 8 + 32 q, k 4 (t % 8));
+  // B as 16 floats per thread (column t % 128, k 16 (t / 128) + i)
+  float4 ra[4];
+  float rb[16];
+  const int ak = (tid & 7) * 4, arow = tid >> 3;
+  const int bn = tid & 127, bk = (tid >> 7) * 16;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gm = m0 + arow + 32 * q, gk = k0 + ak;
+      if (gm < M && gk + 4 <= K) {
+        ra[q] = *reinterpret_cast<const float4 *>(A + (long long)gm * K + gk);
+      } else {
+        float e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = (gm < M && gk + u < K) ? A[(long long)gm * K + gk + u] : 0.f;
+        ra[q] = make_float4(e[0], e[1], e[2], e[3]);
+      }
+    }
+    const long long gn = n0 + bn;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int gk = k0 + bk + i;
+      rb[i] = (gk < K && gn < N) ? B[(long long)gk * N + gn] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float e[4] = {ra[q].x, ra[q].y, ra[q].z, ra[q].w};
+      __bf16 h[4], l[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) split_bf16(e[u], h[u], l[u]);
+      *reinterpret_cast<uint2 *>(&Ah[buf][arow + 32 * q][ak]) = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
+      *reinterpret_cast<uint2 *>(&Al[buf][arow + 32 * q][ak]) = make_uint2(pack_bf16(l[0], l[1]), pack_bf16(l[2], l[3]));
+    }
+    unsigned hw[8], lw[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      __bf16 h0, l0, h1, l1;
+      split_bf16(rb[2 * i], h0, l0);
+      split_bf16(rb[2 * i + 1], h1, l1);
+      hw[i] = pack_bf16(h0, h1);
+      lw[i] = pack_bf16(l0, l1);
+    }
+    uint4 *bh = reinterpret_cast<uint4 *>(&Bh[buf][bn][bk]);
+    uint4 *bl = reinterpret_cast<uint4 *>(&Bl[buf][bn][bk]);
+    bh[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    bh[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+    bl[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    bl[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
+  };
+  auto mma = [&](int buf) {
+    bf8 ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *reinterpret_cast<const bf8 *>(&Ah[buf][wm0 + 16 * i + lr][8 * lk]);
+      al[i] = *reinterpret_cast<const bf8 *>(&Al[buf][wm0 + 16 * i + lr][8 * lk]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf8 bh = *reinterpret_cast<const bf8 *>(&Bh[buf][wn0 + 16 * j + lr][8 * lk]);
+      const bf8 bl = *reinterpret_cast<const bf8 *>(&Bl[buf][wn0 + 16 * j + lr][8 * lk]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) load(k0 + BK);
+    mma(buf);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long gn = n0 + wn0 + 16 * j + lr;
+      const float cs = (colscale && gn < N) ? (float)colscale[gn / cell] : 1.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm0 + 16 * i + 4 * lk + r;
+        if (gm < M && gn < N) {
+          const long long o = (long long)gm * N + gn;
+          float y = acc[i][j][r];
+          if (colscale) y *= cs;
+          if (bias) y += bias[o];
+          C[o] = y;
+        }
+      }
+    }
+}
+
 }  // namespace
 
 // Launch shapes (tile M x N x depth, LDS double buffering, minimum waves per
@@ -235,6 +383,15 @@ void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t 
   else
     launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell);
 }
+void launch_gemm_bf16x3(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t st,
+                        const float *bias, const double *colscale, int cell) {
+  const int mblocks = (M + 127) / 128;
+  const int nblocks = (int)(((long long)N + 127) / 128);
+  const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(mblocks * nb_pad)), dim3(256), 0, st, A, B, C, M, N, K, mblocks,
+                     nblocks, bias, colscale, cell);
+}
+
 template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t,
                                   const double *, const double *, int);
 template void launch_gemm<float>(const float *, const float *, float *, int, int, int, hipStream_t, const float *,

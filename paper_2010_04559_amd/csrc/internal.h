@@ -145,5 +145,9 @@ void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st);
 template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
                  const double *colscale = nullptr, int cell = 8);
+// FP32 C = A B with split-BF16 operands (three BF16 MFMA products, FP32
+// accumulate); same epilogue as launch_gemm
+void launch_gemm_bf16x3(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t st,
+                        const float *bias = nullptr, const double *colscale = nullptr, int cell = 8);
 
 }  // namespace tr

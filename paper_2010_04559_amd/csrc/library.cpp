@@ -13,6 +13,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tr.h"
@@ -182,6 +183,7 @@ struct tr_handle {
     int brick_steps = 0;
   };
   bool gs_brick = true;       // dataflow solve over 2 x 2 x 2 bricks where the grid allows
+  bool split32 = false;       // FP32 scatter products from split-BF16 operands
   bool gs_flow = true;        // coarse solve without grid barriers
   bool gs_coh = true;         // barrier form: device-coherent iterate accesses
   unsigned *gs_cnt = nullptr;  // [cells] update counters of the dataflow solve
@@ -579,13 +581,28 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   tend(h);
 }
 
+// C = A B on the level GEMM path: FP64 and FP32 on the matrix cores in
+// their own precision, FP32 from split-BF16 operands when the handle's
+// preconditioner mode asks for it.
+template <typename T>
+void gemm(tr_handle *h, const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
+          const double *colscale = nullptr, int cell = 8) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (h->split32) {
+      tr::launch_gemm_bf16x3(A, B, C, M, N, K, st, bias, colscale, cell);
+      return;
+    }
+  }
+  tr::launch_gemm<T>(A, B, C, M, N, K, st, bias, colscale, cell);
+}
+
 // y = G x, or y = bias + sigma_s (G x) per cell with scale_sn (bias may be
 // null): the forward V-cycle's prepared right-hand sides.
 template <typename T>
 void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st, bool scale_sn = false,
              const T *bias = nullptr) {
   tbegin(h, C_SCATTER);
-  tr::launch_gemm<T>(G, x, y, A, (int)h->g.S, A, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns);
+  gemm<T>(h, G, x, y, A, (int)h->g.S, A, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns);
   tend(h);
 }
 
@@ -822,9 +839,8 @@ void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t 
   T *tmp = LevelBuf<T>::fact(h);
   const int S = (int)h->g.S;
   tbegin(h, C_SCATTER);
-  tr::launch_gemm<T>(LevelBuf<T>::Lf(D, adj), u, tmp, D.Kf, S, D.A, st);
-  tr::launch_gemm<T>(LevelBuf<T>::Rf(D, adj), tmp, y, D.A, S, D.Kf, st, bias, scale_sn ? h->sig_s : nullptr,
-                     h->g.ns);
+  gemm<T>(h, LevelBuf<T>::Lf(D, adj), u, tmp, D.Kf, S, D.A, st);
+  gemm<T>(h, LevelBuf<T>::Rf(D, adj), tmp, y, D.A, S, D.Kf, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns);
   tend(h);
 }
 
@@ -935,8 +951,13 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
     tend(h);
     return;
   }
-  if (mode == TR_PREC_MIXED) {
+  if (mode == TR_PREC_MIXED || mode == TR_PREC_MIXED_BF16) {
     ensure_mixed(h);
+    struct Split {  // FP32 scatter products for this V-cycle only
+      tr_handle *h;
+      ~Split() { h->split32 = false; }
+    } split_guard{h};
+    h->split32 = mode == TR_PREC_MIXED_BF16;
     tbegin(h, C_OTHER);
     convert_in<double, float>(h, L, adj, r, D.f32, st);
     tend(h);
@@ -1380,7 +1401,7 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
   if (!phi || !s) return fail(TR_ERR_ARG, "null buffer");
   TR_CHECK_ALIGNED(phi, s);
   if (outer && level != h->top()) return fail(TR_ERR_ARG, "the problem operator lives on the finest level");
-  if (prec != TR_F64 && prec != TR_F32) return fail(TR_ERR_ARG, "bad precision");
+  if (prec != TR_F64 && prec != TR_F32 && prec != TR_F32_SPLIT) return fail(TR_ERR_ARG, "bad precision");
   if (outer && prec != TR_F64) return fail(TR_ERR_UNSUPPORTED, "the problem operator is FP64 only");
   return translate([&]() {
     DevLevel &D = h->lv[level];
@@ -1392,7 +1413,10 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
     } else {
       TmpBuf tb((size_t)h->vec_len(level) * sizeof(float));
       float *t = tb.as<float>();
-      tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+      if (prec == TR_F32_SPLIT)
+        tr::launch_gemm_bf16x3(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+      else
+        tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
       tr::launch_scale_sn<float>(t, (float *)s, h->sig_s, D.A, h->g, S(st));
       HIPCHK(hipStreamSynchronize(S(st)));
     }
@@ -1453,7 +1477,8 @@ int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi
 int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, double *z, tr_stream st) {
   if (!h || !r || !z) return fail(TR_ERR_ARG, "null argument");
   TR_CHECK_ALIGNED(r, z);
-  if (prec_mode != TR_PREC_F64 && prec_mode != TR_PREC_MIXED && prec_mode != TR_PREC_SG)
+  if (prec_mode != TR_PREC_F64 && prec_mode != TR_PREC_MIXED && prec_mode != TR_PREC_SG &&
+      prec_mode != TR_PREC_MIXED_BF16)
     return fail(TR_ERR_ARG, "bad preconditioner mode");
   return translate([&]() {
     precondition(h, prec_mode, adjoint != 0, r, z, S(st));
@@ -1468,7 +1493,8 @@ static int solve_common(tr_handle *h, bool adj, const double *b, double *x, cons
   TR_CHECK_ALIGNED(b, x);
   if (o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->tol > 0))
     return fail(TR_ERR_ARG, "bad solver options");
-  if (o->prec_mode != TR_PREC_F64 && o->prec_mode != TR_PREC_MIXED && o->prec_mode != TR_PREC_SG)
+  if (o->prec_mode != TR_PREC_F64 && o->prec_mode != TR_PREC_MIXED && o->prec_mode != TR_PREC_SG &&
+      o->prec_mode != TR_PREC_MIXED_BF16)
     return fail(TR_ERR_ARG, "bad preconditioner mode");
   std::unique_ptr<EventTimer> timer;
   int rc = translate([&]() {
@@ -1572,12 +1598,18 @@ int tr_time_scatter_kernel(tr_handle *h, int level, int outer, int prec, int rep
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    if (prec == TR_F32) {
+    if (prec == TR_F32 || prec == TR_F32_SPLIT) {
       if (level == 0) throw ArgError{"FP32 runs on levels >= 1"};
       ensure_mixed(h);
-      tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+      auto run = [&]() {
+        if (prec == TR_F32_SPLIT)
+          tr::launch_gemm_bf16x3(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+        else
+          tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+      };
+      run();
       HIPCHK(hipEventRecord(e0, S(st)));
-      for (int i = 0; i < reps; ++i) tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+      for (int i = 0; i < reps; ++i) run();
     } else {
       const double *G = outer ? h->Souter : D.G64;
       tr::launch_gemm<double>(G, D.u64, D.sa64, D.A, (int)h->g.S, D.A, S(st));

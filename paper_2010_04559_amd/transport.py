@@ -11,7 +11,8 @@ import numpy as np
 from . import _lib
 from .inputs import Problem
 
-_MODES = {"f64": _lib.TR_PREC_F64, "mixed": _lib.TR_PREC_MIXED, "sg": _lib.TR_PREC_SG}
+_MODES = {"f64": _lib.TR_PREC_F64, "mixed": _lib.TR_PREC_MIXED, "sg": _lib.TR_PREC_SG,
+          "mixed_bf16": _lib.TR_PREC_MIXED_BF16}
 
 
 def _torch():
@@ -144,10 +145,11 @@ class Transport:
         _lib.check(fn(self.h, level, self._prec(g), _ptr(g), _ptr(out), _stream()))
         return out
 
-    def scatter(self, level, phi, outer=False):
+    def scatter(self, level, phi, outer=False, split_bf16=False):
+        """split_bf16: FP32 buffers, product from split-BF16 operands."""
         out = _torch().empty_like(phi)
-        _lib.check(self.lib.tr_scatter(self.h, level, 1 if outer else 0, self._prec(phi), _ptr(phi), _ptr(out),
-                                       _stream()))
+        prec = _lib.TR_F32_SPLIT if split_bf16 else self._prec(phi)
+        _lib.check(self.lib.tr_scatter(self.h, level, 1 if outer else 0, prec, _ptr(phi), _ptr(out), _stream()))
         return out
 
     def apply(self, x):
@@ -217,7 +219,7 @@ class Transport:
     def time_scatter_kernel(self, level=None, outer=False, prec="f64", reps=10):
         level = self.nlev - 1 if level is None else level
         ms = ctypes.c_double()
-        _lib.check(self.lib.tr_time_scatter_kernel(self.h, level, 1 if outer else 0,
-                                                   _lib.TR_F64 if prec == "f64" else _lib.TR_F32, reps,
+        code = {"f64": _lib.TR_F64, "f32": _lib.TR_F32, "bf16x3": _lib.TR_F32_SPLIT}[prec]
+        _lib.check(self.lib.tr_time_scatter_kernel(self.h, level, 1 if outer else 0, code, reps,
                                                    ctypes.byref(ms), _stream()))
         return ms.value

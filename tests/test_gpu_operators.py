@@ -72,6 +72,24 @@ def test_scatter_fp32(pair):
     assert rel(got, lv.apply_S(x)) < 1e-5
 
 
+def test_scatter_split_bf16(pair):
+    """FP32 scatter with split-BF16 operands against the FP64 oracle.  Each
+    product a b is formed as a_hi b_hi + a_hi b_lo + a_lo b_hi with
+    |a - a_hi - a_lo| <= 2^-16 |a| (two round-to-nearest BF16 steps) and the
+    dropped |a_lo b_lo| <= 2^-16 |a b|: at most 3 2^-16 = 4.6e-5 relative per
+    term, plus FP32 accumulation; norm-wise over these random inputs the sum
+    stays within 2e-4 (cancellation factor below 4)."""
+    torch = torch_mod()
+    for l in range(1, pair.tr.nlev):
+        lv = pair.level(l)
+        x = _rand(lv.A * lv.grid.S, 62 + l)
+        got = to_np(pair.tr.scatter(l, to_dev(x, torch.float32), split_bf16=True))
+        ref = lv.apply_S(x)
+        assert rel(got, ref) < 2e-4, l
+        # and it is really the split product, not plain FP32 (which is ~1e-7)
+        assert rel(got, ref) > 1e-8, l
+
+
 def test_apply(pair):
     lv = pair.level(0, outer=True)
     x = _rand(lv.A * lv.grid.S, 70)

@@ -36,6 +36,25 @@ def test_mixed_precision_solution_matches_fp64_oracle():
     assert rel(phi, phi_ref) < 1e-7
 
 
+def test_split_bf16_preconditioner_solution_matches_fp64_oracle():
+    """FP32 V-cycle with split-BF16 scatter products inside FP64 GMRES: the
+    converged solution meets the FP64 oracle's to 1e-7, and the iteration
+    count is that of the FP32 preconditioner (the condition under which the
+    split products are used)."""
+    prob = small(dim=3, n=4, level=2, order=10, g=0.9, c=0.98, seed=19)
+    pr = Pair(prob)
+    b_np = pr.op.rhs()
+    ref = krylov.gmres(pr.op.outer.apply_A, pr.op.mg.vcycle, b_np, 1e-12, prob.restart)
+    x32, st32 = pr.tr.solve(to_dev(b_np), tol=1e-8, mode="mixed")
+    x, st = pr.tr.solve(to_dev(b_np), tol=1e-8, mode="mixed_bf16")
+    print("iterations fp32", st32["iters"], "split-bf16", st["iters"], flush=True)
+    assert st["converged"] == 1 and st["rel_res"] < 1e-8
+    assert st["iters"] == st32["iters"]
+    phi_ref = pr.op.outer.scalar_flux_cell_avg(ref.x)
+    phi = pr.op.outer.scalar_flux_cell_avg(to_np(x))
+    assert rel(phi, phi_ref) < 1e-7
+
+
 def test_single_grid_preconditioner_matches_oracle():
     prob = small(dim=2, n=3, level=1, order=4, g=0.8, c=0.9, seed=8)
     pr = Pair(prob)
