@@ -21,6 +21,8 @@
 // the same XCD, one after another, and B is fetched from HBM about once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace tr {
@@ -212,16 +214,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 
 // Split-BF16 product for FP32 operands (the preconditioner's scatter when
 // its accuracy suffices): every operand element is split x = x_hi + x_lo
-// with x_hi = bf16(x) and x_lo = bf16(x - x_hi) while it is staged into LDS,
-// and C = A_hi B_hi + A_hi B_lo + A_lo B_hi is accumulated in FP32 by
-// v_mfma_f32_16x16x32_bf16 (the dropped A_lo B_lo and the split's own
-// rounding leave a relative error of about 2^-16 per product).
+// with x_hi = bf16(x) and x_lo = bf16(x - x_hi), and C = A_hi B_hi +
+// A_hi B_lo + A_lo B_hi is accumulated in FP32 by v_mfma_f32_16x16x32_bf16
+// (the dropped A_lo B_lo and the split's own rounding leave a relative
+// error of about 2^-16 per product).  A (the small level matrix) is split
+// once by k_split_rows into [hi | lo][M][Kp] (rows zero-padded to Kp, a
+// multiple of 32) and its MFMA operands are read straight from global
+// memory (L2-resident), one k-slice ahead; B is split while it is staged
+// into LDS.
 // Tile 128 x 128 x 32, 256 threads as 2 x 2 waves of 64 x 64 (4 x 4 MFMA
 // tiles).  Lane l of an MFMA supplies A[l % 16][8 (l / 16) + i] and
-// B[8 (l / 16) + i][l % 16], i < 8, as 16-byte vectors; both operands are
-// therefore kept k-contiguous in LDS ([row][k] and [column][k], padded to
-// 40 elements so that 16-byte accesses of consecutive rows spread over the
-// banks).  Accumulator element r of lane l is D[4 (l / 16) + r][l % 16].
+// B[8 (l / 16) + i][l % 16], i < 8, as 16-byte vectors, so B is kept
+// column-major ([column][k], padded to 40 elements so that 16-byte accesses
+// of consecutive columns spread over the banks).  Accumulator element r of
+// lane l is D[4 (l / 16) + r][l % 16].
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ unsigned pack_bf16(__bf16 a, __bf16 b) {
@@ -232,11 +238,22 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+__global__ void k_split_rows(const float *__restrict__ A, int M, int K, int Kp, __bf16 *__restrict__ out) {
+  const long long n = (long long)M * Kp;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(t / Kp), k = (int)(t - (long long)m * Kp);
+    __bf16 h = (__bf16)0.f, l = (__bf16)0.f;
+    if (k < K) split_bf16(A[(long long)m * K + k], h, l);
+    out[t] = h;
+    out[n + t] = l;
+  }
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_bf16x3(
-    const float *__restrict__ A, const float *__restrict__ B, float *__restrict__ C, int M, int N, int K,
+    const __bf16 *__restrict__ As, int Kp, const float *__restrict__ B, float *__restrict__ C, int M, int N, int K,
     int mblocks, int nblocks, const float *__restrict__ bias, const double *__restrict__ colscale, int cell) {
   constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][KP], Al[2][BM][KP], Bh[2][BN][KP], Bl[2][BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][KP], Bl[2][BN][KP];
   const int b = blockIdx.x;
   const int xcd = b % kXcds, slot = b / kXcds;
   const int mb = slot % mblocks;
@@ -248,6 +265,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int wave = tid >> 6, lane = tid & 63;
   const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
+  const __bf16 *Alo = As + (long long)M * Kp;
 
   f4 acc[4][4];
 #pragma unroll
@@ -255,25 +273,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // staging: A as four float4 per thread (rows t / 8 + 32 q, k 4 (t % 8));
-  // B as 16 floats per thread (column t % 128, k 16 (t / 128) + i)
-  float4 ra[4];
-  float rb[16];
-  const int ak = (tid & 7) * 4, arow = tid >> 3;
-  const int bn = tid & 127, bk = (tid >> 7) * 16;
-  auto load = [&](int k0) {
+  // A operands of this lane (rows past M read row M - 1; their products
+  // land in rows that are not stored)
+  long long arow[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gm = m0 + arow + 32 * q, gk = k0 + ak;
-      if (gm < M && gk + 4 <= K) {
-        ra[q] = *reinterpret_cast<const float4 *>(A + (long long)gm * K + gk);
-      } else {
-        float e[4];
+  for (int i = 0; i < 4; ++i) arow[i] = (long long)min(m0 + wm0 + 16 * i + lr, M - 1) * Kp + 8 * lk;
+  bf8 ah[4], al[4];
+  auto load_a = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = (gm < M && gk + u < K) ? A[(long long)gm * K + gk + u] : 0.f;
-        ra[q] = make_float4(e[0], e[1], e[2], e[3]);
-      }
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *reinterpret_cast<const bf8 *>(As + arow[i] + k0);
+      al[i] = *reinterpret_cast<const bf8 *>(Alo + arow[i] + k0);
     }
+  };
+  // B staging: 16 floats per thread (column t % 128, k 16 (t / 128) + i)
+  float rb[16];
+  const int bn = tid & 127, bk = (tid >> 7) * 16;
+  auto load_b = [&](int k0) {
     const long long gn = n0 + bn;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -281,16 +297,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       rb[i] = (gk < K && gn < N) ? B[(long long)gk * N + gn] : 0.f;
     }
   };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float e[4] = {ra[q].x, ra[q].y, ra[q].z, ra[q].w};
-      __bf16 h[4], l[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) split_bf16(e[u], h[u], l[u]);
-      *reinterpret_cast<uint2 *>(&Ah[buf][arow + 32 * q][ak]) = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
-      *reinterpret_cast<uint2 *>(&Al[buf][arow + 32 * q][ak]) = make_uint2(pack_bf16(l[0], l[1]), pack_bf16(l[2], l[3]));
-    }
+  auto store_b = [&](int buf) {
     unsigned hw[8], lw[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -307,34 +314,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     bl[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
     bl[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
   };
-  auto mma = [&](int buf) {
-    bf8 ah[4], al[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ah[i] = *reinterpret_cast<const bf8 *>(&Ah[buf][wm0 + 16 * i + lr][8 * lk]);
-      al[i] = *reinterpret_cast<const bf8 *>(&Al[buf][wm0 + 16 * i + lr][8 * lk]);
-    }
+  auto mma = [&](int buf, const bf8 (&xh)[4], const bf8 (&xl)[4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const bf8 bh = *reinterpret_cast<const bf8 *>(&Bh[buf][wn0 + 16 * j + lr][8 * lk]);
       const bf8 bl = *reinterpret_cast<const bf8 *>(&Bl[buf][wn0 + 16 * j + lr][8 * lk]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bh, acc[i][j], 0, 0, 0);
       }
     }
   };
-  load(0);
-  store(0);
+  load_a(0);
+  load_b(0);
+  store_b(0);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
     const bool more = k0 + BK < K;
-    if (more) load(k0 + BK);
-    mma(buf);
-    if (more) store(buf ^ 1);
+    const bf8 ch[4] = {ah[0], ah[1], ah[2], ah[3]}, cl[4] = {al[0], al[1], al[2], al[3]};
+    if (more) {
+      load_a(k0 + BK);
+      load_b(k0 + BK);
+    }
+    mma(buf, ch, cl);
+    if (more) store_b(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
@@ -383,13 +389,23 @@ void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t 
   else
     launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell);
 }
-void launch_gemm_bf16x3(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t st,
+int split_rows_kp(int K) { return (K + 31) / 32 * 32; }
+
+void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st) {
+  const int Kp = split_rows_kp(K);
+  const long long n = (long long)M * Kp;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_split_rows, dim3(blocks), dim3(256), 0, st, A, M, K, Kp, reinterpret_cast<__bf16 *>(out));
+}
+
+void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int N, int K, hipStream_t st,
                         const float *bias, const double *colscale, int cell) {
   const int mblocks = (M + 127) / 128;
   const int nblocks = (int)(((long long)N + 127) / 128);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(mblocks * nb_pad)), dim3(256), 0, st, A, B, C, M, N, K, mblocks,
-                     nblocks, bias, colscale, cell);
+  hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(mblocks * nb_pad)), dim3(256), 0, st,
+                     reinterpret_cast<const __bf16 *>(Asplit), split_rows_kp(K), B, C, M, N, K, mblocks, nblocks,
+                     bias, colscale, cell);
 }
 
 template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t,

@@ -146,8 +146,12 @@ template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
                  const double *colscale = nullptr, int cell = 8);
 // FP32 C = A B with split-BF16 operands (three BF16 MFMA products, FP32
-// accumulate); same epilogue as launch_gemm
-void launch_gemm_bf16x3(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t st,
+// accumulate); same epilogue as launch_gemm.  Asplit: A split once by
+// launch_split_rows into [hi | lo][M][split_rows_kp(K)] BF16 (device,
+// 2 M split_rows_kp(K) elements of 2 bytes).
+int split_rows_kp(int K);
+void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st);
+void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int N, int K, hipStream_t st,
                         const float *bias = nullptr, const double *colscale = nullptr, int cell = 8);
 
 }  // namespace tr

@@ -184,6 +184,12 @@ struct tr_handle {
   };
   bool gs_brick = true;       // dataflow solve over 2 x 2 x 2 bricks where the grid allows
   bool split32 = false;       // FP32 scatter products from split-BF16 operands
+  struct SplitA {             // level matrices split into BF16 hi/lo once
+    const float *A;
+    int M, K;
+    void *p;
+  };
+  std::vector<SplitA> splits;
   bool gs_flow = true;        // coarse solve without grid barriers
   bool gs_coh = true;         // barrier form: device-coherent iterate accesses
   unsigned *gs_cnt = nullptr;  // [cells] update counters of the dataflow solve
@@ -581,6 +587,16 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   tend(h);
 }
 
+// The split-BF16 form of a constant level matrix (made on first use).
+const void *split_of(tr_handle *h, const float *A, int M, int K, hipStream_t st) {
+  for (auto &e : h->splits)
+    if (e.A == A && e.M == M && e.K == K) return e.p;
+  void *p = h->alloc<unsigned short>(2LL * M * tr::split_rows_kp(K));
+  tr::launch_split_rows(A, M, K, p, st);
+  h->splits.push_back({A, M, K, p});
+  return p;
+}
+
 // C = A B on the level GEMM path: FP64 and FP32 on the matrix cores in
 // their own precision, FP32 from split-BF16 operands when the handle's
 // preconditioner mode asks for it.
@@ -589,7 +605,7 @@ void gemm(tr_handle *h, const T *A, const T *B, T *C, int M, int N, int K, hipSt
           const double *colscale = nullptr, int cell = 8) {
   if constexpr (std::is_same<T, float>::value) {
     if (h->split32) {
-      tr::launch_gemm_bf16x3(A, B, C, M, N, K, st, bias, colscale, cell);
+      tr::launch_gemm_bf16x3(split_of(h, A, M, K, st), B, C, M, N, K, st, bias, colscale, cell);
       return;
     }
   }
@@ -1414,7 +1430,8 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
       TmpBuf tb((size_t)h->vec_len(level) * sizeof(float));
       float *t = tb.as<float>();
       if (prec == TR_F32_SPLIT)
-        tr::launch_gemm_bf16x3(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+        tr::launch_gemm_bf16x3(split_of(h, D.St32, D.A, D.A, S(st)), (const float *)phi, t, D.A, (int)h->g.S, D.A,
+                               S(st));
       else
         tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
       tr::launch_scale_sn<float>(t, (float *)s, h->sig_s, D.A, h->g, S(st));
@@ -1603,7 +1620,7 @@ int tr_time_scatter_kernel(tr_handle *h, int level, int outer, int prec, int rep
       ensure_mixed(h);
       auto run = [&]() {
         if (prec == TR_F32_SPLIT)
-          tr::launch_gemm_bf16x3(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+          tr::launch_gemm_bf16x3(split_of(h, D.G32, D.A, D.A, S(st)), D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
         else
           tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
       };
