@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
+BF16_PEAK_TFS = 2500.0  # dense BF16 MFMA
 
 
 def kernel_sources_digest():
@@ -152,6 +153,19 @@ def main():
         dx = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
         mixed = {"ms": ms_mixed, "iters": stm["iters"], "rel_res": stm["rel_res"], "rel_diff_vs_fp64": dx}
         print("mixed: %.1f ms, iters %d" % (ms_mixed, stm["iters"]), file=sys.stderr, flush=True)
+        # the same V-cycle with split-BF16 scatter products; used only where
+        # its iteration count equals the FP32 one
+        xs, sts = tr.solve(b, mode="mixed_bf16")
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(args.steps):
+            xs, sts = tr.solve(b, mode="mixed_bf16")
+        torch.cuda.synchronize()
+        ms_split = (time.perf_counter() - tm0) / args.steps * 1e3
+        mixed["split_bf16"] = {"ms": ms_split, "iters": sts["iters"], "rel_res": sts["rel_res"],
+                               "rel_diff_vs_fp64": float(torch.linalg.norm(xs - x) / torch.linalg.norm(x)),
+                               "same_iterations_as_fp32": sts["iters"] == stm["iters"]}
+        print("mixed split-bf16: %.1f ms, iters %d" % (ms_split, sts["iters"]), file=sys.stderr, flush=True)
 
     # component breakdown (HIP events around every launch group)
     _, stt = tr.solve(b, timing=True)
@@ -172,6 +186,8 @@ def main():
     gemm_tfs = 2.0 * A * A * tr.S / (ms_gemm * 1e-3) / 1e12
     ms_gemm32 = tr.time_scatter_kernel(L, outer=False, prec="f32", reps=10)
     gemm32_tfs = 2.0 * A * A * tr.S / (ms_gemm32 * 1e-3) / 1e12
+    ms_gemm16 = tr.time_scatter_kernel(L, outer=False, prec="bf16x3", reps=10)
+    gemm16_tfs = 2.0 * A * A * tr.S / (ms_gemm16 * 1e-3) / 1e12
 
     line = {
         "metric": "sweep DoF-updates/s; time-to-1e-8 residual, FP32-MG vs FP64 plain, 1 GPU",
@@ -191,8 +207,10 @@ def main():
                                "source, vacuum; GMRES(10) + FP64 angular MG V(1,1), tol 1e-8" % args.n,
                    "cells": tr.C, "spatial_dofs": tr.S, "angular_dofs": A, "dofs": dofs,
                    "parallelism": "single GPU"},
-        "time_to_tol_ms": {"fp64_plain": ms_step, "fp32_mg": mixed["ms"] if mixed else None},
-        "iters": {"fp64_plain": st["iters"], "fp32_mg": mixed["iters"] if mixed else None},
+        "time_to_tol_ms": {"fp64_plain": ms_step, "fp32_mg": mixed["ms"] if mixed else None,
+                           "fp32_mg_split_bf16": mixed["split_bf16"]["ms"] if mixed else None},
+        "iters": {"fp64_plain": st["iters"], "fp32_mg": mixed["iters"] if mixed else None,
+                  "fp32_mg_split_bf16": mixed["split_bf16"]["iters"] if mixed else None},
         "explicit_rel_res": rel_res,
         "mixed": mixed,
         "breakdown_ms": breakdown,
@@ -203,7 +221,9 @@ def main():
         "sweep_kernel": {"fp64_dof_per_s": dofs / (ms_sweep * 1e-3), "fp32_dof_per_s": dofs / (ms_sweep32 * 1e-3),
                          "fp32_ms": ms_sweep32},
         "scatter_gemm": {"fp64_ms": ms_gemm, "fp64_tflops": gemm_tfs, "fp64_frac": gemm_tfs / FP64_PEAK_TFS,
-                         "fp32_ms": ms_gemm32, "fp32_tflops": gemm32_tfs, "fp32_frac": gemm32_tfs / FP32_PEAK_TFS},
+                         "fp32_ms": ms_gemm32, "fp32_tflops": gemm32_tfs, "fp32_frac": gemm32_tfs / FP32_PEAK_TFS,
+                         "split_bf16_ms": ms_gemm16, "split_bf16_tflops_fp32_equiv": gemm16_tfs,
+                         "split_bf16_mfma_frac": 3 * gemm16_tfs / BF16_PEAK_TFS},
         "coarse_gs": coarse_gs_line(stt),
         "setup_s": t_setup,
     }
@@ -274,7 +294,7 @@ def other_workload(args):
     print("%s setup %.1f s, patches %s, S=%d" % (prob.name, t_setup, tr.patches, tr.S), file=sys.stderr, flush=True)
     out = {"workload": prob.name, "patches": tr.patches, "spatial_dofs": tr.S,
            "dofs": 3 * tr.patches[-1] * tr.S, "setup_s": t_setup, "solves": {}}
-    modes = ["f64", "mixed"]
+    modes = ["f64", "mixed", "mixed_bf16"]
     xs = {}
     for mode in modes:
         x, st, ms = _solve_timed(tr, b, mode, args.steps, args.warmup)
@@ -285,6 +305,8 @@ def other_workload(args):
                                "sweep_dof_updates_per_s": st["sweep_dof_updates"] / (ms * 1e-3)}
         print(mode, out["solves"][mode], file=sys.stderr, flush=True)
     out["mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs["mixed"] - xs["f64"]) / torch.linalg.norm(xs["f64"]))
+    out["mixed_bf16_vs_fp64_rel_diff"] = float(torch.linalg.norm(xs["mixed_bf16"] - xs["f64"]) /
+                                               torch.linalg.norm(xs["f64"]))
     _, stt = tr.solve(b, timing=True)
     out["breakdown_ms_fp64"] = {k: round(stt[k], 3) for k in ("ms_total", "ms_sweep", "ms_scatter", "ms_transfer",
                                                               "ms_coarse", "ms_apply", "ms_orth", "ms_other")}
