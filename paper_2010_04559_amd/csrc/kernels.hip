@@ -1569,10 +1569,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_lanes(const double *__restrict
   for (long long t0 = wave_first; t0 < groups; t0 += gstride) {
     const long long t = t0 + (threadIdx.x & 63) / NS;
     const bool active = t < groups;
-    const long long tt = active ? t : 0;
-    const int q = (int)(tt / C);
-    const long long j = tt - (long long)q * C;
-    const int ix[3] = {(int)(j % g.n[0]), (int)((j / g.n[0]) % g.n[1]), (int)(j / ((long long)g.n[0] * g.n[1]))};
+    // 32-bit index arithmetic (patches x cells < 2^31, checked at launch):
+    // 64-bit divisions would dominate the kernel's instruction count
+    const unsigned tt = active ? (unsigned)t : 0u;
+    const unsigned q = tt / (unsigned)C;
+    const unsigned ju = tt - q * (unsigned)C;
+    const unsigned r0 = ju / (unsigned)g.n[0];
+    const int ix[3] = {(int)(ju - r0 * (unsigned)g.n[0]), (int)(r0 % (unsigned)g.n[1]), (int)(r0 / (unsigned)g.n[1])};
+    const long long j = ju;
     const double st = sig_t[j], ss = sig_s[j];
     double xv[3];
 #pragma unroll
@@ -2200,6 +2204,7 @@ void launch_apply(const double *x, const double *s, double *y, const double *sig
                   const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
   // one lane per node, kBlock / 2^dim cells per workgroup
   const long long cells = (long long)P * g.C;
+  if (cells >= (1LL << 31)) throw std::runtime_error("operator apply: patches x cells must be below 2^31");
   const int grid = (int)std::max(1LL, std::min((cells * g.ns + kBlock - 1) / kBlock, 16384LL));
   if (g.dim == 3) {
     if (adjoint)
