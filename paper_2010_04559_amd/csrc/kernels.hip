@@ -635,6 +635,51 @@ __device__ __forceinline__ double lane_backward(cx<double> U, int b, const AxisX
   return U.re;
 }
 
+// The same butterflies with each lane's stage coefficients formed once
+// (per octant): stage d of the forward transform is y' = A_d y + B_d p with
+// p the partner lane's value, and of the inverse U' = C_d U + D_d p; the
+// lane's node bit selects which of the axis coefficients (and whether
+// their conjugates) A..D are, so the stages themselves take no selects.
+struct LaneXf {
+  cx<double> fa[3], fb[3], ba[3], bb[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ LaneXf lane_xf(int flip, bool adj, int b) {
+  LaneXf x;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const AxisXf<double> a = axis_xf<double>((flip >> d) & 1, adj);
+    const bool hi = (b >> d) & 1;
+    const cx<double> f0 = a.fwd[0], f1 = a.fwd[1], c0 = a.bwd[0], c1 = a.bwd[1];
+    // forward: bit clear  y' = f0 y + f1 p;  bit set  y' = conj(f1) y + conj(f0) p
+    x.fa[d] = hi ? cx<double>{f1.re, -f1.im} : f0;
+    x.fb[d] = hi ? cx<double>{f0.re, -f0.im} : f1;
+    // inverse: bit clear  U' = c0 U + conj(c0) p;  bit set  U' = conj(c1) U + c1 p
+    x.ba[d] = hi ? cx<double>{c1.re, -c1.im} : c0;
+    x.bb[d] = hi ? c1 : cx<double>{c0.re, -c0.im};
+  }
+  return x;
+}
+
+template <int DIM>
+__device__ __forceinline__ cx<double> lane_forward_x(double v, const LaneXf &x) {
+  const double p = shx(v, 1);
+  cx<double> y{x.fa[0].re * v + x.fb[0].re * p, x.fa[0].im * v + x.fb[0].im * p};
+#pragma unroll
+  for (int d = 1; d < DIM; ++d) y = cadd(cmul(x.fa[d], y), cmul(x.fb[d], shx(y, 1 << d)));
+  return y;
+}
+
+template <int DIM>
+__device__ __forceinline__ double lane_backward_x(cx<double> U, const LaneXf &x) {
+#pragma unroll
+  for (int d = DIM - 1; d >= 1; --d) U = cadd(cmul(x.ba[d], U), cmul(x.bb[d], shx(U, 1 << d)));
+  // last stage: only the real part is needed
+  const cx<double> p = shx(U, 1);
+  return x.ba[0].re * U.re - x.ba[0].im * U.im + x.bb[0].re * p.re - x.bb[0].im * p.im;
+}
+
 // What a (cell, octant) update needs that does not depend on earlier
 // updates: cell indices, right-hand side and cross sections.  Loaded for
 // the next step before the grid barrier that ends the current one.
@@ -958,6 +1003,7 @@ template <int DIM>
 struct GsCell {
   double vb[3];
   cx<double> U[3][3], Lf[3][3], dinv[3];
+  LaneXf xf;
 };
 
 template <int DIM, bool ADJ>
@@ -1003,6 +1049,7 @@ __device__ __forceinline__ void gs_cell_setup(GsCell<DIM> &cs, const double *uv,
       for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(cs.Lf[i][p], M[p][jj]));
     }
   }
+  cs.xf = lane_xf<DIM>(ord_lds[k0].flip, ADJ, b);
 }
 
 template <int DIM, bool ADJ>
@@ -1033,12 +1080,9 @@ __device__ __forceinline__ void gs_cell_solve(const GsCell<DIM> &cs, const doubl
       }
     }
   }
-  AxisXf<double> ax[3];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) ax[d] = axis_xf<double>((flip >> d) & 1, ADJ);
   cx<double> r[3];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) r[m] = lane_forward<DIM>(v[m], b, ax);
+  for (int m = 0; m < 3; ++m) r[m] = lane_forward_x<DIM>(v[m], cs.xf);
 #pragma unroll
   for (int i = 1; i < 3; ++i)
 #pragma unroll
@@ -1052,7 +1096,7 @@ __device__ __forceinline__ void gs_cell_solve(const GsCell<DIM> &cs, const doubl
   }
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    double o = lane_backward<DIM>(r[m], b, ax);
+    double o = lane_backward_x<DIM>(r[m], cs.xf);
     if (ADJ) o = lane_mass<DIM>(o, NS - 1, true) * (1.0 / g.vol);
     out[m] = o;
   }
