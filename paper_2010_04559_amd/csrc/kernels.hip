@@ -559,13 +559,15 @@ __global__ void k_sigma_planes(const double *__restrict__ sig_t, const double *_
 // use DPP moves (VALU, no LDS round trip): quad permutations for bits 1
 // and 2; for bit 4 the half-row mirror (lane i of 8 takes lane 7 - i)
 // followed by the quad reversal (i takes i ^ 3), together i ^ 4.
+// (every lane of every row is written, so no prior destination value is
+// needed: mov_dpp with bound_ctrl)
 __device__ __forceinline__ int dpp_xor(int v, int mask) {
   switch (mask) {
-    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
     case 4: {
-      const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-      return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);         // quad_perm 3,2,1,0
+      const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+      return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, true);         // quad_perm 3,2,1,0
     }
     default: return __shfl_xor(v, mask, 64);
   }
