@@ -2340,8 +2340,22 @@ void launch_multi_axpy(long long n, int k, const double *const *x, const double 
     hipLaunchKernelGGL(k_multi_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, y);
   }
 }
+// Workgroups of a multi-vector pass: one resident round (a second, partly
+// filled round of long grid-stride workgroups costs more than it hides),
+// at most nblocks (the partial buffer's capacity).
+static int resident_blocks(const void *fn, int nblocks) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess || per_cu < 1)
+    return nblocks;
+  return std::max(1, std::min(nblocks, ncu * per_cu));
+}
+
 void launch_multi_dot(long long n, int k, const double *const *x, const double *y, int kz, const double *z,
                       double *partial, int nblocks, double *out, hipStream_t st) {
+  static const int resident = resident_blocks((const void *)k_multi_dot, 1 << 30);
+  nblocks = std::min(nblocks, resident);
   if (k < 1 || k > kMaxMulti || kz < 0 || kz > k) throw std::runtime_error("multi-dot: bad vector count");
   MultiDotArgs a{};
   a.k = k;
@@ -2355,6 +2369,8 @@ void launch_multi_dot(long long n, int k, const double *const *x, const double *
 }
 void launch_multi_axpy_norm(long long n, int k, const double *const *x, const double *c, double *y,
                             double *partial, int nblocks, double *out, hipStream_t st) {
+  static const int resident = resident_blocks((const void *)k_multi_axpy_norm, 1 << 30);
+  nblocks = std::min(nblocks, resident);
   // all but the last group of vectors without the norm
   int q0 = 0;
   for (; k - q0 > kMaxMulti; q0 += kMaxMulti) launch_multi_axpy(n, kMaxMulti, x + q0, c + q0, y, st);
