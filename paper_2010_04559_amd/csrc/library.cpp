@@ -1040,9 +1040,12 @@ void ensure_krylov(tr_handle *h, int m) {
 //   host:   h = (I + L)^{-1} s, L strictly lower with the Gram rows, which
 //           reproduces the sequential projections of modified Gram-Schmidt
 //   pass 2: w -= sum_i h_i v_i, returning |w|^2.
-// Lg holds the Gram rows (row j written here); hcol receives h.
-double arnoldi_orth(tr_handle *h, int j, double *w, std::vector<double> &Lg, int m, double *hcol, long long n,
-                    hipStream_t st) {
+// The basis is stored unnormalised: v_i = vs[i] V[i], and w = vs[j] W with
+// W the stored vector (the operator applied to the preconditioned stored
+// V[j]); the scales enter the host arithmetic only.  Lg holds the Gram rows
+// (row j written here); hcol receives h; returns |W|^2 after the update.
+double arnoldi_orth(tr_handle *h, int j, double *W, const std::vector<double> &vs, std::vector<double> &Lg, int m,
+                    double *hcol, long long n, hipStream_t st) {
   const int k = j + 1;
   std::vector<const double *> X(h->V.begin(), h->V.begin() + k);
   int off = 0;
@@ -1050,7 +1053,7 @@ double arnoldi_orth(tr_handle *h, int j, double *w, std::vector<double> &Lg, int
   for (int q0 = 0; q0 < k; q0 += 16) {
     const int c = std::min(16, k - q0);
     const int kz = std::min(c, std::max(0, j - q0));
-    tr::launch_multi_dot(n, c, X.data() + q0, w, kz, h->V[j], h->mdot_partial, h->dot_blocks, h->mdot_out + off,
+    tr::launch_multi_dot(n, c, X.data() + q0, W, kz, h->V[j], h->mdot_partial, h->dot_blocks, h->mdot_out + off,
                          st);
     chunks.push_back({q0, c, kz});
     off += c + kz;
@@ -1061,8 +1064,8 @@ double arnoldi_orth(tr_handle *h, int j, double *w, std::vector<double> &Lg, int
   std::vector<double> sv(k);
   off = 0;
   for (auto &ch : chunks) {
-    for (int q = 0; q < ch[1]; ++q) sv[ch[0] + q] = r[off + q];
-    for (int q = 0; q < ch[2]; ++q) Lg[(size_t)j * m + ch[0] + q] = r[off + ch[1] + q];
+    for (int q = 0; q < ch[1]; ++q) sv[ch[0] + q] = vs[ch[0] + q] * vs[j] * r[off + q];
+    for (int q = 0; q < ch[2]; ++q) Lg[(size_t)j * m + ch[0] + q] = vs[j] * vs[ch[0] + q] * r[off + ch[1] + q];
     off += ch[1] + ch[2];
   }
   std::vector<double> c(k);
@@ -1070,9 +1073,9 @@ double arnoldi_orth(tr_handle *h, int j, double *w, std::vector<double> &Lg, int
     double t = sv[i];
     for (int q = 0; q < i; ++q) t -= Lg[(size_t)i * m + q] * hcol[q];
     hcol[i] = t;
-    c[i] = -t;
+    c[i] = -t * vs[i] / vs[j];
   }
-  tr::launch_multi_axpy_norm(n, k, X.data(), c.data(), w, h->dot_partial, h->dot_blocks, h->dot_out, st);
+  tr::launch_multi_axpy_norm(n, k, X.data(), c.data(), W, h->dot_partial, h->dot_blocks, h->dot_out, st);
   double nrm2 = 0;
   HIPCHK(hipMemcpyAsync(&nrm2, h->dot_out, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1080,13 +1083,15 @@ double arnoldi_orth(tr_handle *h, int j, double *w, std::vector<double> &Lg, int
 }
 
 // Restarted right-preconditioned GMRES(m), x0 = 0, modified Gram-Schmidt.
+// The Krylov basis is kept unnormalised with host-side scales (saves a
+// normalisation pass per step): the next basis vector is the updated work
+// vector itself, whose buffer changes place with the work buffer.
 int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
           hipStream_t st) {
   const int m = o->restart;
   ensure_krylov(h, m);
   const long long n = h->vec_len(h->top());
   const bool keepZ = (int)h->Z.size() >= m;
-  double *w = h->kw;
   tr::launch_fill<double>(x, n, 0.0, st);
   tbegin(h, C_ORTH);
   const double bnorm = std::sqrt(dot(h, b, b, n, st));
@@ -1100,7 +1105,8 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
     return TR_OK;
   }
   HIPCHK(hipMemcpyAsync(h->V[0], b, n * sizeof(double), hipMemcpyDeviceToDevice, st));  // r0 = b
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), Lg((size_t)m * m), hcol(m + 1);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), Lg((size_t)m * m), hcol(m + 1),
+      vs(m + 1), yc(m);
   for (int cycle = 0; cycle <= o->max_restarts; ++cycle) {
     tbegin(h, C_ORTH);
     const double beta = std::sqrt(dot(h, h->V[0], h->V[0], n, st));
@@ -1112,21 +1118,21 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       return TR_OK;
     }
     if (cycle == o->max_restarts) break;
-    tbegin(h, C_ORTH);
-    tr::launch_scal(n, 1.0 / beta, h->V[0], st);
-    tend(h);
+    vs[0] = 1.0 / beta;
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
+      // z_j = vs[j] M^{-1} V[j], A z_j = vs[j] W
       double *zj = keepZ ? h->Z[j] : h->tmp2;
+      double *W = h->kw;
       precondition(h, o->prec_mode, adj, h->V[j], zj, st);
-      apply_A(h, adj, zj, w, st);
+      apply_A(h, adj, zj, W, st);
       stats->iters++;
       // modified Gram-Schmidt (two passes over the basis, see arnoldi_orth)
       tbegin(h, C_ORTH);
-      const double hn = std::sqrt(arnoldi_orth(h, j, w, Lg, m, hcol.data(), n, st));
+      const double hn = vs[j] * std::sqrt(arnoldi_orth(h, j, W, vs, Lg, m, hcol.data(), n, st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
       tend(h);
       H[(size_t)(j + 1) * m + j] = hn;
@@ -1140,9 +1146,9 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       sn[j] = hn / rho;
       const bool breakdown = hn == 0.0;
       if (!breakdown) {
-        tbegin(h, C_ORTH);
-        tr::launch_axpby(n, 1.0 / hn, w, 0.0, w, h->V[j + 1], st);
-        tend(h);
+        // v_{j+1} = vs[j] W / hn: W becomes V[j+1]
+        std::swap(h->V[j + 1], h->kw);
+        vs[j + 1] = vs[j] / hn;
       }
       H[(size_t)j * m + j] = rho;
       H[(size_t)(j + 1) * m + j] = 0.0;
@@ -1156,12 +1162,14 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       for (int jj = i + 1; jj < k; ++jj) t -= H[(size_t)i * m + jj] * y[jj];
       y[i] = t / H[(size_t)i * m + i];
     }
+    for (int i = 0; i < k; ++i) yc[i] = y[i] * vs[i];
+    double *w = h->kw;
     tbegin(h, C_ORTH);
     if (keepZ) {
-      tr::launch_multi_axpy(n, k, h->Z.data(), y.data(), x, st);
+      tr::launch_multi_axpy(n, k, h->Z.data(), yc.data(), x, st);
     } else {
       tr::launch_fill<double>(w, n, 0.0, st);
-      tr::launch_multi_axpy(n, k, h->V.data(), y.data(), w, st);
+      tr::launch_multi_axpy(n, k, h->V.data(), yc.data(), w, st);
     }
     tend(h);
     if (!keepZ) {
