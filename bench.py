@@ -85,6 +85,51 @@ def cpu_baseline(prob):
                       "%d^3 grid: %d DoF-updates in %.1f s" % (len(patches), prob.n[0], dofs, t1 - t0)}
 
 
+def oracle_timings(args):
+    """Host timings of the oracle (the CPU baseline leg, extended): one sweep,
+    one scatter application and one V-cycle of the finest level, and the full
+    GMRES solve where it finishes in minutes (the 2-D problem), FP64 numpy
+    with the host's BLAS threads."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import numpy as np
+    from oracle import krylov
+    from oracle_problem import OracleProblem
+    from paper_2010_04559_amd import inputs
+
+    def timed(fn, what=""):
+        r0 = resource.getrusage(resource.RUSAGE_SELF)
+        t0 = time.perf_counter()
+        out = fn()
+        t1 = time.perf_counter()
+        r1 = resource.getrusage(resource.RUSAGE_SELF)
+        cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+        print("oracle %s: %.2f s" % (what, t1 - t0), file=sys.stderr, flush=True)
+        return out, t1 - t0, cpu / max(t1 - t0, 1e-9)
+
+    res = {"host_cpus": os.cpu_count(), "rows": []}
+    for name, prob, full in (("cfg1", inputs.config1(), True), ("cfg2", inputs.config2(args.n), False)):
+        op, t_setup, _ = timed(lambda: OracleProblem(prob), name + " setup")
+        lv = op.outer
+        rng = np.random.default_rng(0)
+        x = rng.standard_normal(lv.A * lv.grid.S)
+        dofs = lv.A * lv.grid.S
+        row = {"workload": name, "dofs": dofs, "setup_s": t_setup}
+        _, t, c = timed(lambda: lv.sweep(x), name + " sweep")
+        row["sweep_s"], row["sweep_dof_per_s"], row["sweep_cores"] = t, dofs / t, c
+        _, t, c = timed(lambda: lv.apply_S(x), name + " scatter")
+        row["scatter_s"], row["scatter_cores"] = t, c
+        _, t, c = timed(lambda: op.mg.vcycle(x), name + " V-cycle")
+        row["vcycle_s"], row["vcycle_cores"] = t, c
+        if full:
+            b = op.rhs()
+            sol, t, c = timed(lambda: krylov.gmres(lv.apply_A, op.mg.vcycle, b, prob.tol, prob.restart),
+                              name + " solve")
+            row["solve_s"], row["solve_iters"], row["solve_cores"] = t, sol.iters, c
+        res["rows"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +142,9 @@ def main():
                     help="cfg2 (default) is the headline line; the others print a measurement line of "
                          "their own (2-D square, 48^3 precision study, 32^3 beam gradient, cone mesh)")
     ap.add_argument("--fd-cells", type=int, default=6, help="finite-difference cells for cfg4/cfg5")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the oracle on the host (sweep, scatter and V-cycle of the 2-D and 32^3 "
+                         "problems, full solve of the 2-D problem)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the kernels whose hardware counters are recorded: a 1 GiB device copy "
                          "(counter calibration), then the finest-level FP64 and FP32 sweeps (3 launches each) "
@@ -106,6 +154,9 @@ def main():
         print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
               "note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.oracle_timings:
+        print(json.dumps(oracle_timings(args)))
+        return
     import torch
     from paper_2010_04559_amd import inputs
     from paper_2010_04559_amd.transport import Transport
