@@ -230,7 +230,7 @@ def main():
     ms_sweep = tr.time_sweep_kernel(L, "f64", reps=20)
     achieved = dofs * 16 / (ms_sweep * 1e-3) / 1e9
     digest = kernel_sources_digest()
-    traffic = measured_traffic("k_sweep_lds<double,3,false,false,true>", digest)
+    traffic = measured_traffic("k_sweep_lds<double,3,false,false,true,true>", digest)
     ms_sweep32 = tr.time_sweep_kernel(L, "f32", reps=20)
     ms_gemm = tr.time_scatter_kernel(L, outer=False, prec="f64", reps=10)
     A = 3 * tr.patches[L]
@@ -267,7 +267,7 @@ def main():
         "breakdown_ms": breakdown,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep_lds<double,3,false,false,true> (finest-level FP64 transport sweep)",
+                     "kernel": "k_sweep_lds<double,3,false,false,true,true> (finest-level FP64 transport sweep)",
                      "ms_per_launch": ms_sweep, "bytes_per_launch": dofs * 16},
         "sweep_kernel": {"fp64_dof_per_s": dofs / (ms_sweep * 1e-3), "fp32_dof_per_s": dofs / (ms_sweep32 * 1e-3),
                          "fp32_ms": ms_sweep32},

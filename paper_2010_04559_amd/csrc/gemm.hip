@@ -62,6 +62,41 @@ struct Vec16 {
 
 constexpr int kXcds = 8;
 
+// Plane-layout output (a sweep input): column gn of row gm goes to the
+// cell's position in row gm's orientation list, keeping the node index; the
+// bias is read at the same place.  The workgroup stages the orientation of
+// its rows and the positions of its columns' cells (all 8 orientations) in
+// LDS once, so the epilogue takes no dependent global loads.
+template <int BM, int BN>
+struct OutMap {
+  unsigned char flip[BM];
+  int pos[8][BN / 4];  // cells of the tile (a cell spans >= 4 columns)
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ void out_map_load(OutMap<BM, BN> &om, const int *pos, const OrdInfo *rord, int m0,
+                                             long long n0, int M, int N, int cell) {
+  const long long C = N / cell;
+  const long long c0 = n0 / cell;
+  const int ncell = BN / cell;
+  for (int t = threadIdx.x; t < BM + 8 * ncell; t += blockDim.x) {
+    if (t < BM) {
+      om.flip[t] = (unsigned char)rord[min(m0 + t, M - 1)].flip;
+    } else {
+      const int u = t - BM, fl = u / ncell, c = u % ncell;
+      om.pos[fl][c] = pos[(long long)fl * C + min(c0 + c, C - 1)];
+    }
+  }
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ long long out_col(const OutMap<BM, BN> &om, long long gn, int gm, int m0, long long n0,
+                                             int cell, const int *pos) {
+  if (!pos) return gn;
+  const int c = (int)((gn - n0) / cell);
+  return (long long)om.pos[om.flip[gm - m0]][c] * cell + (gn % cell);
+}
+
 // C = G * U, optionally C = bias + diag-per-column(colscale) * (G * U) where
 // colscale[c / cell] scales column c (cell = spatial dofs per cell); bias has
 // C's layout.
@@ -70,7 +105,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
                                               int M, int N, int K, int mblocks, int nblocks,
                                               const T *__restrict__ bias, const double *__restrict__ colscale,
-                                              int cell) {
+                                              int cell, const int *__restrict__ pos,
+                                              const OrdInfo *__restrict__ rord) {
   using acc_t = typename Mma<T>::acc_t;
   using V = Vec16<T>;
   constexpr int VN = V::n;
@@ -83,6 +119,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   constexpr int NB = DB ? 2 : 1;
   __shared__ T As[NB][BK][BM + PAD];
   __shared__ T Bs[NB][BK][BN + PAD];
+  __shared__ OutMap<BM, BN> om;
 
   // XCD-aware tile order (see the file comment)
   const int b = blockIdx.x;
@@ -167,6 +204,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         for (int jn = 0; jn < TN; ++jn) acc[i][jn] = Mma<T>::op(a[i], bb[jn], acc[i][jn]);
     }
   };
+  if (pos) out_map_load<BM, BN>(om, pos, rord, m0, n0, M, N, cell);  // read after the loop's barriers
   load(0);
   if (DB) {
     // double-buffered: slice k+1 is loaded into registers during the MFMAs
@@ -202,7 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
         if (gm < M && gn < N) {
-          const long long o = (long long)gm * N + gn;
+          const long long o = (long long)gm * N + out_col<BM, BN>(om, gn, gm, m0, n0, cell, pos);
           T y = acc[i][jn][r];
           if (colscale) y *= cs;
           if (bias) y += bias[o];
@@ -251,9 +289,11 @@ __global__ void k_split_rows(const float *__restrict__ A, int M, int K, int Kp, 
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_bf16x3(
     const __bf16 *__restrict__ As, int Kp, const float *__restrict__ B, float *__restrict__ C, int M, int N, int K,
-    int mblocks, int nblocks, const float *__restrict__ bias, const double *__restrict__ colscale, int cell) {
+    int mblocks, int nblocks, const float *__restrict__ bias, const double *__restrict__ colscale, int cell,
+    const int *__restrict__ pos, const OrdInfo *__restrict__ rord) {
   constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][KP], Bl[2][BN][KP];
+  __shared__ OutMap<BM, BN> om;
   const int b = blockIdx.x;
   const int xcd = b % kXcds, slot = b / kXcds;
   const int mb = slot % mblocks;
@@ -327,6 +367,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
     }
   };
+  if (pos) out_map_load<BM, BN>(om, pos, rord, m0, n0, M, N, cell);  // read after the loop's barriers
   load_a(0);
   load_b(0);
   store_b(0);
@@ -354,7 +395,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm0 + 16 * i + 4 * lk + r;
         if (gm < M && gn < N) {
-          const long long o = (long long)gm * N + gn;
+          const long long o = (long long)gm * N + out_col<BM, BN>(om, gn, gm, m0, n0, cell, pos);
           float y = acc[i][j][r];
           if (colscale) y *= cs;
           if (bias) y += bias[o];
@@ -372,22 +413,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // SIMD (53-57 TF/s), FP32 128 x 128 x 16 (108-110 TF/s).
 template <typename T, int BM, int BN, int BK, bool DB, int WPE>
 static void launch_shape(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
-                         const double *colscale, int cell) {
+                         const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   const int mblocks = (M + BM - 1) / BM;
   const int nblocks = (int)(((long long)N + BN - 1) / BN);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
   const long long grid = (long long)mblocks * nb_pad;
   hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, DB, WPE>), dim3((unsigned)grid), dim3(256), 0, st, A, B, C, M, N, K,
-                     mblocks, nblocks, bias, colscale, cell);
+                     mblocks, nblocks, bias, colscale, cell, pos, rord);
 }
 
 template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
-                 const double *colscale, int cell) {
+                 const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   if (sizeof(T) == 8)
-    launch_shape<T, 64, 128, 8, true, 4>(A, B, C, M, N, K, st, bias, colscale, cell);
+    launch_shape<T, 64, 128, 8, true, 4>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
   else
-    launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell);
+    launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
 }
 int split_rows_kp(int K) { return (K + 31) / 32 * 32; }
 
@@ -399,18 +440,18 @@ void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st) 
 }
 
 void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int N, int K, hipStream_t st,
-                        const float *bias, const double *colscale, int cell) {
+                        const float *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   const int mblocks = (M + 127) / 128;
   const int nblocks = (int)(((long long)N + 127) / 128);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(mblocks * nb_pad)), dim3(256), 0, st,
                      reinterpret_cast<const __bf16 *>(Asplit), split_rows_kp(K), B, C, M, N, K, mblocks, nblocks,
-                     bias, colscale, cell);
+                     bias, colscale, cell, pos, rord);
 }
 
 template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t,
-                                  const double *, const double *, int);
+                                  const double *, const double *, int, const int *, const OrdInfo *);
 template void launch_gemm<float>(const float *, const float *, float *, int, int, int, hipStream_t, const float *,
-                                 const double *, int);
+                                 const double *, int, const int *, const OrdInfo *);
 
 }  // namespace tr

@@ -49,7 +49,19 @@ struct SweepArgs {
   const OrdInfo *ord;
   Planes pl;
   Grid g;
+  // f is stored in plane order: ordinate k's cell at list position i of its
+  // orientation's sweep occupies f[k][i][node] (forward sweeps without s)
+  bool plane_in = false;
 };
+
+// Sweep-input ("plane") layout: pos[flip][cell] = the cell's position in
+// the sweep list of orientation flip ([8][C], device).  Writers of sweep
+// inputs store ordinate k's cell j at position pos[ord[k].flip][j].
+
+// Whether the LDS sweep (the only one that reads the plane layout) runs
+// for this level and element type.
+template <typename T>
+bool sweep_lds_fits(const Planes &pl, const Grid &g, bool has_s);
 
 // Fill SweepArgs::sig_pl from the per-cell cross sections.
 void launch_sigma_planes(const double *sig_t, const double *sig_s, const Planes &pl, const Grid &g, double *out,
@@ -87,14 +99,14 @@ void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *
 // forward sweep, forward coarse solve and forward restriction works in).
 template <typename Tin, typename Tout>
 void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
-                         hipStream_t st);
+                         hipStream_t st, const int *pos = nullptr, const OrdInfo *ord = nullptr);
 
 // Restriction to level l-1: fc[p] = sum_children R_c (sigma_s N (s_new - s_prev))_c
 // (apply_sn = 0: plain fc[p] = sum_children R_c in_c).
 template <typename Tin, typename Tout>
 void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,
                      const int *n_child, int Pc, const double *sig_s, bool apply_sn, const Grid &g,
-                     hipStream_t st);
+                     hipStream_t st, const int *pos = nullptr, const OrdInfo *cord = nullptr);
 
 // Prolongation: uf[c] (+)= P_c uc[owner(c)]
 template <typename Tin, typename Tout>
@@ -144,7 +156,8 @@ void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st);
 // C = bias + colscale[c / cell] * (A B) per column c.
 template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
-                 const double *colscale = nullptr, int cell = 8);
+                 const double *colscale = nullptr, int cell = 8,
+                 const int *pos = nullptr, const OrdInfo *rord = nullptr);
 // FP32 C = A B with split-BF16 operands (three BF16 MFMA products, FP32
 // accumulate); same epilogue as launch_gemm.  Asplit: A split once by
 // launch_split_rows into [hi | lo][M][split_rows_kp(K)] BF16 (device,
@@ -152,6 +165,7 @@ void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t 
 int split_rows_kp(int K);
 void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st);
 void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int N, int K, hipStream_t st,
-                        const float *bias = nullptr, const double *colscale = nullptr, int cell = 8);
+                        const float *bias = nullptr, const double *colscale = nullptr, int cell = 8,
+                        const int *pos = nullptr, const OrdInfo *rord = nullptr);
 
 }  // namespace tr

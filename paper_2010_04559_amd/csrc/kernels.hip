@@ -279,7 +279,7 @@ struct StageRegs {
   int4 lk;
 };
 
-template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, int FLIP>
+template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, bool PIN, int FLIP>
 __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
                                                float4 *stage, int tc) {
   constexpr int NS = 1 << DIM;
@@ -329,7 +329,9 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int jj = __shfl(j, CPI * i + lane % CPI, 64);
-      q.f[i] = *reinterpret_cast<const float4 *>(fk + (long long)jj * NS + ch * EPC);
+      // plane layout: the wave's cells are consecutive list positions
+      const long long fi = PIN ? (long long)min(off[p] + (tid & ~63) + CPI * i + lane % CPI, (int)C - 1) : jj;
+      q.f[i] = *reinterpret_cast<const float4 *>(fk + fi * NS + ch * EPC);
       if (HAS_S) q.s[HAS_S ? i : 0] = *reinterpret_cast<const float4 *>(sk + (long long)jj * NS + ch * EPC);
     }
     q.st = sgt[idx];
@@ -503,7 +505,7 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
   }
 }
 
-template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF>
+template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, bool PIN>
 __global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a, int tc) {
   extern __shared__ __align__(16) unsigned char sweep_smem[];
   constexpr int NS = 1 << DIM;
@@ -519,14 +521,14 @@ __global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a, 
   __syncthreads();
   const int k = blockIdx.x;
   switch (a.ord[k].flip) {
-    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 0>(a, k, lds, jbuf, off, stage, tc); break;
-    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 1>(a, k, lds, jbuf, off, stage, tc); break;
-    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 2>(a, k, lds, jbuf, off, stage, tc); break;
-    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 3>(a, k, lds, jbuf, off, stage, tc); break;
-    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 4>(a, k, lds, jbuf, off, stage, tc); break;
-    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 5>(a, k, lds, jbuf, off, stage, tc); break;
-    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 6>(a, k, lds, jbuf, off, stage, tc); break;
-    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, 7>(a, k, lds, jbuf, off, stage, tc); break;
+    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 0>(a, k, lds, jbuf, off, stage, tc); break;
+    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 1>(a, k, lds, jbuf, off, stage, tc); break;
+    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 2>(a, k, lds, jbuf, off, stage, tc); break;
+    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 3>(a, k, lds, jbuf, off, stage, tc); break;
+    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 4>(a, k, lds, jbuf, off, stage, tc); break;
+    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 5>(a, k, lds, jbuf, off, stage, tc); break;
+    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 6>(a, k, lds, jbuf, off, stage, tc); break;
+    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 7>(a, k, lds, jbuf, off, stage, tc); break;
   }
 }
 
@@ -1359,7 +1361,8 @@ __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, in
 // per ordinate (f~ = N^{-1} f).  One thread per (patch, cell).
 template <typename Tin, typename Tout, int DIM>
 __global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ out, int P, Grid g,
-                               const double *__restrict__ pre, const double *__restrict__ post) {
+                               const double *__restrict__ pre, const double *__restrict__ post,
+                               const int *__restrict__ pos, const OrdInfo *__restrict__ ord) {
   constexpr int NS = 1 << DIM;
   const long long C = g.C, S = g.S;
   const long long total = (long long)P * C;
@@ -1382,8 +1385,9 @@ __global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ ou
 #pragma unroll
       for (int b = 0; b < NS; ++b) y[b] = (2.0 * x[k][b] - (x[0][b] + x[1][b] + x[2][b]) * (1.0 / 3.0)) * sc;
       mass_shape<double, DIM, true>(y);
+      const long long jo = pos ? (long long)pos[(long long)ord[3 * p + k].flip * C + j] : j;  // plane layout
 #pragma unroll
-      for (int b = 0; b < NS; ++b) out[(3LL * p + k) * S + j * NS + b] = (Tout)(y[b] * iv);
+      for (int b = 0; b < NS; ++b) out[(3LL * p + k) * S + jo * NS + b] = (Tout)(y[b] * iv);
     }
   }
 }
@@ -1393,7 +1397,7 @@ template <typename Tin, typename Tout, int DIM>
 __global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict__ s_prev, Tout *__restrict__ fc,
                            const double *__restrict__ R, const int *__restrict__ first_child,
                            const int *__restrict__ n_child, int Pc, const double *__restrict__ sig_s,
-                           int apply_sn, Grid g) {
+                           int apply_sn, Grid g, const int *__restrict__ pos, const OrdInfo *__restrict__ cord) {
   constexpr int NS = 1 << DIM;
   const long long C = g.C, S = g.S;
   const long long total = (long long)Pc * C;
@@ -1437,7 +1441,9 @@ __global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict_
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const long long off = (3LL * p + k) * S + j * NS;
+      // plane layout: the cell's position in its ordinate's sweep list
+      const long long jo = pos ? (long long)pos[(long long)cord[3 * p + k].flip * C + j] : j;
+      const long long off = (3LL * p + k) * S + jo * NS;
 #pragma unroll
       for (int b = 0; b < NS; ++b) fc[off + b] = (Tout)out[k][b];
     }
@@ -2067,7 +2073,13 @@ static bool launch_sweep_lds(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
   const bool dbuf = stage + 2 * plane + tail <= 160 * 1024;
   const size_t lds = stage + (dbuf ? 2 : 1) * plane + tail;
   if (lds > 160 * 1024) return false;
-  auto fn = dbuf ? k_sweep_lds<T, DIM, ADJ, HAS_S, true> : k_sweep_lds<T, DIM, ADJ, HAS_S, false>;
+  // right-hand side in plane layout: forward sweeps without s only
+  const bool pin = a.plane_in && !ADJ && !HAS_S;
+  if (a.plane_in && !pin) throw std::runtime_error("plane-layout input needs a forward sweep without s");
+  auto fn = dbuf ? (pin ? k_sweep_lds<T, DIM, ADJ, HAS_S, true, !ADJ && !HAS_S>
+                        : k_sweep_lds<T, DIM, ADJ, HAS_S, true, false>)
+                 : (pin ? k_sweep_lds<T, DIM, ADJ, HAS_S, false, !ADJ && !HAS_S>
+                        : k_sweep_lds<T, DIM, ADJ, HAS_S, false, false>);
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return false;
@@ -2075,10 +2087,22 @@ static bool launch_sweep_lds(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
   return true;
 }
 
+template <typename T>
+bool sweep_lds_fits(const Planes &pl, const Grid &g, bool has_s) {
+  const int tc = (pl.max_plane + 63) / 64 * 64;
+  if (tc > kSweepLdsThreads - 64) return false;
+  const size_t stage = (size_t)(tc / 64) * (has_s ? 2 : 1) * 64 * sizeof(T) * g.ns;
+  const size_t plane = (sizeof(T) * (size_t)g.ns + sizeof(int)) * (size_t)pl.max_plane;
+  return stage + plane + sizeof(int) * (pl.nplanes + 1) <= 160 * 1024;  // as launch_sweep_lds
+}
+template bool sweep_lds_fits<double>(const Planes &, const Grid &, bool);
+template bool sweep_lds_fits<float>(const Planes &, const Grid &, bool);
+
 template <typename T, int DIM, bool ADJ>
 static void launch_sweep_r(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
   if (a.s ? launch_sweep_lds<T, DIM, ADJ, true>(a, n_ord, st) : launch_sweep_lds<T, DIM, ADJ, false>(a, n_ord, st))
     return;
+  if (a.plane_in) throw std::runtime_error("plane-layout input needs the LDS sweep");
   const int R = (a.pl.max_plane + kSweepThreads - 1) / kSweepThreads;
   // register prefetch of the next plane when a thread owns one cell per
   // plane; with more cells per thread the prefetch buffers would halve the
@@ -2190,19 +2214,21 @@ void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *
 }
 template <typename Tin, typename Tout>
 void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
-                         hipStream_t st) {
+                         hipStream_t st, const int *pos, const OrdInfo *ord) {
   const int grid = grid_for((long long)P * g.C);
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post);
+    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post, pos,
+                       ord);
   else
-    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post);
+    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post, pos,
+                       ord);
 }
 template void launch_convert_minv<double, double>(const double *, double *, int, const Grid &, const double *,
-                                                  const double *, hipStream_t);
+                                                  const double *, hipStream_t, const int *, const OrdInfo *);
 template void launch_convert_minv<double, float>(const double *, float *, int, const Grid &, const double *,
-                                                 const double *, hipStream_t);
+                                                 const double *, hipStream_t, const int *, const OrdInfo *);
 template void launch_convert_minv<float, float>(const float *, float *, int, const Grid &, const double *,
-                                                const double *, hipStream_t);
+                                                const double *, hipStream_t, const int *, const OrdInfo *);
 template void launch_convert<double, double>(const double *, double *, int, long long, const double *,
                                              const double *, hipStream_t);
 template void launch_convert<double, float>(const double *, float *, int, long long, const double *, const double *,
@@ -2215,18 +2241,19 @@ template void launch_convert<float, float>(const float *, float *, int, long lon
 template <typename Tin, typename Tout>
 void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,
                      const int *n_child, int Pc, const double *sig_s, bool apply_sn, const Grid &g,
-                     hipStream_t st) {
+                     hipStream_t st, const int *pos, const OrdInfo *cord) {
   const int grid = grid_for((long long)Pc * g.C);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_restrict<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, s_new, s_prev, fc, R,
-                       first_child, n_child, Pc, sig_s, (int)apply_sn, g);
+                       first_child, n_child, Pc, sig_s, (int)apply_sn, g, pos, cord);
   else
     hipLaunchKernelGGL((k_restrict<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, s_new, s_prev, fc, R,
-                       first_child, n_child, Pc, sig_s, (int)apply_sn, g);
+                       first_child, n_child, Pc, sig_s, (int)apply_sn, g, pos, cord);
 }
 #define TR_INST_RESTRICT(TI, TO)                                                                               \
   template void launch_restrict<TI, TO>(const TI *, const TI *, TO *, const double *, const int *, const int *, \
-                                        int, const double *, bool, const Grid &, hipStream_t);
+                                        int, const double *, bool, const Grid &, hipStream_t, const int *,     \
+                                        const OrdInfo *);
 TR_INST_RESTRICT(double, double)
 TR_INST_RESTRICT(float, float)
 TR_INST_RESTRICT(float, double)

@@ -65,6 +65,9 @@ void mat3_mul(const double *a, const double *b, double *c) {
 
 struct DevLevel {
   int P = 0, A = 0, order = 0;
+  // forward sweep inputs (f and the post-smoothing right-hand side) are
+  // kept in plane layout (see tr::SweepArgs::plane_in)
+  bool pin = false;
   OrdInfo *ord = nullptr;
   double *w = nullptr, *winv = nullptr, *ipsi = nullptr;
   double *St64 = nullptr;      // canonical S~ (order of this level), A x A
@@ -184,6 +187,7 @@ struct tr_handle {
   };
   bool gs_brick = true;       // dataflow solve over 2 x 2 x 2 bricks where the grid allows
   bool split32 = false;       // FP32 scatter products from split-BF16 operands
+  int *pos_pl = nullptr;      // [8][cells] position of a cell in each orientation's sweep list
   struct SplitA {             // level matrices split into BF16 hi/lo once
     const float *A;
     int M, K;
@@ -351,6 +355,20 @@ void build(tr_handle *h, const tr_problem *p) {
     h->pl.link[0] = reinterpret_cast<const int4 *>(h->upload(link_up));
     h->pl.link[1] = reinterpret_cast<const int4 *>(h->upload(link_dn));
     h->plane_off_host = off;
+    // position of every cell in each orientation's sweep list (the plane
+    // layout of forward sweep inputs)
+    {
+      std::vector<int> ppos(8 * (size_t)g.C);
+      for (int fl = 0; fl < 8; ++fl)
+        for (size_t i = 0; i < cells.size(); ++i) {
+          const int c = cells[i];
+          int ix[3] = {c & 1023, (c >> 10) & 1023, (c >> 20) & 1023};
+          for (int d = 0; d < 3; ++d)
+            if ((fl >> d) & 1) ix[d] = g.n[d] - 1 - ix[d];
+          ppos[(size_t)fl * g.C + lin(ix[0], ix[1], ix[2])] = (int)i;
+        }
+      h->pos_pl = h->upload(ppos);
+    }
     h->d_cells = h->upload(cells);
     h->d_off = h->upload(off);
     h->pl.cells = h->d_cells;
@@ -391,6 +409,11 @@ void build(tr_handle *h, const tr_problem *p) {
       winv[a] = 1.0 / H.w[a];
     }
     D.ord = h->upload(ord);
+    // forward sweep inputs in plane layout on the V-cycle's smoothing levels
+    // when their sweeps run in the LDS kernel (one pre-smoothing sweep: the
+    // restricted residual then needs no plane-layout input)
+    D.pin = l >= 1 && l < nlev && h->prob.nu_pre == 1 && tr::sweep_lds_fits<double>(h->pl, g, false) &&
+            tr::sweep_lds_fits<float>(h->pl, g, false);
     D.w = h->upload(H.w);
     D.winv = h->upload(winv);
     D.ipsi = h->upload(H.ipsi);
@@ -580,6 +603,7 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   a.ord = h->lv[l].ord;
   a.pl = h->pl;
   a.g = h->g;
+  a.plane_in = !adj && h->lv[l].pin;
   const bool fine = l == h->top();
   h->sweep_dofs += (double)h->lv[l].A * (double)h->g.S;
   tbegin(h, fine ? C_SWEEP_FINE : C_SWEEP);
@@ -602,23 +626,25 @@ const void *split_of(tr_handle *h, const float *A, int M, int K, hipStream_t st)
 // preconditioner mode asks for it.
 template <typename T>
 void gemm(tr_handle *h, const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
-          const double *colscale = nullptr, int cell = 8) {
+          const double *colscale = nullptr, int cell = 8, const int *pos = nullptr, const OrdInfo *rord = nullptr) {
   if constexpr (std::is_same<T, float>::value) {
     if (h->split32) {
-      tr::launch_gemm_bf16x3(split_of(h, A, M, K, st), B, C, M, N, K, st, bias, colscale, cell);
+      tr::launch_gemm_bf16x3(split_of(h, A, M, K, st), B, C, M, N, K, st, bias, colscale, cell, pos, rord);
       return;
     }
   }
-  tr::launch_gemm<T>(A, B, C, M, N, K, st, bias, colscale, cell);
+  tr::launch_gemm<T>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
 }
 
 // y = G x, or y = bias + sigma_s (G x) per cell with scale_sn (bias may be
-// null): the forward V-cycle's prepared right-hand sides.
+// null): the forward V-cycle's prepared right-hand sides; with rord the
+// result (and the bias) are in plane layout for the level's ordinates.
 template <typename T>
 void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st, bool scale_sn = false,
-             const T *bias = nullptr) {
+             const T *bias = nullptr, const OrdInfo *rord = nullptr) {
   tbegin(h, C_SCATTER);
-  gemm<T>(h, G, x, y, A, (int)h->g.S, A, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns);
+  gemm<T>(h, G, x, y, A, (int)h->g.S, A, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns,
+          rord ? h->pos_pl : nullptr, rord);
   tend(h);
 }
 
@@ -846,17 +872,19 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
 // intermediate: G u = L (R^T u), G^T u = R (L^T u).
 template <typename T>
 void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t st, bool scale_sn = false,
-                   const T *bias = nullptr) {
+                   const T *bias = nullptr, bool plane_out = false) {
   DevLevel &D = h->lv[l];
+  const OrdInfo *rord = plane_out ? D.ord : nullptr;
   if (!D.Kf) {
-    do_gemm<T>(h, LevelBuf<T>::G(D, adj), u, y, D.A, st, scale_sn, bias);
+    do_gemm<T>(h, LevelBuf<T>::G(D, adj), u, y, D.A, st, scale_sn, bias, rord);
     return;
   }
   T *tmp = LevelBuf<T>::fact(h);
   const int S = (int)h->g.S;
   tbegin(h, C_SCATTER);
   gemm<T>(h, LevelBuf<T>::Lf(D, adj), u, tmp, D.Kf, S, D.A, st);
-  gemm<T>(h, LevelBuf<T>::Rf(D, adj), tmp, y, D.A, S, D.Kf, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns);
+  gemm<T>(h, LevelBuf<T>::Rf(D, adj), tmp, y, D.A, S, D.Kf, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns,
+          rord ? h->pos_pl : nullptr, rord);
   tend(h);
 }
 
@@ -885,7 +913,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   T *s_prev = nullptr;
   for (int it = 1; it < nu_pre; ++it) {
     if (!adj) {
-      level_scatter<T>(h, l, adj, u, sa, st, true, f);
+      level_scatter<T>(h, l, adj, u, sa, st, true, f, D.pin);
       do_sweep<T>(h, l, sa, nullptr, u, adj, st);
     } else {
       level_scatter<T>(h, l, adj, u, sa, st);
@@ -906,7 +934,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
                                    adj, h->g, st);
   else
     tr::launch_restrict<T, T>(sa, s_prev, LevelBuf<T>::f(Dc), adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P,
-                              h->sig_s, adj, h->g, st);
+                              h->sig_s, adj, h->g, st, !adj && Dc.pin ? h->pos_pl : nullptr, Dc.ord);
   tend(h);
   if (l - 1 == 0)
     do_coarse(h, Dc.f64, Dc.u64, h->prob.nu_coarse, adj, st);
@@ -920,7 +948,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   tend(h);
   for (int it = 0; it < nu_post; ++it) {
     if (!adj) {
-      level_scatter<T>(h, l, adj, u, sa, st, true, f);
+      level_scatter<T>(h, l, adj, u, sa, st, true, f, D.pin);
       do_sweep<T>(h, l, sa, nullptr, u, adj, st);
     } else {
       level_scatter<T>(h, l, adj, u, sa, st);
@@ -939,7 +967,7 @@ void convert_in(tr_handle *h, int level, bool adj, const Tin *r, Tout *f, hipStr
   if (adj)
     tr::launch_convert<Tin, Tout>(r, f, D.P, h->g.S, nullptr, nullptr, st);
   else
-    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st);
+    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st, D.pin ? h->pos_pl : nullptr, D.ord);
 }
 
 void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st) {
