@@ -1385,7 +1385,8 @@ __global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ ou
 #pragma unroll
       for (int b = 0; b < NS; ++b) y[b] = (2.0 * x[k][b] - (x[0][b] + x[1][b] + x[2][b]) * (1.0 / 3.0)) * sc;
       mass_shape<double, DIM, true>(y);
-      const long long jo = pos ? (long long)pos[(long long)ord[3 * p + k].flip * C + j] : j;  // plane layout
+      // plane layout (the three ordinates of a patch share the orientation)
+      const long long jo = pos ? (long long)pos[(long long)ord[3 * p].flip * C + j] : j;
 #pragma unroll
       for (int b = 0; b < NS; ++b) out[(3LL * p + k) * S + jo * NS + b] = (Tout)(y[b] * iv);
     }
@@ -1441,8 +1442,9 @@ __global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict_
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      // plane layout: the cell's position in its ordinate's sweep list
-      const long long jo = pos ? (long long)pos[(long long)cord[3 * p + k].flip * C + j] : j;
+      // plane layout: the cell's position in its ordinate's sweep list (the
+      // three ordinates of a patch share the orientation)
+      const long long jo = pos ? (long long)pos[(long long)cord[3 * p].flip * C + j] : j;
       const long long off = (3LL * p + k) * S + jo * NS;
 #pragma unroll
       for (int b = 0; b < NS; ++b) fc[off + b] = (Tout)out[k][b];
