@@ -198,3 +198,26 @@ def test_coarse_gs_bricks_noncubic():
         assert rel(to_np(pr.tr.coarse_gs(to_dev(f), nu)), pr.op.mg.coarse_gs(f, nu)) < 1e-11
         assert rel(to_np(pr.tr.coarse_gs(to_dev(f), nu, adjoint=True)),
                    pr.op.mg.coarse_gs(f, nu, adjoint=True)) < 1e-11
+
+
+def test_coarse_gs_forms_agree():
+    """The dataflow (brick and cell) and barrier forms of the coarse solve
+    give the oracle's result; 16 sweeps exceed the dataflow counters' range
+    and take the barrier form."""
+    import os
+    prob = small(dim=3, n=4, level=0, order=3, seed=21)
+    print("case 4^3 level 0, forms", flush=True)
+    for form in ("", "cell", "barrier", "barrier_fence"):
+        os.environ["TR_COARSE_GS"] = form
+        try:
+            pr = Pair(prob)
+        finally:
+            os.environ.pop("TR_COARSE_GS", None)
+        lv0 = pr.op.mg.levels[0]
+        f = _rand(lv0.A * lv0.grid.S, 22)
+        for nu in (2, 16):
+            ref = pr.op.mg.coarse_gs(f, nu)
+            assert rel(to_np(pr.tr.coarse_gs(to_dev(f), nu)), ref) < 1e-11, (form, nu)
+            refa = pr.op.mg.coarse_gs(f, nu, adjoint=True)
+            assert rel(to_np(pr.tr.coarse_gs(to_dev(f), nu, adjoint=True)), refa) < 1e-11, (form, nu)
+        pr.tr.close()
