@@ -1199,62 +1199,69 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
   }
 }
 
-// Brick form of the dataflow solve (3-D, even cell counts): one wave
-// updates a 2 x 2 x 2 brick of cells for one (sweep, octant), 8 lanes per
-// cell.  Dependencies and counters are per brick, exactly as the cell form
-// has them per cell, so fewer dependent steps cross the device (the brick
-// grid is half as wide).  Inside the brick the cells are taken in the four
-// diagonal planes of the sweep direction; the inflow a cell takes from a
-// neighbour in the same brick comes from that cell's lanes by a shuffle,
-// from a neighbour outside it by a device-coherent load after the wait.
-// The part of each cell's right-hand side that does not depend on the
-// inflow (source and scatter from the other octants' values), and the
-// factorised 3 x 3 mode systems, are formed once per brick, between the
-// wait for the brick's own earlier update and the wait for the upwind
-// bricks.
-// Slot items: octant << 29 | c << 22 | brick index (one brick per slot).
-template <bool ADJ>
-__global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, double *u,
-                                                  const double *__restrict__ G, const double *__restrict__ sig_t,
-                                                  const double *__restrict__ sig_s,
-                                                  const OrdInfo *__restrict__ ord, Grid g,
-                                                  const int *__restrict__ wave_off, const int *__restrict__ slots,
-                                                  int nwaves, unsigned *cnt, int *err) {
+// Brick form of the dataflow solve (forward, 3-D, even cell counts): one
+// workgroup of three waves updates a 2 x 2 x 2 brick of cells for one
+// (sweep, octant); wave m takes ordinate 3 octant + m of the octant's patch
+// at the brick's 64 cell nodes (8 lanes per cell).  Dependencies and
+// counters are per brick (cnt[B] = updates done), so fewer dependent steps
+// cross the device than in the cell form (the brick grid is half as wide).
+// Inside the brick the cells are taken in the four diagonal planes of the
+// sweep direction; the inflow a cell takes from a neighbour in the same
+// brick comes from that cell's lanes by a shuffle, from a neighbour
+// outside it by a device-coherent load.  Per plane each wave transforms
+// its own ordinate only; the 3 x 3 mode coupling is a product with the
+// lane's row of the inverse mode matrix (formed in the set-up, off the
+// dependent chain) after the three waves exchange their transformed
+// right-hand sides through LDS (one barrier per plane).
+// Slot items: octant << 29 | c << 22 | brick index (one brick per slot);
+// one workgroup of 192 threads per slot list.
+__global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, double *u,
+                                                   const double *__restrict__ G, const double *__restrict__ sig_t,
+                                                   const double *__restrict__ sig_s,
+                                                   const OrdInfo *__restrict__ ord, Grid g,
+                                                   const int *__restrict__ wave_off, const int *__restrict__ slots,
+                                                   int nlists, unsigned *cnt, int *err) {
   constexpr int DIM = 3, NS = 8;
   __shared__ double G_lds[24 * 24];
   __shared__ OrdInfo ord_lds[24];
+  __shared__ cx<double> rx[2][3][64];  // transformed right-hand sides, by plane parity
+  __shared__ int up_flag;               // wave 0 found the upwind bricks done
   for (int i = threadIdx.x; i < 24 * 24; i += blockDim.x) G_lds[i] = G[i];
   if (threadIdx.x < 24) ord_lds[threadIdx.x] = ord[threadIdx.x];
   __syncthreads();
+  const int list = blockIdx.x;
+  if (list >= nlists) return;  // uniform over the workgroup
   const int lane = threadIdx.x & 63;
-  const int b = lane & 7;    // Q1 node of the lane's cell
-  const int grp = lane >> 3; // cell of the brick: bit d = position along d in sweep order
-  const int sub = (grp & 1) + ((grp >> 1) & 1) + ((grp >> 2) & 1);  // its diagonal plane in the brick
-  const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (wave >= nwaves) return;
+  const int m = threadIdx.x >> 6;  // ordinate of the patch (wave-uniform)
+  const int m1 = m == 0 ? 1 : 0, m2 = m == 2 ? 1 : 2;  // the other two
+  const int b = lane & 7;
+  const int grp = lane >> 3;
+  const int sub = (grp & 1) + ((grp >> 1) & 1) + ((grp >> 2) & 1);
   const int nb[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
   const long long S = g.S;
-  const int s0 = wave_off[wave], s1 = wave_off[wave + 1];
+  const double r2 = 1.41421356237309504880;
+  const int s0 = wave_off[list], s1 = wave_off[list + 1];
   for (int sl = s0; sl < s1; ++sl) {
     const int item = __builtin_amdgcn_readfirstlane(slots[sl]);
     const int octant = (item >> 29) & 7;
     const unsigned c = (unsigned)((item >> 22) & 127);
     const int B = item & ((1 << 22) - 1);
     const int k0 = 3 * octant;
+    const int km = k0 + m;
     const int flip = ord_lds[k0].flip;
     const int bx[3] = {B % nb[0], (B / nb[0]) % nb[1], B / (nb[0] * nb[1])};
-    int ix[3], pc[3], nbr[3];
+    int ix[3], nbr[3];
     long long jn[3];
     bool ext[3];
     long long mydep = -1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const bool rev = (((flip >> d) & 1) != 0) != ADJ;  // sweep runs towards lower indices
+      const bool rev = ((flip >> d) & 1) != 0;  // sweep runs towards lower indices
       const int pb = rev ? nb[d] - 1 - bx[d] : bx[d];
       const int lp = (grp >> d) & 1;
-      pc[d] = 2 * pb + lp;
-      ix[d] = rev ? g.n[d] - 1 - pc[d] : pc[d];
-      ext[d] = lp == 0 && pc[d] > 0;  // inflow from the neighbouring brick
+      const int pc = 2 * pb + lp;
+      ix[d] = rev ? g.n[d] - 1 - pc : pc;
+      ext[d] = lp == 0 && pc > 0;
       nbr[d] = rev ? ix[d] + 1 : ix[d] - 1;
       if (grp == 0 && b == 1 + d && pb > 0) {
         int by[3] = {bx[0], bx[1], bx[2]};
@@ -1270,64 +1277,145 @@ __global__ __launch_bounds__(256) void k_gs_brick(const double *__restrict__ f, 
       nx[d] = ext[d] ? nbr[d] : ix[d];
       jn[d] = cell_index(nx, g);
     }
-    double fv[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) fv[m] = f[(k0 + m) * S + j * NS + b];
+    const double fv = f[km * S + j * NS + b];
     const double st = sig_t[j], ss = sig_s[j];
 
-    // wait for the brick's own earlier updates (lane 0), then form what
-    // depends on them only; then wait for the upwind bricks (lanes 1..3)
-    if (!wait_counters(cnt, lane == 0 ? mydep : -1, c, true, err)) return;
+    // Waits are taken by wave 0 alone and passed on through the barrier,
+    // so the three waves leave together.  Lane 0 polls the brick's own
+    // earlier update; lanes 1..3 sample the upwind bricks in the same
+    // round trips.  When these are already done, the iterate and the
+    // inflow traces are fetched at once; otherwise the set-up is formed
+    // first and wave 0 then waits for the upwind bricks.
+    bool ok = true, up_ready = true;
+    if (m == 0) {
+      const bool own = lane == 0;
+      bool ready = !own, upr = mydep < 0 || own;
+      long spins = 0;
+      while (true) {
+        if (!ready) ready = __hip_atomic_load(cnt + mydep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == c;
+        if (!upr) upr = __hip_atomic_load(cnt + mydep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= c + 1;
+        if (__ballot(!ready) == 0) break;
+        if (++spins > (1L << 22) ||
+            (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      up_ready = __ballot(!upr) == 0;
+      if (lane == 0) up_flag = up_ready ? 1 : 0;
+    }
+    if (__syncthreads_or(!ok)) return;  // a wait timed out (err is set)
+    up_ready = up_flag != 0;
     asm volatile("" ::: "memory");
-    // the brick's own values: all 24 ordinates at the lane's node
-    const double *up = u + j * NS + b;
     double uv[24];
+    {
+      const double *up = u + j * NS + b;
 #pragma unroll
-    for (int kp = 0; kp < 24; ++kp) uv[kp] = ld_dev(up + kp * S);
-    GsCell<DIM> cs;
-    gs_cell_setup<DIM, ADJ>(cs, uv, fv, st, ss, octant, b, G_lds, ord_lds, g);
+      for (int kp = 0; kp < 24; ++kp) uv[kp] = ld_dev(up + kp * S);
+    }
+    double tex[DIM] = {0.0, 0.0, 0.0};
+    if (up_ready) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int nbit = ((flip >> d) & 1) ? 0 : 1;
+        const int bn = (b & ~(1 << d)) | (nbit << d);
+        tex[d] = ext[d] ? ld_dev(u + km * S + jn[d] * NS + bn) : 0.0;
+      }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int kp = 0; kp < 24; ++kp) acc += (kp / 3 == octant) ? 0.0 : G_lds[km * 24 + kp] * uv[kp];
+    const double vb = fv + ss * acc;
+    // mode matrix M = L U (unit L) of the three ordinates at mode b
+    cx<double> M[3][3], Lf[3][3], dinv[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const OrdInfo &o = ord_lds[k0 + q];
+#pragma unroll
+      for (int qp = 0; qp < 3; ++qp) M[q][qp] = cx<double>{-ss * G_lds[(k0 + q) * 24 + k0 + qp], 0.0};
+      double re = st, im = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        re += 2.0 * o.c[d];
+        im += (((b >> d) & 1) ? -r2 : r2) * o.c[d];
+      }
+      M[q][q].re += re;
+      M[q][q].im += im;
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      dinv[p] = cinv(M[p][p]);
+#pragma unroll
+      for (int i = p + 1; i < 3; ++i) {
+        Lf[i][p] = cmul(M[i][p], dinv[p]);
+#pragma unroll
+        for (int jj = p + 1; jj < 3; ++jj) M[i][jj] = csub(M[i][jj], cmul(Lf[i][p], M[p][jj]));
+      }
+    }
+    // row m of M^-1 solves M^T y = e_m:  U^T z = e_m, then L^T y = z
+    cx<double> w[3], z[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      cx<double> s{q == m ? 1.0 : 0.0, 0.0};
+#pragma unroll
+      for (int qq = 0; qq < q; ++qq) s = csub(s, cmul(M[qq][q], z[qq]));
+      z[q] = cmul(s, dinv[q]);
+    }
+#pragma unroll
+    for (int q = 2; q >= 0; --q) {
+      cx<double> s = z[q];
+#pragma unroll
+      for (int qq = q + 1; qq < 3; ++qq) s = csub(s, cmul(Lf[qq][q], w[qq]));
+      w[q] = s;
+    }
+    const LaneXf xf = lane_xf<DIM>(flip, false, b);
+    if (!up_ready) {
+      if (m == 0) ok = wait_counters(cnt, lane != 0 ? mydep : -1, c, false, err);
+      if (__syncthreads_or(!ok)) return;
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int nbit = ((flip >> d) & 1) ? 0 : 1;
+        const int bn = (b & ~(1 << d)) | (nbit << d);
+        tex[d] = ext[d] ? ld_dev(u + km * S + jn[d] * NS + bn) : 0.0;
+      }
+    }
 
-    if (!wait_counters(cnt, lane != 0 ? mydep : -1, c, false, err)) return;
-    asm volatile("" ::: "memory");
-    // inflow traces from outside the brick
-    double tex[3][DIM];
+    const OrdInfo &om = ord_lds[km];
+    // the row's entries for this wave's ordinate and the other two
+    // (selects: m is uniform but not a compile-time index)
+    const cx<double> wm = m == 0 ? w[0] : (m == 1 ? w[1] : w[2]);
+    const cx<double> wm1 = m == 0 ? w[1] : w[0];
+    const cx<double> wm2 = m == 2 ? w[1] : w[2];
+    double res = 0.0;
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
+    for (int p = 0; p < 4; ++p) {
+      double v = vb;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         const int fl = (flip >> d) & 1;
-        const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+        const int nbit = fl ? 0 : 1;
         const int bn = (b & ~(1 << d)) | (nbit << d);
-        tex[m][d] = ext[d] ? ld_dev(u + (k0 + m) * S + jn[d] * NS + bn) : 0.0;
+        // the upwind cell inside the brick finished in the previous plane
+        const double tin = __shfl(res, ((grp ^ (1 << d)) << 3) | bn, 64);
+        const double t = ((grp >> d) & 1) ? tin : tex[d];
+        v += (((b >> d) & 1) == fl ? 4.0 : -2.0) * om.c[d] * t;
       }
-
-    double res[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      double t[3][DIM];
-#pragma unroll
-      for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          const int fl = (flip >> d) & 1;
-          const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
-          const int bn = (b & ~(1 << d)) | (nbit << d);
-          // the upwind cell inside the brick finished in the previous plane
-          const double tin = __shfl(res[m], ((grp ^ (1 << d)) << 3) | bn, 64);
-          t[m][d] = ((grp >> d) & 1) ? tin : tex[m][d];
-        }
-      double out[3];
-      gs_cell_solve<DIM, ADJ>(cs, t, octant, flip, b, ord_lds, g, out);
-#pragma unroll
-      for (int m = 0; m < 3; ++m)
-        if (sub == p) res[m] = out[m];
+      const cx<double> r = lane_forward_x<DIM>(v, xf);
+      rx[p & 1][m][lane] = r;
+      __syncthreads();
+      const cx<double> x = cadd(cadd(cmul(wm, r), cmul(wm1, rx[p & 1][m1][lane])), cmul(wm2, rx[p & 1][m2][lane]));
+      const double o = lane_backward_x<DIM>(x, xf);
+      if (sub == p) res = o;
     }
-#pragma unroll
-    for (int m = 0; m < 3; ++m) st_dev(u + (k0 + m) * S + j * NS + b, res[m]);
+    st_dev(u + km * S + j * NS + b, res);
     asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the brick's stores are acknowledged
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are acknowledged
     asm volatile("" ::: "memory");
-    if (lane == 0) __hip_atomic_store(cnt + B, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();                     // ... and those of the other two waves
+    if (threadIdx.x == 0) __hip_atomic_store(cnt + B, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -2167,14 +2255,14 @@ void launch_coarse_brick(const double *f, double *u, const double *G, const doub
                          const OrdInfo *ord, const Grid &g, const int *wave_off, const int *slots, int waves,
                          bool adjoint, unsigned *cnt, long long nbricks, int *err, hipStream_t st) {
   if (g.dim != 3 || (g.n[0] | g.n[1] | g.n[2]) & 1) throw std::runtime_error("brick Gauss-Seidel needs even 3-D grids");
+  if (adjoint) throw std::runtime_error("brick Gauss-Seidel is forward only");
   launch_fill<double>(u, 24LL * g.S, 0.0, st);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nbricks)), dim3(kBlock), 0, st, cnt, nbricks);
-  void *fn = adjoint ? (void *)k_gs_brick<true> : (void *)k_gs_brick<false>;
-  const int blocks = (waves + 3) / 4;
   void *args[] = {(void *)&f,   (void *)&u,        (void *)&G,     (void *)&sig_t, (void *)&sig_s,
                   (void *)&ord, (void *)&g,        (void *)&wave_off, (void *)&slots, (void *)&waves,
                   (void *)&cnt, (void *)&err};
-  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st) != hipSuccess)
+  // one workgroup of three waves per slot list
+  if (hipLaunchCooperativeKernel((void *)k_gs_brick, dim3(waves), dim3(192), args, 0, st) != hipSuccess)
     throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
 }
 
