@@ -82,7 +82,7 @@ void launch_sweep(const SweepArgs<T> &a, int n_ord, bool adjoint, hipStream_t st
 void launch_coarse_flow(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                         const OrdInfo *ord, const Planes &pl, const Grid &g, const int *wave_off, const int *slots,
                         int waves, bool adjoint, unsigned *cnt, int *err, hipStream_t st);
-// The forward solve over 2 x 2 x 2 bricks (3-D, even grids): waves = slot
+// The same solve over 2 x 2 x 2 bricks (3-D, even grids): waves = slot
 // lists, one workgroup of three waves each; cnt[nbricks] zeroed here.
 void launch_coarse_brick(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                          const OrdInfo *ord, const Grid &g, const int *wave_off, const int *slots, int waves,

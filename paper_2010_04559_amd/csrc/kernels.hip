@@ -1199,7 +1199,7 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
   }
 }
 
-// Brick form of the dataflow solve (forward, 3-D, even cell counts): one
+// Brick form of the dataflow solve (3-D, even cell counts): one
 // workgroup of three waves updates a 2 x 2 x 2 brick of cells for one
 // (sweep, octant); wave m takes ordinate 3 octant + m of the octant's patch
 // at the brick's 64 cell nodes (8 lanes per cell).  Dependencies and
@@ -1215,6 +1215,7 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
 // right-hand sides through LDS (one barrier per plane).
 // Slot items: octant << 29 | c << 22 | brick index (one brick per slot);
 // one workgroup of 192 threads per slot list.
+template <bool ADJ>
 __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, double *u,
                                                    const double *__restrict__ G, const double *__restrict__ sig_t,
                                                    const double *__restrict__ sig_s,
@@ -1256,7 +1257,7 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
     long long mydep = -1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const bool rev = ((flip >> d) & 1) != 0;  // sweep runs towards lower indices
+      const bool rev = (((flip >> d) & 1) != 0) != ADJ;  // sweep runs towards lower indices
       const int pb = rev ? nb[d] - 1 - bx[d] : bx[d];
       const int lp = (grp >> d) & 1;
       const int pc = 2 * pb + lp;
@@ -1319,7 +1320,7 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
     if (up_ready) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const int nbit = ((flip >> d) & 1) ? 0 : 1;
+        const int nbit = (((flip >> d) & 1) != 0) == ADJ ? 1 : 0;  // the upwind cell's outflow node
         const int bn = (b & ~(1 << d)) | (nbit << d);
         tex[d] = ext[d] ? ld_dev(u + km * S + jn[d] * NS + bn) : 0.0;
       }
@@ -1327,7 +1328,7 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
     double acc = 0.0;
 #pragma unroll
     for (int kp = 0; kp < 24; ++kp) acc += (kp / 3 == octant) ? 0.0 : G_lds[km * 24 + kp] * uv[kp];
-    const double vb = fv + ss * acc;
+    const double vb = ADJ ? fv + ss * g.vol * lane_mass<DIM>(acc, NS - 1, false) : fv + ss * acc;
     // mode matrix M = L U (unit L) of the three ordinates at mode b
     cx<double> M[3][3], Lf[3][3], dinv[3];
 #pragma unroll
@@ -1370,14 +1371,14 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
       for (int qq = q + 1; qq < 3; ++qq) s = csub(s, cmul(Lf[qq][q], w[qq]));
       w[q] = s;
     }
-    const LaneXf xf = lane_xf<DIM>(flip, false, b);
+    const LaneXf xf = lane_xf<DIM>(flip, ADJ, b);
     if (!up_ready) {
       if (m == 0) ok = wait_counters(cnt, lane != 0 ? mydep : -1, c, false, err);
       if (__syncthreads_or(!ok)) return;
       asm volatile("" ::: "memory");
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const int nbit = ((flip >> d) & 1) ? 0 : 1;
+        const int nbit = (((flip >> d) & 1) != 0) == ADJ ? 1 : 0;  // the upwind cell's outflow node
         const int bn = (b & ~(1 << d)) | (nbit << d);
         tex[d] = ext[d] ? ld_dev(u + km * S + jn[d] * NS + bn) : 0.0;
       }
@@ -1396,18 +1397,29 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         const int fl = (flip >> d) & 1;
-        const int nbit = fl ? 0 : 1;
+        const int nbit = (fl != 0) == ADJ ? 1 : 0;
         const int bn = (b & ~(1 << d)) | (nbit << d);
         // the upwind cell inside the brick finished in the previous plane
         const double tin = __shfl(res, ((grp ^ (1 << d)) << 3) | bn, 64);
         const double t = ((grp >> d) & 1) ? tin : tex[d];
-        v += (((b >> d) & 1) == fl ? 4.0 : -2.0) * om.c[d] * t;
+        if (!ADJ) {
+          v += (((b >> d) & 1) == fl ? 4.0 : -2.0) * om.c[d] * t;
+        } else {
+          // adjoint: the face mass on the other axes, on the lane's own face side
+          double hs = 1.0;
+#pragma unroll
+          for (int e = 0; e < DIM; ++e)
+            if (e != d) hs *= g.h[e];
+          const double tm = lane_mass<DIM>(t, (NS - 1) & ~(1 << d), false);
+          if (((b >> d) & 1) == (fl ? 0 : 1)) v += om.a[d] * hs * tm;
+        }
       }
       const cx<double> r = lane_forward_x<DIM>(v, xf);
       rx[p & 1][m][lane] = r;
       __syncthreads();
       const cx<double> x = cadd(cadd(cmul(wm, r), cmul(wm1, rx[p & 1][m1][lane])), cmul(wm2, rx[p & 1][m2][lane]));
-      const double o = lane_backward_x<DIM>(x, xf);
+      double o = lane_backward_x<DIM>(x, xf);
+      if (ADJ) o = lane_mass<DIM>(o, NS - 1, true) * (1.0 / g.vol);
       if (sub == p) res = o;
     }
     st_dev(u + km * S + j * NS + b, res);
@@ -2255,14 +2267,14 @@ void launch_coarse_brick(const double *f, double *u, const double *G, const doub
                          const OrdInfo *ord, const Grid &g, const int *wave_off, const int *slots, int waves,
                          bool adjoint, unsigned *cnt, long long nbricks, int *err, hipStream_t st) {
   if (g.dim != 3 || (g.n[0] | g.n[1] | g.n[2]) & 1) throw std::runtime_error("brick Gauss-Seidel needs even 3-D grids");
-  if (adjoint) throw std::runtime_error("brick Gauss-Seidel is forward only");
   launch_fill<double>(u, 24LL * g.S, 0.0, st);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nbricks)), dim3(kBlock), 0, st, cnt, nbricks);
   void *args[] = {(void *)&f,   (void *)&u,        (void *)&G,     (void *)&sig_t, (void *)&sig_s,
                   (void *)&ord, (void *)&g,        (void *)&wave_off, (void *)&slots, (void *)&waves,
                   (void *)&cnt, (void *)&err};
   // one workgroup of three waves per slot list
-  if (hipLaunchCooperativeKernel((void *)k_gs_brick, dim3(waves), dim3(192), args, 0, st) != hipSuccess)
+  void *fn = adjoint ? (void *)k_gs_brick<true> : (void *)k_gs_brick<false>;
+  if (hipLaunchCooperativeKernel(fn, dim3(waves), dim3(192), args, 0, st) != hipSuccess)
     throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
 }
 

@@ -739,12 +739,9 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
     sc.wave_off = h->upload(woff);
     sc.slots = h->upload(sl);
   }
-  if (flow_ok && h->gs_brick && !adj && g.dim == 3 && !((g.n[0] | g.n[1] | g.n[2]) & 1)) {
+  if (flow_ok && h->gs_brick && g.dim == 3 && !((g.n[0] | g.n[1] | g.n[2]) & 1)) {
     // the same schedule on the grid of 2 x 2 x 2 bricks, in each sweep's
-    // direction.  Forward only: the adjoint's inflow terms carry face mass
-    // exchanges that make the four in-brick planes as slow as the cell
-    // form's extra dependent steps (32^3, 10 sweeps: 9.4 ms either way;
-    // forward 6.8 against 8.5 ms).
+    // direction (the adjoint's sweeps run the other way).
     const int nb[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
     const long long NB = (long long)nb[0] * nb[1] * nb[2];
     std::vector<std::array<int, 3>> pbs;

@@ -187,8 +187,8 @@ def test_coarse_gs_multiblock_planes():
 
 
 def test_coarse_gs_bricks_noncubic():
-    """An even 6 x 4 x 8 grid: the forward solve runs over 2 x 2 x 2 bricks
-    (brick counts differ per axis); the adjoint over cells."""
+    """An even 6 x 4 x 8 grid: the forward and adjoint solves run over
+    2 x 2 x 2 bricks (brick counts differ per axis)."""
     prob = small(dim=3, n=(6, 4, 8), level=0, order=3, seed=17)
     print("case 6x4x8 level 0", flush=True)
     pr = Pair(prob)
