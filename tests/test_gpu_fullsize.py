@@ -140,6 +140,33 @@ def test_cfg2_solves_converge(cfg2):
     assert float(phi0.min()) > -1e-6 * float(phi0.max())
 
 
+def test_cfg2_coarse_gs_brick_form_matches_cell_form(cfg2):
+    """The ten-sweep coarse Gauss-Seidel solve at 32^3 in the launch
+    configuration the benchmark times (2 x 2 x 2 bricks on three waves
+    each) against the per-cell dataflow form, forward and adjoint.  The two
+    kernels differ in schedule, waits, in-brick exchanges and the mode
+    solve (inverse row against LU); both match the oracle at small sizes."""
+    import os
+    prob, tr, lv, samples = cfg2
+    torch = torch_mod()
+    os.environ["TR_COARSE_GS"] = "cell"
+    try:
+        tc = _transport(prob)
+    finally:
+        os.environ.pop("TR_COARSE_GS", None)
+    try:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        f = torch.randn(tc.n(0), dtype=torch.float64, device="cuda", generator=g)
+        for adj in (False, True):
+            print("coarse GS 32^3, adjoint" if adj else "coarse GS 32^3, forward", flush=True)
+            a = tr.coarse_gs(f, prob.nu_coarse, adjoint=adj)
+            c = tc.coarse_gs(f, prob.nu_coarse, adjoint=adj)
+            assert float(torch.linalg.norm(a - c) / torch.linalg.norm(c)) < 1e-12, adj
+    finally:
+        tc.close()
+
+
 def test_cfg4_gradient_fd_full_size():
     prob = inputs.config4()
     print("case", prob.name, flush=True)
