@@ -1158,33 +1158,62 @@ __global__ __launch_bounds__(256) void k_gs_flow(const double *__restrict__ f, d
     // read-only data of the update first (overlapping the waits)
     const GsPrep<DIM> q = gs_prepare<DIM, ADJ>((octant << 28) | idx, f, sig_t, sig_s, ord_lds, pl, g, b);
     const long long jself = q.j;
-    // wait for the cell's own earlier updates (lane 0 of each group), form
-    // what depends on them only, then wait for the upwind (adjoint:
-    // downwind) neighbours (lane 1 + d polls axis d)
-    if (!wait_counters(cnt, active && b == 0 ? jself : -1, c, true, err)) return;
+    // wait for the cell's own earlier updates (lane 0 of each group) while
+    // lane 1 + d samples the upwind (adjoint: downwind) neighbour along
+    // axis d in the same round trips.  If the neighbours are all done the
+    // iterate and the inflow traces are fetched together; otherwise the
+    // set-up that needs only the own values is formed first, then the
+    // neighbours are awaited.
+    long long dep = -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      if (active && q.has[d] && b == 1 + d) dep = q.jn[d];
+    bool up_ready;
+    {
+      const bool own = active && b == 0;
+      bool ready = !own, upr = dep < 0;
+      long spins = 0;
+      bool failed = false;
+      while (true) {
+        if (!ready) ready = __hip_atomic_load(cnt + jself, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == c;
+        if (!upr) upr = __hip_atomic_load(cnt + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= c + 1;
+        if (__ballot(!ready) == 0) break;
+        if (++spins > (1L << 22) ||
+            (spins % 64 == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          failed = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (__ballot(failed) != 0) return;
+      up_ready = __ballot(!upr) == 0;
+    }
     asm volatile("" ::: "memory");
     const double *up = u + jself * NS + b;
     double uv[24];
 #pragma unroll
     for (int kp = 0; kp < 24; ++kp) uv[kp] = ld_dev(up + kp * S);
+    double t[3][DIM];
+    auto load_traces = [&]() {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int fl = (q.flip >> d) & 1;
+          const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+          const int bn = (b & ~(1 << d)) | (nbit << d);
+          t[m][d] = q.has[d] ? ld_dev(u + (k0 + m) * S + q.jn[d] * NS + bn) : 0.0;
+        }
+    };
+    if (up_ready) load_traces();
     GsCell<DIM> cs;
     gs_cell_setup<DIM, ADJ>(cs, uv, q.fv, q.st, q.ss, octant, b, G_lds, ord_lds, g);
-    long long dep = -1;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-      if (active && q.has[d] && b == 1 + d) dep = q.jn[d];
-    if (!wait_counters(cnt, dep, c, false, err)) return;
-    asm volatile("" ::: "memory");
-    double t[3][DIM];
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const int fl = (q.flip >> d) & 1;
-        const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
-        const int bn = (b & ~(1 << d)) | (nbit << d);
-        t[m][d] = q.has[d] ? ld_dev(u + (k0 + m) * S + q.jn[d] * NS + bn) : 0.0;
-      }
+    if (!up_ready) {
+      if (!wait_counters(cnt, dep, c, false, err)) return;
+      asm volatile("" ::: "memory");
+      load_traces();
+    }
     double out[3];
     gs_cell_solve<DIM, ADJ>(cs, t, octant, q.flip, b, ord_lds, g, out);
     if (active)
