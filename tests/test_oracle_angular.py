@@ -171,3 +171,61 @@ def test_quad3_collocation_structure():
     ref = (3 * np.eye(3) + np.ones((3, 3))) / 6
     for ps in rule.psi:
         assert np.abs(ps - ref).max() < 1e-13
+
+
+def _octant_perm(leaves, mask):
+    """Row maps of the reflection group of the axes in ``mask``: the patch of
+    octant o at position k goes to position k of octant o ^ s (asserted by
+    reflecting its vertices)."""
+    by_oct = {o: [p for p in leaves if p.octant == o] for o in range(8)}
+    for o in range(8):
+        for d in range(3):
+            if mask & (1 << d):
+                o2 = o ^ (1 << d)
+                assert len(by_oct[o]) == len(by_oct[o2])
+                for p, p2 in zip(by_oct[o], by_oct[o2]):
+                    v = p.verts.copy()
+                    v[:, d] *= -1
+                    assert np.abs(v - p2.verts).max() < 1e-14
+    start, off = {}, 0
+    for o in range(8):
+        start[o] = off
+        off += 3 * len(by_oct[o])
+    return by_oct, start
+
+
+@pytest.mark.parametrize("mesh,mask", [("uniform2", 7), ("cone", 6), ("band", 3)])
+def test_scatter_matrix_reflection_structure(mesh, mask):
+    """On a mesh mapped onto itself by the reflections of the axes in mask,
+    the scatter matrix depends on two octants only through their sign
+    difference, and the Walsh-Hadamard transform over the reflected sign
+    patterns splits it into 2^R diagonal blocks of size A / 2^R (the form
+    the library's scatter product uses)."""
+    leaves = {"uniform2": lambda: ang.AngularMesh.uniform(2).leaves(),
+              "cone": lambda: ang.AngularMesh.cone((1, 0, 0), 15.0, 1, 2).leaves(),
+              "band": lambda: ang.AngularMesh.band_z(3).leaves()}[mesh]()
+    St = ang.scatter_matrix(leaves, ang.hg_moments(0.9, 6))
+    by_oct, start = _octant_perm(leaves, mask)
+    bits = [d for d in range(3) if mask & (1 << d)]
+    R = len(bits)
+    pats = [sum(1 << bits[b] for b in range(R) if i & (1 << b)) for i in range(2 ** R)]
+    reps = [f for f in range(8) if not f & mask]
+    urow = np.array([[start[f | s] + k for f in reps for k in range(3 * len(by_oct[f]))] for s in pats])
+    nc = urow.shape[1]
+    assert nc * 2 ** R == St.shape[0]
+    # M[(i1,t1),(i2,t2)] = M[(0,t1),(i1^i2,t2)]
+    for i1 in range(2 ** R):
+        for i2 in range(2 ** R):
+            a = St[np.ix_(urow[i1], urow[i2])]
+            b = St[np.ix_(urow[0], urow[i1 ^ i2])]
+            assert np.abs(a - b).max() < 1e-13 * np.abs(St).max()
+    # block form of the product
+    sign = np.array([[(-1) ** bin(i & j).count("1") for i in range(2 ** R)] for j in range(2 ** R)], float)
+    B = [sum(sign[j, i] * St[np.ix_(urow[0], urow[i])] for i in range(2 ** R)) / 2 ** R for j in range(2 ** R)]
+    u = np.random.default_rng(0).standard_normal((St.shape[0], 5))
+    uh = [sum(sign[j, i] * u[urow[i]] for i in range(2 ** R)) for j in range(2 ** R)]
+    ch = [B[j] @ uh[j] for j in range(2 ** R)]
+    c = np.zeros_like(u)
+    for i in range(2 ** R):
+        c[urow[i]] = sum(sign[j, i] * ch[j] for j in range(2 ** R))
+    assert np.abs(c - St @ u).max() < 1e-13 * np.abs(St @ u).max()
