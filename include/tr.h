@@ -62,6 +62,16 @@ enum { TR_F64 = 0, TR_F32 = 1, TR_F32_SPLIT = 2 };
 enum { TR_PREC_F64 = 0, TR_PREC_MIXED = 1, TR_PREC_SG = 2, TR_PREC_MIXED_BF16 = 3 };
 enum { TR_INFLOW_NONE = 0, TR_INFLOW_ISO = 1, TR_INFLOW_BEAM = 2 };
 enum { TR_RESTRICT = 0, TR_PROLONG = 1 };
+/* storage of the preconditioned vectors z_j = M^{-1} v_j in GMRES:
+ * TR_Z_AUTO: FP32 preconditioners (non-linear) always keep them, in FP32
+ *   (flexible GMRES, x += sum_j y_j z_j); the FP64 preconditioners (linear,
+ *   so both forms give the same iterates in exact arithmetic) keep them in
+ *   FP64 when they fit in half of the free device memory, else recompute
+ *   x += M^{-1}(V y) with one extra preconditioner application per restart;
+ * TR_Z_KEEP: always keep them (TR_ERR_ALLOC when they do not fit);
+ * TR_Z_RECOMPUTE: never keep them (for an FP32 preconditioner this is the
+ *   non-flexible update, kept as a comparison point). */
+enum { TR_Z_AUTO = 0, TR_Z_KEEP = 1, TR_Z_RECOMPUTE = 2 };
 
 /* Problem definition (eq. LBE, Sections 2.1, 4.1, 5.2, 5.3, 5.5).
  * All pointers are host memory, read during tr_setup only. */
@@ -85,11 +95,22 @@ typedef struct {
   int octant_order[8];          /* Gauss-Seidel octant order (a permutation)     */
 } tr_problem;
 
+/* how a level's scatter product G_l u is formed (multiply-adds per spatial
+ * dof): DENSE 2 A^2; FACTORED through the K = (order+1)^2 harmonics, 4 A K;
+ * OCTANT through the Walsh-Hadamard blocks of the octant reflection group
+ * of R axes (meshes mapped onto themselves by those reflections), 2 A^2/2^R */
+enum { TR_SCATTER_DENSE = 0, TR_SCATTER_FACTORED = 1, TR_SCATTER_OCTANT = 2 };
+
 typedef struct {
   int dim, cells, spatial_dofs, n_levels;
   int patches[16];              /* patches on each level T_l                       */
   int order_outer;
   size_t device_bytes;          /* device memory held by the handle                */
+  int scatter_form[16];         /* TR_SCATTER_* of each level's scatter (level 0:  */
+                                /* dense, used by the Gauss-Seidel solve)          */
+  int scatter_axes[16];         /* R of the OCTANT form, else 0                    */
+  int scatter_k[16];            /* K of the FACTORED form, else 0                  */
+  int outer_axes;               /* R of the problem operator's scatter, 0 = dense  */
 } tr_info_t;
 
 typedef struct {
@@ -106,6 +127,7 @@ typedef struct {
   int max_restarts;
   int prec_mode;                /* TR_PREC_F64, _MIXED, _SG or _MIXED_BF16         */
   int timing;                   /* 1: time components with HIP events              */
+  int z_store;                  /* TR_Z_AUTO, TR_Z_KEEP or TR_Z_RECOMPUTE          */
 } tr_solve_opts;
 
 typedef struct {
@@ -118,6 +140,7 @@ typedef struct {
   int n_precond;                /* preconditioner applications                    */
   double sweep_dof_updates;     /* sum over transport sweeps of (ordinates x spatial dofs) */
   int coarse_steps;             /* dependent steps of one coarse Gauss-Seidel solve */
+  int flexible;                 /* preconditioned vectors kept: 64 / 32 (bits), 0 recomputed */
 } tr_solve_stats;
 
 /* Build the angular mesh, quadrature, level operators, prolongations and
@@ -126,6 +149,15 @@ typedef struct {
  * Errors: TR_ERR_ARG (bad sizes, sigma_t <= 0 or not finite, n_levels not
  * equal to the mesh's level count, orders out of range), TR_ERR_ALLOC. */
 int tr_setup(const tr_problem *prob, tr_handle **out);
+/* Device memory (bytes) a handle for prob holds after tr_setup, plus, when
+ * opts is not NULL, what a solve with those options adds (FP32 level
+ * buffers, the GMRES(opts->restart) workspace with the preconditioned
+ * vectors counted as kept, split-BF16 level matrices, the coarse solve's
+ * schedule and counters); the adjoint solve adds one more vector when its
+ * lambda argument is NULL.  Runs the host part of the setup only: no device
+ * is needed and nothing is allocated.  Errors: as tr_setup; TR_ERR_ARG for
+ * bad options. */
+int tr_workspace_bytes(const tr_problem *prob, const tr_solve_opts *opts, size_t *bytes);
 /* Release a handle and its device memory (NULL is ignored). */
 void tr_destroy(tr_handle *h);
 /* Thread-local text of the last error on this thread. */
@@ -134,7 +166,8 @@ const char *tr_last_error(void);
 int tr_info(const tr_handle *h, tr_info_t *out);
 
 /* Replace the per-cell cross sections (device pointers, [cells] FP64).
- * Nothing else of the setup depends on them. */
+ * Nothing else of the setup depends on them.  They are checked as in
+ * tr_setup (TR_ERR_ARG, the handle's values unchanged); synchronises st. */
 int tr_set_sigma(tr_handle *h, const double *sigma_t, const double *sigma_s, tr_stream st);
 
 /* Weak-form right-hand side b (device, FP64, canonical, finest level): the
@@ -147,6 +180,11 @@ int tr_rhs(tr_handle *h, const double *q_cell, const tr_inflow *inflow, double *
 /* Detector weights w (device, FP64, canonical): R = w . phi is the scalar
  * flux integrated over the cell box lo..hi. */
 int tr_detector(tr_handle *h, const int lo[3], const int hi[3], double *w, tr_stream st);
+
+/* Detector response R = w . phi (host *R), the integrated quantity whose
+ * gradient tr_adjoint_grad returns; w, phi device FP64 canonical finest
+ * level.  Synchronises st. */
+int tr_response(tr_handle *h, const double *w, const double *phi, double *R, tr_stream st);
 
 /* Transport sweep phi = L_l^{-1} g on angular level l (Section 3; exact on
  * the Cartesian mesh since every patch is inflow or outflow per face).

@@ -15,6 +15,8 @@ TR_F64, TR_F32, TR_F32_SPLIT = 0, 1, 2
 TR_PREC_F64, TR_PREC_MIXED, TR_PREC_SG, TR_PREC_MIXED_BF16 = 0, 1, 2, 3
 TR_INFLOW_NONE, TR_INFLOW_ISO, TR_INFLOW_BEAM = 0, 1, 2
 TR_RESTRICT, TR_PROLONG = 0, 1
+TR_Z_AUTO, TR_Z_KEEP, TR_Z_RECOMPUTE = 0, 1, 2
+TR_SCATTER_DENSE, TR_SCATTER_FACTORED, TR_SCATTER_OCTANT = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -33,7 +35,8 @@ class TrProblem(ctypes.Structure):
 class TrInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("cells", ctypes.c_int), ("spatial_dofs", ctypes.c_int),
                 ("n_levels", ctypes.c_int), ("patches", ctypes.c_int * 16), ("order_outer", ctypes.c_int),
-                ("device_bytes", ctypes.c_size_t)]
+                ("device_bytes", ctypes.c_size_t), ("scatter_form", ctypes.c_int * 16),
+                ("scatter_axes", ctypes.c_int * 16), ("scatter_k", ctypes.c_int * 16), ("outer_axes", ctypes.c_int)]
 
 
 class TrInflow(ctypes.Structure):
@@ -44,7 +47,7 @@ class TrInflow(ctypes.Structure):
 
 class TrSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
-                ("prec_mode", ctypes.c_int), ("timing", ctypes.c_int)]
+                ("prec_mode", ctypes.c_int), ("timing", ctypes.c_int), ("z_store", ctypes.c_int)]
 
 
 class TrSolveStats(ctypes.Structure):
@@ -55,7 +58,8 @@ class TrSolveStats(ctypes.Structure):
                 ("ms_other", ctypes.c_double), ("n_sweep", ctypes.c_int), ("n_scatter", ctypes.c_int),
                 ("n_coarse", ctypes.c_int), ("ms_sweep_finest", ctypes.c_double),
                 ("n_sweep_finest", ctypes.c_int), ("n_precond", ctypes.c_int),
-                ("sweep_dof_updates", ctypes.c_double), ("coarse_steps", ctypes.c_int)]
+                ("sweep_dof_updates", ctypes.c_double), ("coarse_steps", ctypes.c_int),
+                ("flexible", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -68,7 +72,10 @@ SIGNATURES = {
     "tr_destroy": (None, [_h]),
     "tr_last_error": (ctypes.c_char_p, []),
     "tr_info": (ctypes.c_int, [_h, ctypes.POINTER(TrInfo)]),
+    "tr_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(TrProblem), ctypes.POINTER(TrSolveOpts),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
     "tr_set_sigma": (ctypes.c_int, [_h, _vp, _vp, _vp]),
+    "tr_response": (ctypes.c_int, [_h, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "tr_rhs": (ctypes.c_int, [_h, _vp, ctypes.POINTER(TrInflow), _vp, _vp]),
     "tr_detector": (ctypes.c_int, [_h, _ip, _ip, _vp, _vp]),
     "tr_sweep": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),

@@ -9,8 +9,10 @@ sections (A is affine in sigma_t and sigma_s):
     dR/dsigma_t[j] = -sum_q lambda_jq^T (N (x) M_q) phi_jq
     dR/dsigma_s[j] = +lambda_j^T (N (x) S~) phi_j
 
-both computed by the library (tr_adjoint_grad).  The right-hand side b
-(volume source and inflow data) does not depend on the cross sections.
+both computed by the library (tr_adjoint_grad), and R = w . phi itself
+(tr_response).  R is linear in b and in w: dR/db = lambda (the adjoint
+solution, A^T lambda = w) and dR/dw = phi, returned when those inputs
+require gradients.
 """
 import torch
 
@@ -34,7 +36,7 @@ class DetectorResponse(torch.autograd.Function):
         ctx.tr, ctx.mode, ctx.tol = tr, mode, tol
         ctx.save_for_backward(sigma_t, sigma_s, w, x)
         ctx.stats = st
-        return torch.dot(w, x)
+        return torch.tensor(tr.response(w, x), dtype=torch.float64, device=x.device)
 
     @staticmethod
     def backward(ctx, grad_out):
@@ -42,8 +44,10 @@ class DetectorResponse(torch.autograd.Function):
         tr = ctx.tr
         # another forward call may have replaced the handle's cross sections
         tr.set_sigma(sigma_t.detach(), sigma_s.detach())
-        gt, gs, _, _ = tr.adjoint_grad(w, x, tol=ctx.tol, mode=ctx.mode)
-        return None, grad_out * gt, grad_out * gs, None, None, None, None
+        gt, gs, lam, _ = tr.adjoint_grad(w, x, tol=ctx.tol, mode=ctx.mode)
+        gb = grad_out * lam if ctx.needs_input_grad[3] else None
+        gw = grad_out * x if ctx.needs_input_grad[4] else None
+        return None, grad_out * gt, grad_out * gs, gb, gw, None, None
 
 
 def detector_response(tr: Transport, sigma_t, sigma_s, b, w, mode="f64", tol=1e-10):

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <stdexcept>
 
 #include "internal.h"
 
@@ -405,6 +406,218 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
+// Octant-group scatter product.  On an angular mesh that is mapped onto
+// itself by the reflections through the coordinate planes of a set of axes
+// (all three on uniformly refined meshes, two on meshes refined around an
+// axis), with reflected patches in the same position of their octants'
+// patch lists, the scatter matrix M depends on a pair of octants only
+// through their sign difference: M[(f|s1, k1), (g|s2, k2)] depends on
+// s1 ^ s2 (s: the reflected sign bits, f, g: the other bits, k: position in
+// the octant).  Such a matrix is block-diagonalised by the Walsh-Hadamard
+// transform over the 2^R sign patterns s:
+//   U^[chi][t] = sum_s (-1)^{|chi & s|} U[(f|s, k)],  t = (f, k)
+//   C^[chi]    = B^[chi] U^[chi]       (2^R GEMMs of size nc = A / 2^R)
+//   C[(f|s,k)] = sum_chi (-1)^{|chi & s|} C^[chi][t]
+// with B^[chi][t1][t2] = 2^-R sum_s (-1)^{|chi & s|} M[(f1|0,k1),(f2|s,k2)].
+// That is 2 A^2 / 2^R multiply-adds per column instead of 2 A^2.  One
+// kernel does all of it: a workgroup owns a BM x BN tile of transformed rows
+// for every chi at once; per k-slice the loader threads fetch the 2^R
+// canonical rows of each transformed index (urow[i][t], i the sign pattern
+// in the order of its bits) and transform them in registers into the 2^R
+// B tiles, the other threads stage the 2^R A tiles; after the k loop each
+// lane holds, for its accumulator positions, the values of every chi, and
+// the inverse transform is taken in registers before the store (with the
+// epilogue of k_gemm).  U and C each cross HBM once.
+template <typename T, int R, int BM, int BN, int BK, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_oct(
+    const T *__restrict__ Bh, int ldb, const T *__restrict__ U, T *__restrict__ C, const int *__restrict__ urow,
+    int nc, int N, int mblocks, int nblocks, const T *__restrict__ bias, const double *__restrict__ colscale,
+    int cell, const int *__restrict__ pos, const OrdInfo *__restrict__ rord, long long ncells) {
+  constexpr int NCHI = 1 << R;
+  using acc_t = typename Mma<T>::acc_t;
+  using V = Vec16<T>;
+  constexpr int VN = V::n;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int PAD = 2;
+  constexpr int BPAIRS = BK * BN / VN;             // loader threads of U: one (k, column vector) each
+  constexpr int ATHREADS = 256 - BPAIRS;           // the others stage the A tiles
+  constexpr int AVT = NCHI * BM * BK / VN;         // A vectors per slice
+  constexpr int AV = (AVT + ATHREADS - 1) / ATHREADS;
+  static_assert(BK % 4 == 0 && BK % VN == 0 && BPAIRS <= 128, "tile shape");
+  __shared__ T As[2][NCHI][BK][BM + PAD];
+  __shared__ T Bs[2][NCHI][BK][BN + PAD];
+  __shared__ int pos_s[8][BN / 4 + 1];
+
+  const int b = blockIdx.x;
+  const int xcd = b % kXcds, slot = b / kXcds;
+  const int mb = slot % mblocks;
+  const int nb = xcd + kXcds * (slot / mblocks);
+  if (nb >= nblocks) return;
+  const int m0 = mb * BM;
+  const long long n0 = (long long)nb * BN;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
+  const int lrow = lane & 15, lk = lane >> 4;
+
+  acc_t acc[NCHI][TM][TN];
+#pragma unroll
+  for (int j = 0; j < NCHI; ++j)
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int jn = 0; jn < TN; ++jn) acc[j][i][jn] = acc_t{0, 0, 0, 0};
+
+  V rx[NCHI];   // U rows of one (k, column vector), loader threads
+  V ra[AV];     // A vectors, staging threads
+  const bool loader = tid < BPAIRS;
+  const int bk = tid / (BN / VN), bnv = (tid % (BN / VN)) * VN;
+  auto load = [&](int k0) {
+    if (loader) {
+      const int gk = k0 + bk;
+      const long long gn = n0 + bnv;
+#pragma unroll
+      for (int i = 0; i < NCHI; ++i) {
+        if (gk < nc) {
+          const long long row = urow[i * nc + gk];
+          if (gn + VN <= N) {
+            rx[i] = *reinterpret_cast<const V *>(U + row * N + gn);
+          } else {
+#pragma unroll
+            for (int e = 0; e < VN; ++e) rx[i].v[e] = gn + e < N ? U[row * N + gn + e] : T(0);
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < VN; ++e) rx[i].v[e] = T(0);
+        }
+      }
+    } else {
+      const int idx = tid - BPAIRS;
+#pragma unroll
+      for (int q = 0; q < AV; ++q) {
+        const int v = idx + ATHREADS * q;
+        if (AVT % ATHREADS != 0 && v >= AVT) break;
+        const int j = v / (BM * BK / VN), rem = v % (BM * BK / VN);
+        const int i = rem / (BK / VN), kv = (rem % (BK / VN)) * VN;
+        const int gm = m0 + i, gk = k0 + kv;
+        if (gm < nc && gk < ldb) {
+          ra[q] = *reinterpret_cast<const V *>(Bh + ((long long)j * nc + gm) * ldb + gk);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VN; ++e) ra[q].v[e] = T(0);
+        }
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    if (loader) {
+      // forward transform over the sign patterns, in registers
+#pragma unroll
+      for (int hh = 1; hh < NCHI; hh <<= 1)
+#pragma unroll
+        for (int i = 0; i < NCHI; ++i)
+          if (!(i & hh)) {
+#pragma unroll
+            for (int e = 0; e < VN; ++e) {
+              const T a = rx[i].v[e], c = rx[i + hh].v[e];
+              rx[i].v[e] = a + c;
+              rx[i + hh].v[e] = a - c;
+            }
+          }
+#pragma unroll
+      for (int j = 0; j < NCHI; ++j)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) Bs[buf][j][bk][bnv + e] = rx[j].v[e];
+    } else {
+      const int idx = tid - BPAIRS;
+#pragma unroll
+      for (int q = 0; q < AV; ++q) {
+        const int v = idx + ATHREADS * q;
+        if (AVT % ATHREADS != 0 && v >= AVT) break;
+        const int j = v / (BM * BK / VN), rem = v % (BM * BK / VN);
+        const int i = rem / (BK / VN), kv = (rem % (BK / VN)) * VN;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) As[buf][j][kv + e][i] = ra[q].v[e];
+      }
+    }
+  };
+  auto mma_slice = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+#pragma unroll
+      for (int j = 0; j < NCHI; ++j) {
+        T a[TM], bb[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[buf][j][ks + lk][wm0 + i * 16 + lrow];
+#pragma unroll
+        for (int jn = 0; jn < TN; ++jn) bb[jn] = Bs[buf][j][ks + lk][wn0 + jn * 16 + lrow];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int jn = 0; jn < TN; ++jn) acc[j][i][jn] = Mma<T>::op(a[i], bb[jn], acc[j][i][jn]);
+      }
+    }
+  };
+  if (pos) {
+    // positions of the tile's cells in every orientation's list (plane
+    // layout output); read after the loop's barriers
+    const int ncell = BN / cell;
+    for (int t = tid; t < 8 * ncell; t += 256) {
+      const int fl = t / ncell, c = t % ncell;
+      pos_s[fl][c] = pos[(long long)fl * ncells + min(n0 / cell + c, ncells - 1)];
+    }
+  }
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < nc; k0 += BK) {
+    const bool more = k0 + BK < nc;
+    if (more) load(k0 + BK);
+    mma_slice(buf);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // inverse transform and store
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int jn = 0; jn < TN; ++jn) {
+      const long long gn = n0 + wn0 + jn * 16 + lrow;
+      const T cs = (colscale && gn < N) ? T(colscale[gn / cell]) : T(1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
+        if (t >= nc || gn >= N) continue;
+        T y[NCHI];
+#pragma unroll
+        for (int j = 0; j < NCHI; ++j) y[j] = acc[j][i][jn][r];
+#pragma unroll
+        for (int hh = 1; hh < NCHI; hh <<= 1)
+#pragma unroll
+          for (int q = 0; q < NCHI; ++q)
+            if (!(q & hh)) {
+              const T a = y[q], c = y[q + hh];
+              y[q] = a + c;
+              y[q + hh] = a - c;
+            }
+#pragma unroll
+        for (int q = 0; q < NCHI; ++q) {
+          const long long row = urow[q * nc + t];
+          long long col = gn;
+          if (pos) col = (long long)pos_s[rord[row].flip][(int)((gn - n0) / cell)] * cell + (gn % cell);
+          const long long o = row * N + col;
+          T v = y[q];
+          if (colscale) v *= cs;
+          if (bias) v += bias[o];
+          C[o] = v;
+        }
+      }
+    }
+}
+
 }  // namespace
 
 // Launch shapes (tile M x N x depth, LDS double buffering, minimum waves per
@@ -430,6 +643,38 @@ void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t 
   else
     launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
 }
+// Octant-group product (see k_gemm_oct): FP64 tiles 32 x 64 x 4, FP32
+// 64 x 64 x 4, 256 threads, LDS double buffering.
+template <typename T, int R, int BM, int BN, int BK, int WPE>
+static void launch_oct_shape(const T *Bh, int ldb, const T *U, T *C, const int *urow, int nc, int N, hipStream_t st,
+                             const T *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
+  const int mblocks = (nc + BM - 1) / BM;
+  const int nblocks = (int)(((long long)N + BN - 1) / BN);
+  const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
+  const long long grid = (long long)mblocks * nb_pad;
+  hipLaunchKernelGGL((k_gemm_oct<T, R, BM, BN, BK, WPE>), dim3((unsigned)grid), dim3(256), 0, st, Bh, ldb, U, C, urow,
+                     nc, N, mblocks, nblocks, bias, colscale, cell, pos, rord, (long long)(N / cell));
+}
+
+template <typename T>
+void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const int *urow, int R, int nc, int N, hipStream_t st,
+                     const T *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
+  if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int BM = F64 ? 32 : 64, BN = 64, BK = 4;
+  switch (R) {
+    case 1: launch_oct_shape<T, 1, BM, BN, BK, 2>(Bh, ldb, U, C, urow, nc, N, st, bias, colscale, cell, pos, rord); break;
+    case 2: launch_oct_shape<T, 2, BM, BN, BK, 2>(Bh, ldb, U, C, urow, nc, N, st, bias, colscale, cell, pos, rord); break;
+    case 3: launch_oct_shape<T, 3, BM, BN, BK, 2>(Bh, ldb, U, C, urow, nc, N, st, bias, colscale, cell, pos, rord); break;
+    default: throw std::runtime_error("octant-group GEMM: 1 to 3 reflected axes");
+  }
+}
+template void launch_gemm_oct<double>(const double *, int, const double *, double *, const int *, int, int, int,
+                                      hipStream_t, const double *, const double *, int, const int *,
+                                      const OrdInfo *);
+template void launch_gemm_oct<float>(const float *, int, const float *, float *, const int *, int, int, int,
+                                     hipStream_t, const float *, const double *, int, const int *, const OrdInfo *);
+
 int split_rows_kp(int K) { return (K + 31) / 32 * 32; }
 
 void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st) {

@@ -92,16 +92,16 @@ void launch_coarse_gs(const double *f, double *u, const double *G, const double 
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
                       int *bar_err, int max_blocks, unsigned gen0, bool coh, hipStream_t st);
 
-// out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * in[3p+m][s]
+// out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * scale * in[3p+m][s]
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
-                    hipStream_t st);
+                    hipStream_t st, double scale = 1.0);
 // The same conversion followed by the inverse cell mass matrix per ordinate:
 // a forward right-hand side in prepared form f~ = N^{-1} f (the form every
 // forward sweep, forward coarse solve and forward restriction works in).
 template <typename Tin, typename Tout>
 void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
-                         hipStream_t st, const int *pos = nullptr, const OrdInfo *ord = nullptr);
+                         hipStream_t st, const int *pos = nullptr, const OrdInfo *ord = nullptr, double scale = 1.0);
 
 // Restriction to level l-1: fc[p] = sum_children R_c (sigma_s N (s_new - s_prev))_c
 // (apply_sn = 0: plain fc[p] = sum_children R_c in_c).
@@ -140,6 +140,8 @@ void launch_axpy(long long n, double a, const double *x, double *y, hipStream_t 
 void launch_scal(long long n, double a, double *x, hipStream_t st);
 // y += sum_q c[q] x[q] (host arrays of k device vectors and coefficients)
 void launch_multi_axpy(long long n, int k, const double *const *x, const double *c, double *y, hipStream_t st);
+// the same with FP32 vectors x (FP64 accumulation)
+void launch_multi_axpy_f32(long long n, int k, const float *const *x, const double *c, double *y, hipStream_t st);
 // inner products x_q . y (q < k) and x_q . z (q < kz), k <= 16, into
 // out[0..k) and out[k..k+kz); partial holds (k + kz) x nblocks doubles
 void launch_multi_dot(long long n, int k, const double *const *x, const double *y, int kz, const double *z,
@@ -160,6 +162,15 @@ template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
                  const double *colscale = nullptr, int cell = 8,
                  const int *pos = nullptr, const OrdInfo *rord = nullptr);
+// C = M U for a scatter matrix M with the octant reflection structure, via
+// its 2^R Walsh-Hadamard blocks Bh ([2^R][nc][ldb], the factor 2^-R folded
+// in; nc = rows / 2^R, ldb >= nc a multiple of 4, zero-padded) and the row
+// map urow[i][t] (canonical row of transformed index t under sign pattern
+// i); same epilogue as launch_gemm.  U, C: [2^R nc][N].
+template <typename T>
+void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const int *urow, int R, int nc, int N, hipStream_t st,
+                     const T *bias = nullptr, const double *colscale = nullptr, int cell = 8,
+                     const int *pos = nullptr, const OrdInfo *rord = nullptr);
 // FP32 C = A B with split-BF16 operands (three BF16 MFMA products, FP32
 // accumulate); same epilogue as launch_gemm.  Asplit: A split once by
 // launch_split_rows into [hi | lo][M][split_rows_kp(K)] BF16 (device,

@@ -1463,7 +1463,7 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
 // ------------------------------------------------------------- conversions
 template <typename Tin, typename Tout>
 __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, int P, long long S,
-                          const double *__restrict__ pre, const double *__restrict__ post) {
+                          const double *__restrict__ pre, const double *__restrict__ post, double scale) {
   const long long total = (long long)P * S;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
@@ -1472,7 +1472,7 @@ __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, in
     double x[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      x[m] = (double)in[(3LL * p + m) * S + s];
+      x[m] = (double)in[(3LL * p + m) * S + s] * scale;
       if (pre) x[m] *= pre[3 * p + m];
     }
     const double sum = x[0] + x[1] + x[2];
@@ -1491,7 +1491,7 @@ __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, in
 template <typename Tin, typename Tout, int DIM>
 __global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ out, int P, Grid g,
                                const double *__restrict__ pre, const double *__restrict__ post,
-                               const int *__restrict__ pos, const OrdInfo *__restrict__ ord) {
+                               const int *__restrict__ pos, const OrdInfo *__restrict__ ord, double scale) {
   constexpr int NS = 1 << DIM;
   const long long C = g.C, S = g.S;
   const long long total = (long long)P * C;
@@ -1503,7 +1503,7 @@ __global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ ou
     double x[3][NS];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const double sc = pre ? pre[3 * p + m] : 1.0;
+      const double sc = (pre ? pre[3 * p + m] : 1.0) * scale;
 #pragma unroll
       for (int b = 0; b < NS; ++b) x[m][b] = (double)in[(3LL * p + m) * S + j * NS + b] * sc;
     }
@@ -2020,6 +2020,30 @@ __global__ void k_multi_axpy(long long n, MultiAxpyArgs a, double *__restrict__ 
     for (int q = 0; q < a.k; ++q) y[n - 1] += a.c[q] * a.x[q][n - 1];
 }
 
+// y += sum_i c_i x_i with FP32 vectors x_i (the flexible GMRES update from
+// the FP32 preconditioned vectors), accumulated in FP64
+struct MultiAxpyArgsF {
+  const float *x[kMaxMulti];
+  double c[kMaxMulti];
+  int k;
+};
+
+__global__ void k_multi_axpy_f32(long long n, MultiAxpyArgsF a, double *__restrict__ y) {
+  const long long n2 = n / 2;
+  double2 *y2 = reinterpret_cast<double2 *>(y);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    double2 v = y2[i];
+    for (int q = 0; q < a.k; ++q) {
+      const float2 u = reinterpret_cast<const float2 *>(a.x[q])[i];
+      v.x += a.c[q] * (double)u.x;
+      v.y += a.c[q] * (double)u.y;
+    }
+    y2[i] = v;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+    for (int q = 0; q < a.k; ++q) y[n - 1] += a.c[q] * (double)a.x[q][n - 1];
+}
+
 // Several inner products in one pass (the projections of one Arnoldi step
 // computed together, see the GMRES driver):
 //   partial[q][block]     = x_q . y   (q < k)
@@ -2339,35 +2363,35 @@ void launch_coarse_gs(const double *f, double *u, const double *G, const double 
 
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
-                    hipStream_t st) {
+                    hipStream_t st, double scale) {
   hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for((long long)P * S)), dim3(kBlock), 0, st, in, out, P, S,
-                     pre, post);
+                     pre, post, scale);
 }
 template <typename Tin, typename Tout>
 void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
-                         hipStream_t st, const int *pos, const OrdInfo *ord) {
+                         hipStream_t st, const int *pos, const OrdInfo *ord, double scale) {
   const int grid = grid_for((long long)P * g.C);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post, pos,
-                       ord);
+                       ord, scale);
   else
     hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post, pos,
-                       ord);
+                       ord, scale);
 }
 template void launch_convert_minv<double, double>(const double *, double *, int, const Grid &, const double *,
-                                                  const double *, hipStream_t, const int *, const OrdInfo *);
+                                                  const double *, hipStream_t, const int *, const OrdInfo *, double);
 template void launch_convert_minv<double, float>(const double *, float *, int, const Grid &, const double *,
-                                                 const double *, hipStream_t, const int *, const OrdInfo *);
+                                                 const double *, hipStream_t, const int *, const OrdInfo *, double);
 template void launch_convert_minv<float, float>(const float *, float *, int, const Grid &, const double *,
-                                                const double *, hipStream_t, const int *, const OrdInfo *);
+                                                const double *, hipStream_t, const int *, const OrdInfo *, double);
 template void launch_convert<double, double>(const double *, double *, int, long long, const double *,
-                                             const double *, hipStream_t);
+                                             const double *, hipStream_t, double);
 template void launch_convert<double, float>(const double *, float *, int, long long, const double *, const double *,
-                                            hipStream_t);
+                                            hipStream_t, double);
 template void launch_convert<float, double>(const float *, double *, int, long long, const double *, const double *,
-                                            hipStream_t);
+                                            hipStream_t, double);
 template void launch_convert<float, float>(const float *, float *, int, long long, const double *, const double *,
-                                           hipStream_t);
+                                           hipStream_t, double);
 
 template <typename Tin, typename Tout>
 void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,
@@ -2496,6 +2520,17 @@ void launch_multi_axpy(long long n, int k, const double *const *x, const double 
       a.c[q] = c[q0 + q];
     }
     hipLaunchKernelGGL(k_multi_axpy, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, y);
+  }
+}
+void launch_multi_axpy_f32(long long n, int k, const float *const *x, const double *c, double *y, hipStream_t st) {
+  for (int q0 = 0; q0 < k; q0 += kMaxMulti) {
+    MultiAxpyArgsF a{};
+    a.k = std::min(kMaxMulti, k - q0);
+    for (int q = 0; q < a.k; ++q) {
+      a.x[q] = x[q0 + q];
+      a.c[q] = c[q0 + q];
+    }
+    hipLaunchKernelGGL(k_multi_axpy_f32, dim3(blas_grid(n)), dim3(kBlock), 0, st, n, a, y);
   }
 }
 // Workgroups of a multi-vector pass: one resident round (a second, partly

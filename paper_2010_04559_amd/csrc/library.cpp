@@ -81,10 +81,19 @@ struct DevLevel {
   int Kf = 0;
   double *L64 = nullptr, *R64 = nullptr, *Lt64 = nullptr, *Rt64 = nullptr;
   float *L32 = nullptr, *R32 = nullptr, *Lt32 = nullptr, *Rt32 = nullptr;
+  // Octant-group form of the level scatter (levels >= 1 whose mesh is mapped
+  // onto itself by the reflections of symR axes): Walsh-Hadamard blocks of
+  // G, G^T and the canonical S~ ([2^symR][sym_nc][sym_ldb]) and the row map
+  int symR = 0, sym_nc = 0, sym_ldb = 0;
+  int *urow = nullptr;
+  double *Bh64 = nullptr, *Bht64 = nullptr, *Bc64 = nullptr;
+  float *Bh32 = nullptr, *Bht32 = nullptr, *Bc32 = nullptr;
   int *owner = nullptr;                    // level >= 1: owner patch on level l-1
   double *Pu = nullptr, *Ru = nullptr, *Pa = nullptr, *Ra = nullptr, *Pc = nullptr, *Rc = nullptr;
   int *first_child = nullptr, *n_child = nullptr;  // over level l-1 patches
-  // workspaces (ordinate form)
+  // workspaces (ordinate form); blk holds all of them, and on levels >= 1
+  // the FP32 buffers are views of the same block
+  double *blk = nullptr;
   double *f64 = nullptr, *u64 = nullptr, *sa64 = nullptr, *sb64 = nullptr;
   float *f32 = nullptr, *u32 = nullptr, *sa32 = nullptr, *sb32 = nullptr;
 };
@@ -154,12 +163,16 @@ struct tr_handle {
   Grid g{};
   Planes pl{};
   std::vector<int> plane_off_host;
+  std::vector<int> cells_host;    // the (+,+,+) sweep list (packed cells), plane by plane
   int *d_cells = nullptr, *d_off = nullptr;
   double *sig_t = nullptr, *sig_s = nullptr;
   double *sig_pl = nullptr;  // [2][8][cells] cross sections per orientation, cell-list order
   tr::HostAngular ang;
   std::vector<DevLevel> lv;
   double *Souter = nullptr;  // canonical S~ at the problem's order on the finest level
+  double *Bouter = nullptr;  // its octant-group blocks (mesh with reflection structure), else null
+  int *outer_urow = nullptr;
+  int outer_R = 0, outer_nc = 0, outer_ldb = 0;
   double *iom = nullptr;     // [A][3] int Omega^xi psi on the finest level
   double *dot_partial = nullptr, *dot_out = nullptr;
   double *mdot_partial = nullptr, *mdot_out = nullptr;  // [32][dot_blocks], [2 m + 4]
@@ -170,6 +183,8 @@ struct tr_handle {
   // Krylov workspace
   int kry_m = 0;
   std::vector<double *> V, Z;
+  std::vector<float *> Z32;       // FP32 preconditioned vectors (flexible form, FP32 preconditioners)
+  bool dry = false;               // size-only setup (tr_workspace_bytes): nothing allocated or launched
   double *kw = nullptr, *kx = nullptr;
   bool mixed_ready = false;
   struct GsSchedule {
@@ -212,26 +227,32 @@ struct tr_handle {
   size_t bytes = 0;
   EventTimer *timer = nullptr;
 
+  uintptr_t dry_next = 1 << 20;   // distinct stand-in addresses of a size-only setup (never dereferenced)
   template <typename T>
   T *alloc(size_t n) {
     void *p = nullptr;
     if (n == 0) n = 1;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) throw std::bad_alloc();
-    allocs.push_back(p);
+    if (dry) {
+      p = reinterpret_cast<void *>(dry_next);
+      dry_next += (n * sizeof(T) + 255) / 256 * 256;
+    } else {
+      hipError_t e = hipMalloc(&p, n * sizeof(T));
+      if (e != hipSuccess) throw std::bad_alloc();
+      allocs.push_back(p);
+    }
     bytes += n * sizeof(T);
     return static_cast<T *>(p);
   }
   template <typename T>
   T *upload(const std::vector<T> &v) {
     T *p = alloc<T>(v.size());
-    HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!dry) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return p;
   }
   int top() const { return (int)lv.size() - 1; }
   long long vec_len(int l) const { return (long long)lv[l].A * g.S; }
   ~tr_handle() {
-    for (void *p : allocs) hipFree(p);
+    for (void *p : allocs) hipFree(p);  // empty for a size-only setup
   }
 };
 
@@ -245,6 +266,105 @@ void tend(tr_handle *h) {
 }
 
 // ------------------------------------------------------------------ setup
+// Reflection structure of level l's mesh: the axes d whose reflection
+// (sign flip of component d) maps every patch of octant o, at position k of
+// that octant's list, onto the patch at position k of octant o ^ (1 << d),
+// vertex by vertex.  Returns R = the number of such axes and fills urow
+// ([2^R][nc]): transformed row t = (coset representative f, dof k within
+// its octant) under sign pattern i (bit b of i = the b-th reflected axis)
+// sits at canonical row urow[i * nc + t].
+int octant_symmetry(const tr::HostAngular &ang, int l, std::vector<int> &urow, int &nc) {
+  const tr::HostLevel &H = ang.lv[l];
+  int first[8], cnt[8];
+  for (int o = 0; o < 8; ++o) first[o] = -1, cnt[o] = 0;
+  for (int q = 0; q < H.P; ++q) {
+    const int o = H.octant[q];
+    if (first[o] < 0) first[o] = q;
+    else if (H.octant[q - 1] != o) return 0;  // not octant-major
+    cnt[o]++;
+  }
+  int mask = 0;
+  for (int d = 0; d < 3; ++d) {
+    bool ok = true;
+    for (int o = 0; o < 8 && ok; ++o) {
+      const int o2 = o ^ (1 << d);
+      if (cnt[o] != cnt[o2]) ok = false;
+      for (int k = 0; k < cnt[o] && ok; ++k) {
+        const tr::PatchNode &a = ang.tree[H.node[first[o] + k]], &b = ang.tree[H.node[first[o2] + k]];
+        for (int v = 0; v < 3 && ok; ++v) {
+          const double ax[3] = {a.v[v].x, a.v[v].y, a.v[v].z}, bx[3] = {b.v[v].x, b.v[v].y, b.v[v].z};
+          for (int c = 0; c < 3; ++c)
+            if (std::fabs((c == d ? -ax[c] : ax[c]) - bx[c]) > 1e-13) ok = false;
+        }
+      }
+    }
+    if (ok) mask |= 1 << d;
+  }
+  const int R = __builtin_popcount(mask);
+  if (R == 0) return 0;
+  int bits[3], nb = 0;
+  for (int d = 0; d < 3; ++d)
+    if (mask & (1 << d)) bits[nb++] = d;
+  const int nchi = 1 << R;
+  nc = H.A / nchi;
+  urow.assign((size_t)nchi * nc, 0);
+  int t = 0;
+  for (int f = 0; f < 8; ++f) {
+    if (f & mask) continue;  // coset representatives: reflected bits clear
+    for (int k = 0; k < 3 * cnt[f]; ++k, ++t)
+      for (int i = 0; i < nchi; ++i) {
+        int o = f;
+        for (int b = 0; b < R; ++b)
+          if (i & (1 << b)) o |= 1 << bits[b];
+        urow[(size_t)i * nc + t] = 3 * first[o] + k;
+      }
+  }
+  if (t != nc) return 0;
+  return R;
+}
+
+// Whether the A x A matrix M has the octant-group structure of urow:
+// M[(i1, t1), (i2, t2)] = M[(0, t1), (i1 ^ i2, t2)] (checked on a sample of
+// rows, to a relative 1e-12).
+bool octant_structured(const std::vector<double> &M, int A, const std::vector<int> &urow, int R, int nc) {
+  const int nchi = 1 << R;
+  double mx = 0;
+  for (double v : M) mx = std::max(mx, std::fabs(v));
+  const int step = std::max(1, nc / 64);
+  for (int t1 = 0; t1 < nc; t1 += step)
+    for (int i1 = 0; i1 < nchi; ++i1)
+      for (int i2 = 0; i2 < nchi; ++i2)
+        for (int t2 = 0; t2 < nc; ++t2) {
+          const double a = M[(size_t)urow[(size_t)i1 * nc + t1] * A + urow[(size_t)i2 * nc + t2]];
+          const double b = M[(size_t)urow[t1] * A + urow[(size_t)(i1 ^ i2) * nc + t2]];
+          if (std::fabs(a - b) > 1e-12 * mx) return false;
+        }
+  return true;
+}
+
+// Walsh-Hadamard blocks Bh[j][t1][t2] = 2^-R sum_i (-1)^{|i & j|} M[(0,t1),(i,t2)]
+// with rows padded to ldb (zeros).
+std::vector<double> octant_blocks(const std::vector<double> &M, int A, const std::vector<int> &urow, int R, int nc,
+                                  int ldb) {
+  const int nchi = 1 << R;
+  std::vector<double> B((size_t)nchi * nc * ldb, 0.0);
+  const double sc = 1.0 / nchi;
+  for (int j = 0; j < nchi; ++j)
+    for (int t1 = 0; t1 < nc; ++t1)
+      for (int t2 = 0; t2 < nc; ++t2) {
+        double v = 0;
+        for (int i = 0; i < nchi; ++i) {
+          const double m = M[(size_t)urow[t1] * A + urow[(size_t)i * nc + t2]];
+          v += (__builtin_popcount(i & j) & 1) ? -m : m;
+        }
+        B[((size_t)j * nc + t1) * ldb + t2] = v * sc;
+      }
+  return B;
+}
+
+const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj);
+void ensure_coarse_buffers(tr_handle *h);
+
 void build(tr_handle *h, const tr_problem *p) {
   if (p->dim != 2 && p->dim != 3) throw ArgError{"dim must be 2 or 3"};
   for (int d = 0; d < p->dim; ++d) {
@@ -355,6 +475,7 @@ void build(tr_handle *h, const tr_problem *p) {
     h->pl.link[0] = reinterpret_cast<const int4 *>(h->upload(link_up));
     h->pl.link[1] = reinterpret_cast<const int4 *>(h->upload(link_dn));
     h->plane_off_host = off;
+    h->cells_host = cells;
     // position of every cell in each orientation's sweep list (the plane
     // layout of forward sweep inputs)
     {
@@ -379,8 +500,10 @@ void build(tr_handle *h, const tr_problem *p) {
   h->sig_t = h->upload(h->sig_t_host);
   h->sig_s = h->upload(h->sig_s_host);
   h->sig_pl = h->alloc<double>(16 * g.C);
-  tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, g, h->sig_pl, nullptr);
-  HIPCHK(hipDeviceSynchronize());
+  if (!h->dry) {
+    tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, g, h->sig_pl, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+  }
 
   // levels
   h->lv.assign(nlev, DevLevel());
@@ -423,7 +546,14 @@ void build(tr_handle *h, const tr_problem *p) {
     tr::scatter_matrix(h->ang, l, mom, St, &X);
     const int A = H.A;
     const int K = (D.order + 1) * (D.order + 1);
-    if (l >= 1 && 20LL * K < 9LL * A) {
+    // scatter form of levels >= 1, by multiply-adds per spatial dof: the
+    // octant-group blocks (2 A^2 / 2^R) where the mesh has the reflection
+    // structure, the factored form (4 A K) where K is small, else dense
+    std::vector<int> urow;
+    int nc = 0;
+    const int R = l >= 1 ? octant_symmetry(h->ang, l, urow, nc) : 0;
+    const double cost_sym = R ? 2.0 * A * A / (1 << R) : 1e300;
+    if (l >= 1 && 20LL * K < 9LL * A && 4.0 * A * K < cost_sym) {
       // G = L R^T with L_q = W_q^{-1} Psi^{-1} X_q F and R_p = Psi^{-1} X_p
       std::vector<double> Lh((size_t)A * K), Rh((size_t)A * K), Lt((size_t)K * A), Rt((size_t)K * A);
       for (int q = 0; q < H.P; ++q)
@@ -467,6 +597,21 @@ void build(tr_handle *h, const tr_problem *p) {
             Gt[(size_t)(3 * p2 + kk) * A + 3 * q + k] = v;
           }
       }
+    if (R && !D.Kf && octant_structured(G, A, urow, R, nc) && octant_structured(Gt, A, urow, R, nc) &&
+        octant_structured(St, A, urow, R, nc)) {
+      D.symR = R;
+      D.sym_nc = nc;
+      D.sym_ldb = (nc + 3) / 4 * 4;
+      D.urow = h->upload(urow);
+      auto up2 = [&](const std::vector<double> &M, double *&b64, float *&b32) {
+        std::vector<double> B = octant_blocks(M, A, urow, R, nc, D.sym_ldb);
+        b64 = h->upload(B);
+        b32 = h->upload(std::vector<float>(B.begin(), B.end()));
+      };
+      up2(G, D.Bh64, D.Bh32);
+      up2(Gt, D.Bht64, D.Bht32);
+      up2(St, D.Bc64, D.Bc32);
+    }
     std::vector<float> St32(St.begin(), St.end()), G32(G.begin(), G.end()), Gt32(Gt.begin(), Gt.end());
     D.St64 = h->upload(St);
     D.St32 = h->upload(St32);
@@ -477,10 +622,28 @@ void build(tr_handle *h, const tr_problem *p) {
     if (l == nlev - 1) {
       if (p->order == D.order) {
         h->Souter = D.St64;
+        h->Bouter = D.Bc64;
       } else {
         std::vector<double> mo(h->moments.begin(), h->moments.begin() + p->order + 1), So;
         tr::scatter_matrix(h->ang, l, mo, So);
         h->Souter = h->upload(So);
+        std::vector<int> ur;
+        int ncc = 0;
+        const int Ro = l >= 1 ? octant_symmetry(h->ang, l, ur, ncc) : 0;
+        if (Ro && octant_structured(So, A, ur, Ro, ncc)) {
+          // the row map depends on the mesh only: share the level's when it has one
+          h->outer_urow = D.urow ? D.urow : h->upload(ur);
+          h->outer_R = Ro;
+          h->outer_nc = ncc;
+          h->outer_ldb = (ncc + 3) / 4 * 4;
+          h->Bouter = h->upload(octant_blocks(So, A, ur, Ro, ncc, h->outer_ldb));
+        }
+      }
+      if (h->Bouter && !h->outer_urow) {
+        h->outer_urow = D.urow;
+        h->outer_R = D.symR;
+        h->outer_nc = D.sym_nc;
+        h->outer_ldb = D.sym_ldb;
       }
       h->iom = h->upload(H.iom);
     }
@@ -532,13 +695,20 @@ void build(tr_handle *h, const tr_problem *p) {
       D.first_child = h->upload(H.first_child);
       D.n_child = h->upload(H.n_child);
     }
+    // level buffers f, u, s (and a second s for nu_pre > 1) in one block;
+    // on levels >= 1 the FP32 V-cycle's buffers live in the same memory
+    // (a solve uses one precision per level at a time)
     const long long n = (long long)D.A * g.S;
-    D.f64 = h->alloc<double>(n);
-    D.u64 = h->alloc<double>(n);
-    D.sa64 = h->alloc<double>(n);
-    D.sb64 = p->nu_pre > 1 ? h->alloc<double>(n) : nullptr;  // second buffer only for nu_pre > 1
-    tr::launch_fill<double>(D.f64, n, 0.0, nullptr);
-    tr::launch_fill<double>(D.u64, n, 0.0, nullptr);
+    const int nbuf = p->nu_pre > 1 ? 4 : 3;
+    D.blk = h->alloc<double>(nbuf * n);
+    D.f64 = D.blk;
+    D.u64 = D.blk + n;
+    D.sa64 = D.blk + 2 * n;
+    D.sb64 = p->nu_pre > 1 ? D.blk + 3 * n : nullptr;
+    if (!h->dry) {
+      tr::launch_fill<double>(D.f64, n, 0.0, nullptr);
+      tr::launch_fill<double>(D.u64, n, 0.0, nullptr);
+    }
   }
   if (h->fact_len > 0) h->fact64 = h->alloc<double>(h->fact_len);
   const long long nf = h->vec_len(h->top());
@@ -546,7 +716,12 @@ void build(tr_handle *h, const tr_problem *p) {
   h->tmp2 = h->alloc<double>(nf);
   h->dot_partial = h->alloc<double>(h->dot_blocks);
   h->dot_out = h->alloc<double>(1);
-  HIPCHK(hipDeviceSynchronize());
+  // the coarse solve's schedules for nu_coarse sweeps (both directions) and
+  // its counters, so that no solve or coarse-solve call allocates them
+  gs_schedule(h, p->nu_coarse, false);
+  gs_schedule(h, p->nu_coarse, true);
+  ensure_coarse_buffers(h);
+  if (!h->dry) HIPCHK(hipDeviceSynchronize());
 }
 
 void ensure_mixed(tr_handle *h) {
@@ -554,10 +729,12 @@ void ensure_mixed(tr_handle *h) {
   for (int l = 1; l < (int)h->lv.size(); ++l) {
     DevLevel &D = h->lv[l];
     const long long n = (long long)D.A * h->g.S;
-    D.f32 = h->alloc<float>(n);
-    D.u32 = h->alloc<float>(n);
-    D.sa32 = h->alloc<float>(n);
-    D.sb32 = h->prob.nu_pre > 1 ? h->alloc<float>(n) : nullptr;
+    // FP32 views of the level block (see build)
+    float *b32 = reinterpret_cast<float *>(D.blk);
+    D.f32 = b32;
+    D.u32 = b32 + n;
+    D.sa32 = b32 + 2 * n;
+    D.sb32 = h->prob.nu_pre > 1 ? b32 + 3 * n : nullptr;
   }
   if (h->fact_len > 0) h->fact32 = h->alloc<float>(h->fact_len);
   h->mixed_ready = true;
@@ -577,6 +754,8 @@ struct LevelBuf<double> {
   static double *sb(DevLevel &D) { return D.sb64; }
   static const double *G(DevLevel &D, bool adj) { return adj ? D.Gt64 : D.G64; }
   static const double *St(DevLevel &D) { return D.St64; }
+  static const double *Bh(DevLevel &D, bool adj) { return adj ? D.Bht64 : D.Bh64; }
+  static const double *Bc(DevLevel &D) { return D.Bc64; }
 };
 template <>
 struct LevelBuf<float> {
@@ -589,6 +768,8 @@ struct LevelBuf<float> {
   static float *sb(DevLevel &D) { return D.sb32; }
   static const float *G(DevLevel &D, bool adj) { return adj ? D.Gt32 : D.G32; }
   static const float *St(DevLevel &D) { return D.St32; }
+  static const float *Bh(DevLevel &D, bool adj) { return adj ? D.Bht32 : D.Bh32; }
+  static const float *Bc(DevLevel &D) { return D.Bc32; }
 };
 
 template <typename T>
@@ -616,7 +797,7 @@ const void *split_of(tr_handle *h, const float *A, int M, int K, hipStream_t st)
   for (auto &e : h->splits)
     if (e.A == A && e.M == M && e.K == K) return e.p;
   void *p = h->alloc<unsigned short>(2LL * M * tr::split_rows_kp(K));
-  tr::launch_split_rows(A, M, K, p, st);
+  if (!h->dry) tr::launch_split_rows(A, M, K, p, st);
   h->splits.push_back({A, M, K, p});
   return p;
 }
@@ -661,11 +842,7 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
   std::vector<int> last(C, -1), to(C, -1);
   std::vector<std::vector<int>> steps, fsteps;
   const int np = h->pl.nplanes;
-  std::vector<int> cells_host;
-  {
-    cells_host.resize(h->plane_off_host.back());
-    HIPCHK(hipMemcpy(cells_host.data(), h->d_cells, cells_host.size() * sizeof(int), hipMemcpyDeviceToHost));
-  }
+  const std::vector<int> &cells_host = h->cells_host;
   const bool flow_ok = 8 * nu <= 127 && C < (1LL << 22);
   for (int sweep = 0; sweep < nu; ++sweep)
     for (int oi = 0; oi < 8; ++oi) {
@@ -808,27 +985,42 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
   return h->gs_sched.back();
 }
 
+// After a coarse solve: a wait that timed out set the error word; it is
+// cleared again (the handle stays usable) and the call reports the error.
 void check_barrier(tr_handle *h, hipStream_t st) {
   if (!h->bar_err) return;
   int e = 0;
   HIPCHK(hipMemcpyAsync(&e, h->bar_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (e) throw std::runtime_error("coarse Gauss-Seidel solve timed out waiting for a grid barrier or an upwind update");
+  if (e) {
+    HIPCHK(hipMemset(h->bar_err, 0, sizeof(int)));
+    HIPCHK(hipDeviceSynchronize());
+    throw std::runtime_error("coarse Gauss-Seidel solve timed out waiting for a grid barrier or an upwind update");
+  }
+}
+
+// Barrier words, the error word and the update counters of the coarse
+// solve (allocated once per handle).
+void ensure_coarse_buffers(tr_handle *h) {
+  if (!h->bar_arrive) {
+    h->bar_arrive = h->alloc<unsigned>(tr_handle::kMaxGsBlocks);
+    h->bar_release = h->alloc<unsigned>(1);
+    h->bar_err = h->alloc<int>(1);
+    if (!h->dry) {
+      HIPCHK(hipMemset(h->bar_arrive, 0, tr_handle::kMaxGsBlocks * sizeof(unsigned)));
+      HIPCHK(hipMemset(h->bar_release, 0, sizeof(unsigned)));
+      HIPCHK(hipMemset(h->bar_err, 0, sizeof(int)));
+      HIPCHK(hipDeviceSynchronize());
+    }
+    h->bar_gen = 0;
+  }
+  if (h->gs_flow && !h->gs_cnt) h->gs_cnt = h->alloc<unsigned>(h->g.C);
 }
 
 void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipStream_t st) {
   DevLevel &D = h->lv[0];
   const tr_handle::GsSchedule &sc = gs_schedule(h, nu, adj);
-  if (!h->bar_arrive) {
-    h->bar_arrive = h->alloc<unsigned>(tr_handle::kMaxGsBlocks);
-    h->bar_release = h->alloc<unsigned>(1);
-    h->bar_err = h->alloc<int>(1);
-    HIPCHK(hipMemset(h->bar_arrive, 0, tr_handle::kMaxGsBlocks * sizeof(unsigned)));
-    HIPCHK(hipMemset(h->bar_release, 0, sizeof(unsigned)));
-    HIPCHK(hipMemset(h->bar_err, 0, sizeof(int)));
-    HIPCHK(hipDeviceSynchronize());
-    h->bar_gen = 0;
-  }
+  ensure_coarse_buffers(h);
   if (h->bar_gen > 0xF0000000u - (unsigned)sc.nsteps) {
     // restart the generation count (all earlier launches on this handle's
     // stream have finished once the stream is synchronised)
@@ -839,7 +1031,6 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
     h->bar_gen = 0;
   }
   if (h->gs_flow && sc.brick) {
-    if (!h->gs_cnt) h->gs_cnt = h->alloc<unsigned>(h->g.C);
     tbegin(h, C_COARSE);
     tr::launch_coarse_brick(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->g, sc.wave_off, sc.slots,
                             sc.waves, adj, h->gs_cnt, sc.nbricks, h->bar_err, st);
@@ -848,7 +1039,6 @@ void do_coarse(tr_handle *h, const double *f, double *u, int nu, bool adj, hipSt
     return;
   }
   if (h->gs_flow && sc.waves > 0) {
-    if (!h->gs_cnt) h->gs_cnt = h->alloc<unsigned>(h->g.C);
     tbegin(h, C_COARSE);
     tr::launch_coarse_flow(f, u, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->g, sc.wave_off,
                            sc.slots, sc.waves, adj, h->gs_cnt, h->bar_err, st);
@@ -873,6 +1063,14 @@ void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t 
                    const T *bias = nullptr, bool plane_out = false) {
   DevLevel &D = h->lv[l];
   const OrdInfo *rord = plane_out ? D.ord : nullptr;
+  if (D.symR) {
+    // octant-group blocks (split-BF16 products are not used on these levels)
+    tbegin(h, C_SCATTER);
+    tr::launch_gemm_oct<T>(LevelBuf<T>::Bh(D, adj), D.sym_ldb, u, y, D.urow, D.symR, D.sym_nc, (int)h->g.S, st, bias,
+                           scale_sn ? h->sig_s : nullptr, h->g.ns, rord ? h->pos_pl : nullptr, rord);
+    tend(h);
+    return;
+  }
   if (!D.Kf) {
     do_gemm<T>(h, LevelBuf<T>::G(D, adj), u, y, D.A, st, scale_sn, bias, rord);
     return;
@@ -960,40 +1158,42 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
 // prepared (N^{-1} applied) for the forward direction, weak form for the
 // adjoint.
 template <typename Tin, typename Tout>
-void convert_in(tr_handle *h, int level, bool adj, const Tin *r, Tout *f, hipStream_t st) {
+void convert_in(tr_handle *h, int level, bool adj, const Tin *r, Tout *f, hipStream_t st, double scale = 1.0) {
   DevLevel &D = h->lv[level];
   if (adj)
-    tr::launch_convert<Tin, Tout>(r, f, D.P, h->g.S, nullptr, nullptr, st);
+    tr::launch_convert<Tin, Tout>(r, f, D.P, h->g.S, nullptr, nullptr, st, scale);
   else
-    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st, D.pin ? h->pos_pl : nullptr, D.ord);
+    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st, D.pin ? h->pos_pl : nullptr, D.ord,
+                                       scale);
 }
 
-void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st) {
+// z = out_scale M^{-1} (in_scale r).  The scales keep the FP32 V-cycle's
+// input at unit size whatever the scale of r (GMRES passes its unnormalised
+// basis vectors with the normalising factor).  With z32 (FP32 preconditioner
+// modes only) the result is also left in FP32 in z32 and z is its exact
+// FP64 image, so the flexible GMRES update can use the stored FP32 vectors.
+void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st,
+                  double in_scale = 1.0, double out_scale = 1.0, float *z32 = nullptr) {
   const int L = h->top();
   h->n_precond++;
   DevLevel &D = h->lv[L];
   const double *pre_out = adj ? D.winv : nullptr, *post_out = nullptr;
-  if (mode == TR_PREC_SG) {
+  const bool mixed = (mode == TR_PREC_MIXED || mode == TR_PREC_MIXED_BF16) && L > 0;
+  if (z32 && !mixed) throw std::runtime_error("internal: FP32 preconditioned vectors need an FP32 V-cycle");
+  if (mode == TR_PREC_SG || L == 0) {
     tbegin(h, C_OTHER);
-    convert_in<double, double>(h, L, adj, r, D.f64, st);
+    convert_in<double, double>(h, L, adj, r, D.f64, st, in_scale);
     tend(h);
-    do_sweep<double>(h, L, D.f64, nullptr, D.u64, adj, st);
+    if (mode == TR_PREC_SG)
+      do_sweep<double>(h, L, D.f64, nullptr, D.u64, adj, st);
+    else
+      do_coarse(h, D.f64, D.u64, h->prob.nu_coarse, adj, st);
     tbegin(h, C_OTHER);
-    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st);
-    tend(h);
-    return;
-  }
-  if (L == 0) {
-    tbegin(h, C_OTHER);
-    convert_in<double, double>(h, L, adj, r, D.f64, st);
-    tend(h);
-    do_coarse(h, D.f64, D.u64, h->prob.nu_coarse, adj, st);
-    tbegin(h, C_OTHER);
-    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st);
+    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st, out_scale);
     tend(h);
     return;
   }
-  if (mode == TR_PREC_MIXED || mode == TR_PREC_MIXED_BF16) {
+  if (mixed) {
     ensure_mixed(h);
     struct Split {  // FP32 scatter products for this V-cycle only
       tr_handle *h;
@@ -1001,28 +1201,43 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
     } split_guard{h};
     h->split32 = mode == TR_PREC_MIXED_BF16;
     tbegin(h, C_OTHER);
-    convert_in<double, float>(h, L, adj, r, D.f32, st);
+    convert_in<double, float>(h, L, adj, r, D.f32, st, in_scale);
     tend(h);
     mg_level<float>(h, L, adj, st);
     tbegin(h, C_OTHER);
-    tr::launch_convert<float, double>(D.u32, z, D.P, h->g.S, pre_out, post_out, st);
+    if (z32) {
+      tr::launch_convert<float, float>(D.u32, z32, D.P, h->g.S, pre_out, post_out, st, out_scale);
+      tr::launch_cast<float, double>(z32, z, h->vec_len(L), st);
+    } else {
+      tr::launch_convert<float, double>(D.u32, z, D.P, h->g.S, pre_out, post_out, st, out_scale);
+    }
     tend(h);
   } else {
     tbegin(h, C_OTHER);
-    convert_in<double, double>(h, L, adj, r, D.f64, st);
+    convert_in<double, double>(h, L, adj, r, D.f64, st, in_scale);
     tend(h);
     mg_level<double>(h, L, adj, st);
     tbegin(h, C_OTHER);
-    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st);
+    tr::launch_convert<double, double>(D.u64, z, D.P, h->g.S, pre_out, post_out, st, out_scale);
     tend(h);
   }
+}
+
+// t = S~ x with the problem's scatter order (canonical FP64, finest level)
+void outer_scatter(tr_handle *h, const double *x, double *t, hipStream_t st) {
+  DevLevel &D = h->lv[h->top()];
+  if (h->Bouter)
+    tr::launch_gemm_oct<double>(h->Bouter, h->outer_ldb, x, t, h->outer_urow, h->outer_R, h->outer_nc, (int)h->g.S,
+                                st);
+  else
+    tr::launch_gemm<double>(h->Souter, x, t, D.A, (int)h->g.S, D.A, st);
 }
 
 // y = A x (adj: A^T x), canonical FP64 on the finest level
 void apply_A(tr_handle *h, bool adj, const double *x, double *y, hipStream_t st) {
   DevLevel &D = h->lv[h->top()];
   tbegin(h, C_SCATTER);
-  tr::launch_gemm<double>(h->Souter, x, h->tmp, D.A, (int)h->g.S, D.A, st);
+  outer_scatter(h, x, h->tmp, st);
   tend(h);
   tbegin(h, C_APPLY);
   tr::launch_apply(x, h->tmp, y, h->sig_t, h->sig_s, D.ord, D.w, D.P, h->g, adj, st);
@@ -1038,26 +1253,46 @@ double dot(tr_handle *h, const double *x, const double *y, long long n, hipStrea
   return v;
 }
 
-void ensure_krylov(tr_handle *h, int m) {
-  if (h->kry_m >= m) return;
+bool mixed_mode(int mode) { return mode == TR_PREC_MIXED || mode == TR_PREC_MIXED_BF16; }
+
+// Krylov workspace for GMRES(m): the basis V (m + 1 FP64 vectors), the work
+// vector, and the preconditioned vectors Z of the flexible form when they
+// are kept (FP64 for the FP64 preconditioners, FP32 for the FP32 ones).
+// Returns 0 (recompute M^{-1}(V y) at each restart), 64 or 32.
+int ensure_krylov(tr_handle *h, int m, int mode, int z_store) {
   const long long n = h->vec_len(h->top());
   while ((int)h->V.size() < m + 1) h->V.push_back(h->alloc<double>(n));
-  // keep M^{-1} v_j (flexible form) when it fits in a quarter of free memory
-  size_t fr = 0, tot = 0;
-  HIPCHK(hipMemGetInfo(&fr, &tot));
-  const size_t need = (size_t)m * n * sizeof(double);
-  if (need < fr / 4) {
-    while ((int)h->Z.size() < m) h->Z.push_back(h->alloc<double>(n));
-  } else {
-    h->Z.clear();
-  }
   if (!h->kw) h->kw = h->alloc<double>(n);
   if (!h->mdot_partial) h->mdot_partial = h->alloc<double>(32LL * h->dot_blocks);
   if (h->mdot_len < 2 * m + 4) {
     h->mdot_len = 2 * m + 4;
     h->mdot_out = h->alloc<double>(h->mdot_len);
   }
-  h->kry_m = m;
+  h->kry_m = std::max(h->kry_m, m);
+  if (z_store == TR_Z_RECOMPUTE) return 0;
+  if (mixed_mode(mode) && h->top() > 0) {
+    // a non-linear (FP32) preconditioner needs the flexible form: always
+    // keep its vectors, in FP32
+    try {
+      while ((int)h->Z32.size() < m) h->Z32.push_back(h->alloc<float>(n));
+    } catch (const std::bad_alloc &) {
+      throw std::runtime_error("out of device memory for the FP32 preconditioned vectors of the flexible GMRES (" +
+                               std::to_string((double)m * n * 4 / 1e9) +
+                               " GB); z_store = TR_Z_RECOMPUTE runs without them");
+    }
+    return 32;
+  }
+  if ((int)h->Z.size() >= m) return 64;
+  const size_t need = (size_t)(m - h->Z.size()) * n * sizeof(double);
+  if (z_store == TR_Z_AUTO) {
+    // a linear (FP64) preconditioner gives the same iterates either way:
+    // keep the vectors when they fit in half of the free memory
+    size_t fr = 0, tot = 0;
+    if (!h->dry) HIPCHK(hipMemGetInfo(&fr, &tot));
+    if (h->dry || need >= fr / 2) return 0;
+  }
+  while ((int)h->Z.size() < m) h->Z.push_back(h->alloc<double>(n));
+  return 64;
 }
 
 // One Arnoldi orthogonalisation in two passes over the basis (modified
@@ -1066,10 +1301,9 @@ void ensure_krylov(tr_handle *h, int m) {
 //   host:   h = (I + L)^{-1} s, L strictly lower with the Gram rows, which
 //           reproduces the sequential projections of modified Gram-Schmidt
 //   pass 2: w -= sum_i h_i v_i, returning |w|^2.
-// The basis is stored unnormalised: v_i = vs[i] V[i], and w = vs[j] W with
-// W the stored vector (the operator applied to the preconditioned stored
-// V[j]); the scales enter the host arithmetic only.  Lg holds the Gram rows
-// (row j written here); hcol receives h; returns |W|^2 after the update.
+// The basis is stored unnormalised: v_i = vs[i] V[i]; the scales enter the
+// host arithmetic only.  Lg holds the Gram rows (row j written here); hcol
+// receives h; returns |w|^2 after the update.
 double arnoldi_orth(tr_handle *h, int j, double *W, const std::vector<double> &vs, std::vector<double> &Lg, int m,
                     double *hcol, long long n, hipStream_t st) {
   const int k = j + 1;
@@ -1090,7 +1324,7 @@ double arnoldi_orth(tr_handle *h, int j, double *W, const std::vector<double> &v
   std::vector<double> sv(k);
   off = 0;
   for (auto &ch : chunks) {
-    for (int q = 0; q < ch[1]; ++q) sv[ch[0] + q] = vs[ch[0] + q] * vs[j] * r[off + q];
+    for (int q = 0; q < ch[1]; ++q) sv[ch[0] + q] = vs[ch[0] + q] * r[off + q];
     for (int q = 0; q < ch[2]; ++q) Lg[(size_t)j * m + ch[0] + q] = vs[j] * vs[ch[0] + q] * r[off + ch[1] + q];
     off += ch[1] + ch[2];
   }
@@ -1099,7 +1333,7 @@ double arnoldi_orth(tr_handle *h, int j, double *W, const std::vector<double> &v
     double t = sv[i];
     for (int q = 0; q < i; ++q) t -= Lg[(size_t)i * m + q] * hcol[q];
     hcol[i] = t;
-    c[i] = -t * vs[i] / vs[j];
+    c[i] = -t * vs[i];
   }
   tr::launch_multi_axpy_norm(n, k, X.data(), c.data(), W, h->dot_partial, h->dot_blocks, h->dot_out, st);
   double nrm2 = 0;
@@ -1111,13 +1345,15 @@ double arnoldi_orth(tr_handle *h, int j, double *W, const std::vector<double> &v
 // Restarted right-preconditioned GMRES(m), x0 = 0, modified Gram-Schmidt.
 // The Krylov basis is kept unnormalised with host-side scales (saves a
 // normalisation pass per step): the next basis vector is the updated work
-// vector itself, whose buffer changes place with the work buffer.
+// vector itself, whose buffer changes place with the work buffer.  The
+// preconditioner always receives the unit basis vector v_j (its scale is
+// applied in the input conversion).  With the preconditioned vectors kept
+// this is flexible GMRES (x += sum y_i z_i); without them x += M^{-1} V y.
 int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
           hipStream_t st) {
   const int m = o->restart;
-  ensure_krylov(h, m);
+  const int zkind = ensure_krylov(h, m, o->prec_mode, o->z_store);
   const long long n = h->vec_len(h->top());
-  const bool keepZ = (int)h->Z.size() >= m;
   tr::launch_fill<double>(x, n, 0.0, st);
   tbegin(h, C_ORTH);
   const double bnorm = std::sqrt(dot(h, b, b, n, st));
@@ -1126,6 +1362,7 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
   stats->restarts = 0;
   stats->converged = 0;
   stats->rel_res = 0;
+  stats->flexible = zkind;
   if (bnorm == 0.0) {
     stats->converged = 1;
     return TR_OK;
@@ -1150,15 +1387,15 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
     gv[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      // z_j = vs[j] M^{-1} V[j], A z_j = vs[j] W
-      double *zj = keepZ ? h->Z[j] : h->tmp2;
+      // z_j = M^{-1} v_j (v_j = vs[j] V[j]), w = A z_j
+      double *zj = zkind == 64 ? h->Z[j] : h->tmp2;
       double *W = h->kw;
-      precondition(h, o->prec_mode, adj, h->V[j], zj, st);
+      precondition(h, o->prec_mode, adj, h->V[j], zj, st, vs[j], 1.0, zkind == 32 ? h->Z32[j] : nullptr);
       apply_A(h, adj, zj, W, st);
       stats->iters++;
       // modified Gram-Schmidt (two passes over the basis, see arnoldi_orth)
       tbegin(h, C_ORTH);
-      const double hn = vs[j] * std::sqrt(arnoldi_orth(h, j, W, vs, Lg, m, hcol.data(), n, st));
+      const double hn = std::sqrt(arnoldi_orth(h, j, W, vs, Lg, m, hcol.data(), n, st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
       tend(h);
       H[(size_t)(j + 1) * m + j] = hn;
@@ -1172,9 +1409,9 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       sn[j] = hn / rho;
       const bool breakdown = hn == 0.0;
       if (!breakdown) {
-        // v_{j+1} = vs[j] W / hn: W becomes V[j+1]
+        // v_{j+1} = W / hn: W becomes V[j+1]
         std::swap(h->V[j + 1], h->kw);
-        vs[j + 1] = vs[j] / hn;
+        vs[j + 1] = 1.0 / hn;
       }
       H[(size_t)j * m + j] = rho;
       H[(size_t)(j + 1) * m + j] = 0.0;
@@ -1188,21 +1425,30 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       for (int jj = i + 1; jj < k; ++jj) t -= H[(size_t)i * m + jj] * y[jj];
       y[i] = t / H[(size_t)i * m + i];
     }
-    for (int i = 0; i < k; ++i) yc[i] = y[i] * vs[i];
     double *w = h->kw;
     tbegin(h, C_ORTH);
-    if (keepZ) {
-      tr::launch_multi_axpy(n, k, h->Z.data(), yc.data(), x, st);
+    if (zkind == 64) {
+      tr::launch_multi_axpy(n, k, h->Z.data(), y.data(), x, st);
+    } else if (zkind == 32) {
+      tr::launch_multi_axpy_f32(n, k, h->Z32.data(), y.data(), x, st);
     } else {
+      for (int i = 0; i < k; ++i) yc[i] = y[i] * vs[i];
       tr::launch_fill<double>(w, n, 0.0, st);
       tr::launch_multi_axpy(n, k, h->V.data(), yc.data(), w, st);
     }
     tend(h);
-    if (!keepZ) {
-      precondition(h, o->prec_mode, adj, w, h->tmp2, st);
-      tbegin(h, C_ORTH);
-      tr::launch_axpy(n, 1.0, h->tmp2, x, st);
-      tend(h);
+    if (!zkind) {
+      // x += M^{-1}(V y), the preconditioner's input scaled to about unit
+      // size (|V y| = |y| for the orthonormal basis)
+      double ny = 0;
+      for (int i = 0; i < k; ++i) ny += y[i] * y[i];
+      ny = std::sqrt(ny);
+      if (ny > 0) {
+        precondition(h, o->prec_mode, adj, w, h->tmp2, st, 1.0 / ny, ny);
+        tbegin(h, C_ORTH);
+        tr::launch_axpy(n, 1.0, h->tmp2, x, st);
+        tend(h);
+      }
     }
     // explicit residual r = b - A x into V[0]
     apply_A(h, adj, x, w, st);
@@ -1262,6 +1508,11 @@ bool any_misaligned(P... p) {
 #define TR_CHECK_ALIGNED(...) \
   if (any_misaligned(__VA_ARGS__)) return fail(TR_ERR_ARG, "device buffers must be 16-byte aligned")
 
+bool valid_mode(int m) {
+  return m == TR_PREC_F64 || m == TR_PREC_MIXED || m == TR_PREC_SG || m == TR_PREC_MIXED_BF16;
+}
+bool valid_zstore(int z) { return z == TR_Z_AUTO || z == TR_Z_KEEP || z == TR_Z_RECOMPUTE; }
+
 int check_level(tr_handle *h, int level) {
   if (!h) return fail(TR_ERR_ARG, "null handle");
   if (level < 0 || level > h->top()) return fail(TR_ERR_ARG, "level out of range");
@@ -1314,15 +1565,81 @@ int tr_info(const tr_handle *h, tr_info_t *out) {
   for (size_t l = 0; l < h->lv.size(); ++l) out->patches[l] = h->lv[l].P;
   out->order_outer = h->prob.order;
   out->device_bytes = h->bytes;
+  for (size_t l = 0; l < h->lv.size(); ++l) {
+    const DevLevel &D = h->lv[l];
+    out->scatter_form[l] = D.symR ? TR_SCATTER_OCTANT : D.Kf ? TR_SCATTER_FACTORED : TR_SCATTER_DENSE;
+    out->scatter_axes[l] = D.symR;
+    out->scatter_k[l] = D.Kf;
+  }
+  out->outer_axes = h->Bouter ? h->outer_R : 0;
   return TR_OK;
 }
 
 int tr_set_sigma(tr_handle *h, const double *sigma_t, const double *sigma_s, tr_stream st) {
   if (!h || !sigma_t || !sigma_s) return fail(TR_ERR_ARG, "null argument");
   return translate([&]() {
+    // the same checks as tr_setup, on a host copy; the handle keeps its
+    // cross sections when they fail
+    std::vector<double> t(h->g.C), sc(h->g.C);
+    HIPCHK(hipMemcpyAsync(t.data(), sigma_t, h->g.C * sizeof(double), hipMemcpyDeviceToHost, S(st)));
+    HIPCHK(hipMemcpyAsync(sc.data(), sigma_s, h->g.C * sizeof(double), hipMemcpyDeviceToHost, S(st)));
+    HIPCHK(hipStreamSynchronize(S(st)));
+    for (long long j = 0; j < h->g.C; ++j) {
+      if (!(std::isfinite(t[j]) && t[j] > 0)) throw ArgError{"sigma_t must be finite and > 0 (cell " + std::to_string(j) + ")"};
+      if (!(std::isfinite(sc[j]) && sc[j] >= 0))
+        throw ArgError{"sigma_s must be finite and >= 0 (cell " + std::to_string(j) + ")"};
+    }
     HIPCHK(hipMemcpyAsync(h->sig_t, sigma_t, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
     HIPCHK(hipMemcpyAsync(h->sig_s, sigma_s, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
     tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, h->g, h->sig_pl, S(st));
+    h->sig_t_host = t;
+    h->sig_s_host = sc;
+    return TR_OK;
+  });
+}
+
+int tr_response(tr_handle *h, const double *w, const double *phi, double *R, tr_stream st) {
+  if (!h || !w || !phi || !R) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(w, phi);
+  return translate([&]() {
+    *R = dot(h, w, phi, h->vec_len(h->top()), S(st));
+    return TR_OK;
+  });
+}
+
+int tr_workspace_bytes(const tr_problem *prob, const tr_solve_opts *o, size_t *bytes) {
+  if (!prob || !bytes) return fail(TR_ERR_ARG, "null argument");
+  *bytes = 0;
+  if (o && (o->restart < 1 || o->restart > 200 || !valid_mode(o->prec_mode) || !valid_zstore(o->z_store)))
+    return fail(TR_ERR_ARG, "bad solver options");
+  std::unique_ptr<tr_handle> h(new tr_handle());
+  h->dry = true;
+  return translate([&]() {
+    build(h.get(), prob);
+    if (o) {
+      // what a solve with these options adds: the FP32 level buffers, the
+      // Krylov workspace, the split-BF16 level matrices, the coarse solve's
+      // schedule and counters
+      const bool mixed = mixed_mode(o->prec_mode) && h->top() > 0;
+      if (mixed) ensure_mixed(h.get());
+      ensure_krylov(h.get(), o->restart, o->prec_mode, o->z_store == TR_Z_AUTO ? TR_Z_KEEP : o->z_store);
+      if (o->prec_mode == TR_PREC_MIXED_BF16 && mixed)
+        for (int l = 1; l <= h->top(); ++l) {
+          DevLevel &D = h->lv[l];
+          if (D.symR) continue;  // octant-block levels take no split products
+          if (D.Kf) {
+            split_of(h.get(), D.Rt32, D.Kf, D.A, nullptr);
+            split_of(h.get(), D.L32, D.A, D.Kf, nullptr);
+          } else {
+            split_of(h.get(), D.G32, D.A, D.A, nullptr);
+          }
+        }
+      if (o->prec_mode != TR_PREC_SG) {
+        gs_schedule(h.get(), h->prob.nu_coarse, false);
+        ensure_coarse_buffers(h.get());
+      }
+    }
+    *bytes = h->bytes;
     return TR_OK;
   });
 }
@@ -1424,7 +1741,13 @@ static int sweep_common(tr_handle *h, int level, int prec, const void *g, void *
       convert_in<double, double>(h, level, adj, (const double *)g, D.f64, S(st));
       do_sweep<double>(h, level, D.f64, nullptr, D.u64, adj, S(st));
       tr::launch_convert<double, double>(D.u64, (double *)phi, D.P, h->g.S, pre_out, nullptr, S(st));
+    } else if (level > 0) {
+      ensure_mixed(h);
+      convert_in<float, float>(h, level, adj, (const float *)g, D.f32, S(st));
+      do_sweep<float>(h, level, D.f32, nullptr, D.u32, adj, S(st));
+      tr::launch_convert<float, float>(D.u32, (float *)phi, D.P, h->g.S, pre_out, nullptr, S(st));
     } else {
+      // level 0 has no FP32 buffers: scratch for this call
       const size_t bytes = (size_t)h->vec_len(level) * sizeof(float);
       TmpBuf tf(bytes), tu(bytes);
       float *f = tf.as<float>(), *u = tu.as<float>();
@@ -1455,21 +1778,25 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
   if (outer && prec != TR_F64) return fail(TR_ERR_UNSUPPORTED, "the problem operator is FP64 only");
   return translate([&]() {
     DevLevel &D = h->lv[level];
+    const int Sn = (int)h->g.S;
     if (prec == TR_F64) {
-      const double *St = outer ? h->Souter : D.St64;
       double *t = level == h->top() ? h->tmp : D.sa64;
-      tr::launch_gemm<double>(St, (const double *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+      if (outer)
+        outer_scatter(h, (const double *)phi, t, S(st));
+      else if (D.symR)
+        tr::launch_gemm_oct<double>(D.Bc64, D.sym_ldb, (const double *)phi, t, D.urow, D.symR, D.sym_nc, Sn, S(st));
+      else
+        tr::launch_gemm<double>(D.St64, (const double *)phi, t, D.A, Sn, D.A, S(st));
       tr::launch_scale_sn<double>(t, (double *)s, h->sig_s, D.A, h->g, S(st));
     } else {
-      TmpBuf tb((size_t)h->vec_len(level) * sizeof(float));
-      float *t = tb.as<float>();
+      float *t = reinterpret_cast<float *>(D.sa64);  // the level's FP64 work buffer holds n floats
       if (prec == TR_F32_SPLIT)
-        tr::launch_gemm_bf16x3(split_of(h, D.St32, D.A, D.A, S(st)), (const float *)phi, t, D.A, (int)h->g.S, D.A,
-                               S(st));
+        tr::launch_gemm_bf16x3(split_of(h, D.St32, D.A, D.A, S(st)), (const float *)phi, t, D.A, Sn, D.A, S(st));
+      else if (D.symR)
+        tr::launch_gemm_oct<float>(D.Bc32, D.sym_ldb, (const float *)phi, t, D.urow, D.symR, D.sym_nc, Sn, S(st));
       else
-        tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, (int)h->g.S, D.A, S(st));
+        tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, Sn, D.A, S(st));
       tr::launch_scale_sn<float>(t, (float *)s, h->sig_s, D.A, h->g, S(st));
-      HIPCHK(hipStreamSynchronize(S(st)));
     }
     return TR_OK;
   });
@@ -1528,9 +1855,7 @@ int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi
 int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, double *z, tr_stream st) {
   if (!h || !r || !z) return fail(TR_ERR_ARG, "null argument");
   TR_CHECK_ALIGNED(r, z);
-  if (prec_mode != TR_PREC_F64 && prec_mode != TR_PREC_MIXED && prec_mode != TR_PREC_SG &&
-      prec_mode != TR_PREC_MIXED_BF16)
-    return fail(TR_ERR_ARG, "bad preconditioner mode");
+  if (!valid_mode(prec_mode)) return fail(TR_ERR_ARG, "bad preconditioner mode");
   return translate([&]() {
     precondition(h, prec_mode, adjoint != 0, r, z, S(st));
     check_barrier(h, S(st));
@@ -1542,11 +1867,9 @@ static int solve_common(tr_handle *h, bool adj, const double *b, double *x, cons
                         tr_solve_stats *stats, tr_stream st) {
   if (!h || !b || !x || !o || !stats) return fail(TR_ERR_ARG, "null argument");
   TR_CHECK_ALIGNED(b, x);
-  if (o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->tol > 0))
+  if (o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->tol > 0) || !valid_zstore(o->z_store))
     return fail(TR_ERR_ARG, "bad solver options");
-  if (o->prec_mode != TR_PREC_F64 && o->prec_mode != TR_PREC_MIXED && o->prec_mode != TR_PREC_SG &&
-      o->prec_mode != TR_PREC_MIXED_BF16)
-    return fail(TR_ERR_ARG, "bad preconditioner mode");
+  if (!valid_mode(o->prec_mode)) return fail(TR_ERR_ARG, "bad preconditioner mode");
   std::unique_ptr<EventTimer> timer;
   int rc = translate([&]() {
     if (o->timing) {
@@ -1599,7 +1922,7 @@ int tr_adjoint_grad(tr_handle *h, const double *w, const double *phi, double *la
   int rc2 = translate([&]() {
     DevLevel &D = h->lv[h->top()];
     tr::launch_grad_t(lam, phi, D.w, D.P, h->g, grad_t, S(st));
-    tr::launch_gemm<double>(h->Souter, phi, h->tmp, D.A, (int)h->g.S, D.A, S(st));
+    outer_scatter(h, phi, h->tmp, S(st));
     tr::launch_grad_s(lam, h->tmp, D.A, h->g, grad_s, S(st));
     HIPCHK(hipStreamSynchronize(S(st)));
     return TR_OK;
@@ -1619,7 +1942,7 @@ int tr_time_sweep_kernel(tr_handle *h, int level, int prec, int reps, double *ms
     if (prec == TR_F32) {
       if (level == 0) throw ArgError{"FP32 sweeps run on levels >= 1"};
       ensure_mixed(h);
-      tr::launch_cast<double, float>(D.f64, D.f32, h->vec_len(level), S(st));
+      tr::launch_fill<float>(D.f32, h->vec_len(level), 1.0f, S(st));
       do_sweep<float>(h, level, D.f32, nullptr, D.u32, false, S(st));
       HIPCHK(hipEventRecord(e0, S(st)));
       for (int i = 0; i < reps; ++i) do_sweep<float>(h, level, D.f32, nullptr, D.u32, false, S(st));
@@ -1652,20 +1975,27 @@ int tr_time_scatter_kernel(tr_handle *h, int level, int outer, int prec, int rep
     if (prec == TR_F32 || prec == TR_F32_SPLIT) {
       if (level == 0) throw ArgError{"FP32 runs on levels >= 1"};
       ensure_mixed(h);
+      // the level's scatter as the V-cycle runs it (TR_F32_SPLIT: the dense
+      // split-BF16 product)
       auto run = [&]() {
         if (prec == TR_F32_SPLIT)
           tr::launch_gemm_bf16x3(split_of(h, D.G32, D.A, D.A, S(st)), D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
         else
-          tr::launch_gemm<float>(D.G32, D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
+          level_scatter<float>(h, level, false, D.u32, D.sa32, S(st));
       };
       run();
       HIPCHK(hipEventRecord(e0, S(st)));
       for (int i = 0; i < reps; ++i) run();
     } else {
-      const double *G = outer ? h->Souter : D.G64;
-      tr::launch_gemm<double>(G, D.u64, D.sa64, D.A, (int)h->g.S, D.A, S(st));
+      auto run = [&]() {
+        if (outer)
+          outer_scatter(h, D.u64, D.sa64, S(st));
+        else
+          level_scatter<double>(h, level, false, D.u64, D.sa64, S(st));
+      };
+      run();
       HIPCHK(hipEventRecord(e0, S(st)));
-      for (int i = 0; i < reps; ++i) tr::launch_gemm<double>(G, D.u64, D.sa64, D.A, (int)h->g.S, D.A, S(st));
+      for (int i = 0; i < reps; ++i) run();
     }
     HIPCHK(hipEventRecord(e1, S(st)));
     HIPCHK(hipEventSynchronize(e1));

@@ -188,9 +188,11 @@ def config5(n=32):
 
 
 def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=True, source=True,
-                  mg_orders=None, restart=10):
+                  mg_orders=None, restart=10, angular=None):
     """Small random heterogeneous problem for parity tests (n: cells per
-    axis, or a tuple of per-axis counts)."""
+    axis, or a tuple of per-axis counts; angular: an AngularSpec replacing
+    the uniform mesh of ``level`` refinements, whose level count then sets
+    the length of mg_orders)."""
     if isinstance(n, (tuple, list)):
         nn = tuple(int(v) for v in n) + (1,) * (3 - len(n))
         n = "x".join(str(v) for v in n)
@@ -201,7 +203,10 @@ def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=Tru
     st = rng.uniform(0.5, 4.0, C)
     ss = c * st * rng.uniform(0.8, 1.0, C)
     q = rng.uniform(0.0, 1.0, C) if source else np.zeros(C)
-    mg = mg_orders if mg_orders is not None else [order] * (level + 1)
-    return Problem(f"small-{dim}d-{n}-ang{level}-L{order}-s{seed}", dim, nn, AngularSpec(level),
+    spec = angular if angular is not None else AngularSpec(level)
+    nlev = spec.base_level + spec.extra_levels + 1
+    mg = mg_orders if mg_orders is not None else [order] * nlev
+    tag = f"ang{level}" if angular is None else f"cone{spec.base_level}+{spec.extra_levels}"
+    return Problem(f"small-{dim}d-{n}-{tag}-L{order}-s{seed}", dim, nn, spec,
                    st, ss, g, order, mg, q, Inflow("iso", 0, 0, value=1.0) if inflow else None,
                    restart=restart)

@@ -13,6 +13,63 @@ from .inputs import Problem
 
 _MODES = {"f64": _lib.TR_PREC_F64, "mixed": _lib.TR_PREC_MIXED, "sg": _lib.TR_PREC_SG,
           "mixed_bf16": _lib.TR_PREC_MIXED_BF16}
+_ZSTORE = {"auto": _lib.TR_Z_AUTO, "keep": _lib.TR_Z_KEEP, "recompute": _lib.TR_Z_RECOMPUTE}
+
+
+def problem_struct(prob: Problem):
+    """The tr_problem of a problem description, with the host arrays it
+    points to (keep the second value alive while the struct is used)."""
+    p = _lib.TrProblem()
+    p.dim = prob.dim
+    for d in range(3):
+        p.n[d] = int(prob.n[d]) if d < len(prob.n) else 1
+        p.len[d] = float(prob.length[d])
+    a = prob.angular
+    p.ang_base_level = a.base_level
+    for d in range(3):
+        p.cone_axis[d] = float(a.cone_axis[d])
+    p.cone_half_angle_deg = float(a.cone_half_angle_deg)
+    p.cone_extra_levels = int(a.extra_levels)
+    p.irregularity_closure = 1 if a.closure else 0
+    st = np.ascontiguousarray(prob.sigma_t, dtype=np.float64)
+    ss = np.ascontiguousarray(prob.sigma_s, dtype=np.float64)
+    mom = np.ascontiguousarray(prob.moments(max([prob.order] + list(prob.mg_orders))), dtype=np.float64)
+    order = np.ascontiguousarray(prob.mg_orders, dtype=np.int32)
+    p.sigma_t = st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.sigma_s = ss.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.order = prob.order
+    p.moments = mom.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.n_levels = len(prob.mg_orders)
+    p.mg_order = order.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    p.nu_pre, p.nu_post, p.nu_coarse = prob.nu_pre, prob.nu_post, prob.nu_coarse
+    if sorted(prob.octant_order) != list(range(8)):
+        raise ValueError("octant_order must be a permutation of 0..7")
+    for i in range(8):
+        p.octant_order[i] = int(prob.octant_order[i])
+    return p, (st, ss, mom, order)
+
+
+def solve_opts(prob: Problem, tol=None, restart=None, max_restarts=200, mode="f64", timing=False, z_store="auto"):
+    o = _lib.TrSolveOpts()
+    o.tol = prob.tol if tol is None else tol
+    o.restart = prob.restart if restart is None else restart
+    o.max_restarts = max_restarts
+    o.prec_mode = _MODES[mode]
+    o.timing = 1 if timing else 0
+    o.z_store = _ZSTORE[z_store]
+    return o
+
+
+def workspace_bytes(prob: Problem, mode=None, restart=None, z_store="auto"):
+    """Device bytes a handle for ``prob`` holds after setup (mode None), or
+    after a solve in that preconditioner mode (host computation only)."""
+    lib = _lib.load()
+    p, keep = problem_struct(prob)
+    o = solve_opts(prob, restart=restart, mode=mode, z_store=z_store) if mode is not None else None
+    out = ctypes.c_size_t()
+    _lib.check(lib.tr_workspace_bytes(ctypes.byref(p), ctypes.byref(o) if o is not None else None,
+                                      ctypes.byref(out)))
+    return out.value
 
 
 def _torch():
@@ -38,33 +95,7 @@ class Transport:
             raise RuntimeError("a HIP device is required")
         self.lib = _lib.load()
         self.prob = prob
-        p = _lib.TrProblem()
-        p.dim = prob.dim
-        for d in range(3):
-            p.n[d] = int(prob.n[d]) if d < len(prob.n) else 1
-            p.len[d] = float(prob.length[d])
-        a = prob.angular
-        p.ang_base_level = a.base_level
-        for d in range(3):
-            p.cone_axis[d] = float(a.cone_axis[d])
-        p.cone_half_angle_deg = float(a.cone_half_angle_deg)
-        p.cone_extra_levels = int(a.extra_levels)
-        p.irregularity_closure = 1 if a.closure else 0
-        self._st = np.ascontiguousarray(prob.sigma_t, dtype=np.float64)
-        self._ss = np.ascontiguousarray(prob.sigma_s, dtype=np.float64)
-        self._mom = np.ascontiguousarray(prob.moments(max([prob.order] + list(prob.mg_orders))), dtype=np.float64)
-        self._ord = np.ascontiguousarray(prob.mg_orders, dtype=np.int32)
-        p.sigma_t = self._st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.sigma_s = self._ss.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.order = prob.order
-        p.moments = self._mom.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.n_levels = len(prob.mg_orders)
-        p.mg_order = self._ord.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-        p.nu_pre, p.nu_post, p.nu_coarse = prob.nu_pre, prob.nu_post, prob.nu_coarse
-        if sorted(prob.octant_order) != list(range(8)):
-            raise ValueError("octant_order must be a permutation of 0..7")
-        for i in range(8):
-            p.octant_order[i] = int(prob.octant_order[i])
+        p, self._host_arrays = problem_struct(prob)
         h = ctypes.c_void_p()
         _lib.check(self.lib.tr_setup(ctypes.byref(p), ctypes.byref(h)))
         self.h = h
@@ -75,6 +106,12 @@ class Transport:
         self.S = info.spatial_dofs
         self.patches = [info.patches[l] for l in range(info.n_levels)]
         self.nlev = info.n_levels
+        # scatter form per level: ("dense" | "factored" | "octant", R or K)
+        names = {_lib.TR_SCATTER_DENSE: "dense", _lib.TR_SCATTER_FACTORED: "factored",
+                 _lib.TR_SCATTER_OCTANT: "octant"}
+        self.scatter_forms = [(names[info.scatter_form[l]], info.scatter_axes[l] or info.scatter_k[l])
+                              for l in range(info.n_levels)]
+        self.outer_axes = info.outer_axes
         self.dev = torch.device("cuda")
 
     def close(self):
@@ -87,6 +124,12 @@ class Transport:
             self.close()
         except Exception:
             pass
+
+    def device_bytes(self):
+        """Device memory the handle holds now (setup plus solver workspace)."""
+        info = _lib.TrInfo()
+        _lib.check(self.lib.tr_info(self.h, ctypes.byref(info)))
+        return info.device_bytes
 
     # ------------------------------------------------------------ sizes
     def n(self, level=None):
@@ -126,6 +169,12 @@ class Transport:
         hi_a = (ctypes.c_int * 3)(*[int(v) for v in hi])
         _lib.check(self.lib.tr_detector(self.h, lo_a, hi_a, _ptr(w), _stream()))
         return w
+
+    def response(self, w, phi):
+        """R = w . phi (the detector response) formed by the library."""
+        R = ctypes.c_double()
+        _lib.check(self.lib.tr_response(self.h, _ptr(w), _ptr(phi), ctypes.byref(R), _stream()))
+        return R.value
 
     def set_sigma(self, sigma_t, sigma_s):
         torch = _torch()
@@ -181,18 +230,13 @@ class Transport:
         _lib.check(self.lib.tr_mg_vcycle(self.h, _MODES[mode], 1 if adjoint else 0, _ptr(r), _ptr(z), _stream()))
         return z
 
-    def _opts(self, tol, restart, max_restarts, mode, timing):
-        o = _lib.TrSolveOpts()
-        o.tol = self.prob.tol if tol is None else tol
-        o.restart = self.prob.restart if restart is None else restart
-        o.max_restarts = max_restarts
-        o.prec_mode = _MODES[mode]
-        o.timing = 1 if timing else 0
-        return o
+    def _opts(self, tol, restart, max_restarts, mode, timing, z_store="auto"):
+        return solve_opts(self.prob, tol, restart, max_restarts, mode, timing, z_store)
 
-    def solve(self, b, tol=None, restart=None, max_restarts=200, mode="f64", timing=False, check=True):
+    def solve(self, b, tol=None, restart=None, max_restarts=200, mode="f64", timing=False, check=True,
+              z_store="auto"):
         x = _torch().empty_like(b)
-        o = self._opts(tol, restart, max_restarts, mode, timing)
+        o = self._opts(tol, restart, max_restarts, mode, timing, z_store)
         st = _lib.TrSolveStats()
         rc = self.lib.tr_gmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st), _stream())
         _lib.check(rc, allow=() if check else (_lib.TR_ERR_NOCONV,))
@@ -215,6 +259,20 @@ class Transport:
         _lib.check(self.lib.tr_time_sweep_kernel(self.h, level, _lib.TR_F64 if prec == "f64" else _lib.TR_F32,
                                                  reps, ctypes.byref(ms), _stream()))
         return ms.value
+
+    def scatter_flops(self, level=None, outer=False):
+        """Multiply-add flops per application of a level's scatter product as
+        the library forms it (the problem operator's with outer)."""
+        level = self.nlev - 1 if level is None else level
+        A, S = 3 * self.patches[level], self.S
+        if outer:
+            return 2.0 * A * A * S / 2 ** self.outer_axes
+        form, k = self.scatter_forms[level]
+        if form == "octant":
+            return 2.0 * A * A * S / 2 ** k
+        if form == "factored":
+            return 4.0 * A * k * S
+        return 2.0 * A * A * S
 
     def time_scatter_kernel(self, level=None, outer=False, prec="f64", reps=10):
         level = self.nlev - 1 if level is None else level

@@ -12,14 +12,40 @@ CASES = [
     dict(dim=2, n=5, level=2, order=8, seed=1),    # S = 100, A = 384
     dict(dim=3, n=3, level=1, order=6, seed=2),    # S = 216
     dict(dim=3, n=4, level=2, order=10, seed=3),   # S = 512, A = 384 (several GEMM tiles)
+    # cones around an oblique axis (levels of 32, 50, 89 patches): octant
+    # blocks of three reflections on level 1, of one (the x reflection) on
+    # level 2, none on level 3, where the order-10 case takes the dense
+    # product and the order-4 case the factored one (as does its level 2)
+    dict(dim=3, n=3, level=1, order=10, seed=5, angular=(1, (0.3, 0.5, 0.81), 25.0, 2)),
+    dict(dim=3, n=3, level=1, order=4, seed=6, angular=(1, (0.3, 0.5, 0.81), 25.0, 2)),
 ]
 
 
 @pytest.fixture(scope="module", params=range(len(CASES)))
 def pair(request):
-    kw = CASES[request.param]
+    kw = dict(CASES[request.param])
     print("case", kw, flush=True)
+    if "angular" in kw:
+        from paper_2010_04559_amd import inputs
+        base, axis, half, extra = kw.pop("angular")
+        kw["angular"] = inputs.AngularSpec(base, axis, half, extra, True)
     return Pair(small(**kw))
+
+
+def test_scatter_forms(pair):
+    """Uniform meshes: every level >= 1 in octant-block form (3 reflected
+    axes); the oblique cone's refined level has no reflection symmetry."""
+    forms = pair.tr.scatter_forms
+    assert forms[0] == ("dense", 0)
+    if pair.prob.angular.extra_levels == 0:
+        assert all(f == ("octant", 3) for f in forms[1:]), forms
+        assert pair.tr.outer_axes == 3
+    elif pair.prob.order == 10:
+        assert forms[1:] == [("octant", 3), ("octant", 1), ("dense", 0)], forms
+        assert pair.tr.outer_axes == 0
+    else:
+        assert forms[1:] == [("octant", 3), ("factored", 25), ("factored", 25)], forms
+        assert pair.tr.outer_axes == 0
 
 
 def _rand(n, seed):
