@@ -215,6 +215,19 @@ int tr_transfer(tr_handle *h, int level, int dir, int prec, const void *in, void
  * first. */
 int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi, tr_stream st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): tr_coarse_gs
+ * without any allocation.  Its update counters and error word live in a
+ * library-owned static device array of 4 MiB + 256 B per device (up to
+ * 2^20 counters: one per 2 x 2 x 2 brick of an even 3-D grid, else one per
+ * cell), which every call on that device shares: calls that overlap on one
+ * device race.  Only the dataflow forms (nu <= 15) run here; the schedule
+ * for nu must exist (nu_coarse of the problem is prepared by tr_setup,
+ * other counts by one earlier tr_coarse_gs call).  Errors: TR_ERR_ARG (no
+ * schedule, too many counters), TR_ERR_UNSUPPORTED (nu > 15), TR_ERR_HIP
+ * (a wait timed out).  Synchronises st. */
+int tr_coarse_gs_noalloc(tr_handle *h, int nu, int adjoint, const double *f, double *phi, tr_stream st);
+
 /* Preconditioner z = M^{-1} r: the V-cycle of Fig. lmg (TR_PREC_F64: all
  * levels FP64; TR_PREC_MIXED: levels >= 1 in FP32, T_0 in FP64;
  * TR_PREC_MIXED_BF16: as TR_PREC_MIXED with the FP32 scatter products

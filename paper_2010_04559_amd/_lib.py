@@ -84,6 +84,7 @@ SIGNATURES = {
     "tr_apply": (ctypes.c_int, [_h, _vp, _vp, _vp]),
     "tr_transfer": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "tr_coarse_gs": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "tr_coarse_gs_noalloc": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "tr_mg_vcycle": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "tr_gmres_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.POINTER(TrSolveOpts), ctypes.POINTER(TrSolveStats), _vp]),
     "tr_adjoint_grad": (ctypes.c_int, [_h, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(TrSolveOpts),

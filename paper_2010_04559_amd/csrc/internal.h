@@ -152,6 +152,7 @@ void launch_multi_axpy_norm(long long n, int k, const double *const *x, const do
 void launch_axpby(long long n, double a, const double *x, double b, const double *y, double *z, hipStream_t st);
 template <typename T>
 void launch_fill(T *x, long long n, T v, hipStream_t st);
+void launch_fill_u32(unsigned *x, long long n, hipStream_t st);  // x[0..n) = 0
 template <typename Tin, typename Tout>
 void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st);
 

@@ -2586,6 +2586,9 @@ template <typename T>
 void launch_fill(T *x, long long n, T v, hipStream_t st) {
   hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, x, n, v);
 }
+void launch_fill_u32(unsigned *x, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, st, x, n);
+}
 template void launch_fill<double>(double *, long long, double, hipStream_t);
 template void launch_fill<float>(float *, long long, float, hipStream_t);
 template <typename Tin, typename Tout>

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1523,6 +1524,34 @@ hipStream_t S(tr_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free coarse solve
+// Scratch of tr_coarse_gs_noalloc: word 0 is the wait-timeout error word,
+// the update counters start at word 64 (256 bytes).  One copy per device,
+// held until the process ends; every call on a device shares it.
+constexpr long long kScratchCounters = 1LL << 20;
+constexpr long long kScratchHeader = 64;
+static __device__ __align__(256) unsigned scratch[kScratchHeader + kScratchCounters];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (resolved once per device, with
+// that device current; host code never uses the array's own name).
+unsigned *scratch_ptr() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw std::runtime_error("device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw std::runtime_error("no device address for the coarse-solve scratch");
+    g_scratch_ptr[dev] = static_cast<unsigned *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
 // =================================================================== ABI
 extern "C" {
 
@@ -1543,6 +1572,7 @@ int tr_setup(const tr_problem *prob, tr_handle **out) {
     h->gs_coh = !(gs && std::strcmp(gs, "barrier_fence") == 0);
     h->gs_brick = !(gs && std::strcmp(gs, "cell") == 0);
     build(h, prob);
+    scratch_ptr();  // the allocation-free coarse solve's scratch on this device
     return TR_OK;
   });
   if (rc != TR_OK) {
@@ -1848,6 +1878,45 @@ int tr_coarse_gs(tr_handle *h, int nu, int adjoint, const double *f, double *phi
     do_coarse(h, D.f64, D.u64, nu, adj, S(st));
     tr::launch_convert<double, double>(D.u64, phi, D.P, h->g.S, adj ? D.winv : nullptr, nullptr, S(st));
     check_barrier(h, S(st));
+    return TR_OK;
+  });
+}
+
+int tr_coarse_gs_noalloc(tr_handle *h, int nu, int adjoint, const double *f, double *phi, tr_stream st) {
+  if (!h || !f || !phi) return fail(TR_ERR_ARG, "null argument");
+  TR_CHECK_ALIGNED(f, phi);
+  if (nu < 1) return fail(TR_ERR_ARG, "nu must be >= 1");
+  const bool adj = adjoint != 0;
+  const tr_handle::GsSchedule *sc = nullptr;
+  for (auto &e : h->gs_sched)
+    if (e.nu == nu && e.adj == adj) sc = &e;
+  if (!sc)
+    return fail(TR_ERR_ARG, "no schedule for this sweep count: the problem's nu_coarse is prepared at setup, "
+                            "other counts after one tr_coarse_gs call with them");
+  if (!h->gs_flow || sc->waves <= 0)
+    return fail(TR_ERR_UNSUPPORTED, "the allocation-free form runs the dataflow solves only (at most 15 sweeps)");
+  const long long ncnt = sc->brick ? sc->nbricks : h->g.C;
+  if (ncnt > kScratchCounters)
+    return fail(TR_ERR_ARG, "the allocation-free coarse solve holds at most " + std::to_string(kScratchCounters) +
+                                " update counters (" + std::to_string(ncnt) + " needed)");
+  return translate([&]() {
+    unsigned *base = scratch_ptr();
+    int *err = reinterpret_cast<int *>(base);
+    unsigned *cnt = base + kScratchHeader;
+    DevLevel &D = h->lv[0];
+    tr::launch_fill_u32(base, 1, S(st));  // error word (the counters are cleared by the launch)
+    convert_in<double, double>(h, 0, adj, f, D.f64, S(st));
+    if (sc->brick)
+      tr::launch_coarse_brick(D.f64, D.u64, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->g, sc->wave_off,
+                              sc->slots, sc->waves, adj, cnt, sc->nbricks, err, S(st));
+    else
+      tr::launch_coarse_flow(D.f64, D.u64, adj ? D.Gt64 : D.G64, h->sig_t, h->sig_s, D.ord, h->pl, h->g,
+                             sc->wave_off, sc->slots, sc->waves, adj, cnt, err, S(st));
+    tr::launch_convert<double, double>(D.u64, phi, D.P, h->g.S, adj ? D.winv : nullptr, nullptr, S(st));
+    int e = 0;
+    HIPCHK(hipMemcpyAsync(&e, err, sizeof(int), hipMemcpyDeviceToHost, S(st)));
+    HIPCHK(hipStreamSynchronize(S(st)));
+    if (e) throw std::runtime_error("coarse Gauss-Seidel solve timed out waiting for an upwind update");
     return TR_OK;
   });
 }
