@@ -1,25 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the angular-multigrid transport solver on one MI355X.
 
-One step = one full solve of the 3-D heterogeneous problem (unit cube,
-32^3 trilinear DG cells, angular level 2 = 128 patches x 3 ordinates, HG
-g = 0.95 at Legendre order 16, lognormal sigma_t, c = 0.98, central unit
-source, vacuum) to ||b - A x|| / ||b|| < 1e-8 with FP64 GMRES(10) and the
-FP64 angular-multigrid V(1,1) preconditioner, right-hand side already in HBM.
-Every transport sweep, scatter GEMM, transfer, coarse Gauss-Seidel sweep and
-Krylov update of the solve runs inside the timed region.
+Workload (default): the 48^3 precision problem -- unit cube, 48^3
+trilinear DG cells, angular level 3 (512 patches x 3 ordinates = 1536
+angular dofs, 1.36e9 DoFs), HG g = 0.98 at Legendre order 32, multigrid
+levels at orders (8, 8, 8, 32), checkerboard of 8^3-cell blocks (sigma_t
+1 / 20, c 0.999 / 0.9), central unit source, vacuum, GMRES(10) to
+||b - A x|| / ||b|| < 1e-8, right-hand side already in HBM.
 
-value = sweep DoF-updates per second of the whole solve: the sum over all
-transport sweeps of (ordinates x spatial dofs), divided by the solve's wall
-time.  Also reported: the same solve with the FP32 V-cycle, the component
-breakdown, and the roofline of the finest-level sweep kernel measured with
-HIP events on the library's stream.
+One step = one solve with the FP32 angular-multigrid preconditioner (FP32
+sweeps, scatter products and transfers on levels >= 1, FP64 coarsest
+level) inside FP64 flexible GMRES: every transport sweep, scatter product,
+transfer, coarse Gauss-Seidel sweep, precision cast and Krylov update of
+the solve runs inside the timed region.  value = sweep DoF-updates per
+second of the whole solve (sum over all transport sweeps of ordinates x
+spatial dofs, divided by the solve's wall time).  The same problem solved
+with the FP64 preconditioner (the plain FP64 solve) is timed beside it:
+time-to-1e-8 of both, their iteration counts and the difference of the two
+solutions are in the line.  The roofline objects come from HIP events
+around every launch of the timed steps, on the library's stream.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3]
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import resource
 import sys
@@ -32,15 +38,16 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 BF16_PEAK_TFS = 2500.0  # dense BF16 MFMA
+METRIC = "sweep DoF-updates/s; time-to-1e-8 residual, FP32-MG vs FP64 plain, 1 GPU"
 
 
 def kernel_sources_digest():
-    """Digest of the sources of the LDS sweep kernel (its section of
-    kernels.hip and the local solve header): the committed counter summary
-    is used only while it matches."""
+    """Digest of the sweep kernels' sources (their sections of kernels.hip
+    and the local solve header): a committed counter summary is used only
+    while it matches."""
     with open(os.path.join(ROOT, "paper_2010_04559_amd", "csrc", "kernels.hip")) as fh:
         src = fh.read()
-    beg = src.index("// ------------------------------------------------------------ LDS sweep")
+    beg = src.index("// ------------------------------------------------------------------ sweep")
     end = src.index("// ------------------------------------------------------- coarse Gauss-Seidel")
     h = hashlib.sha256(src[beg:end].encode())
     with open(os.path.join(ROOT, "paper_2010_04559_amd", "csrc", "local_solve.h"), "rb") as fh:
@@ -48,10 +55,10 @@ def kernel_sources_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, digest):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "sweep_fp64_cfg2_counters.json")
+def measured_traffic(workload, kernel, digest):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload's sweep kernel, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "sweep_%s_counters.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -61,16 +68,19 @@ def measured_traffic(kernel, digest):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(prob):
-    """The oracle's transport sweep on a bounded sample of the same workload:
-    one whole finest-level sweep (all 128 patches) on the 32^3 grid, FP64
-    numpy on the host."""
+def cpu_baseline(prob, max_patches):
+    """The oracle's transport sweep on a bounded sample of the same
+    workload: the finest-level sweep of an evenly spaced subset of the
+    patches (at most max_patches, every octant represented) on the full
+    grid, FP64 numpy on the host."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import numpy as np
     from oracle import angular as ang, spatial as sp, transport as otr
     grid = sp.Grid(prob.dim, prob.n, prob.length)
     patches = ang.AngularMesh.uniform(prob.angular.base_level).leaves()
-    lv = otr.Level(grid, patches, prob.sigma_t, prob.sigma_s, [1.0])
+    step = max(1, len(patches) // max_patches)
+    sample = patches[::step]
+    lv = otr.Level(grid, sample, prob.sigma_t, prob.sigma_s, [1.0])
     g = np.random.default_rng(0).standard_normal(lv.A * grid.S)
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
@@ -81,8 +91,10 @@ def cpu_baseline(prob):
     dofs = lv.A * grid.S
     return {"value": dofs / (t1 - t0), "unit": "DoF-updates/s", "cores": max(1, round(cpu / (t1 - t0))),
             "kind": "oracle",
-            "sample": "one oracle transport sweep (coupled 24x24 local solves) over all %d patches on the "
-                      "%d^3 grid: %d DoF-updates in %.1f s" % (len(patches), prob.n[0], dofs, t1 - t0)}
+            "sample": "one oracle transport sweep (coupled %dx%d local solves) over %d of the %d patches (every %d-th, "
+                      "all octants) on the %s grid: %d DoF-updates in %.1f s"
+                      % (3 * grid.ns, 3 * grid.ns, len(sample), len(patches), step,
+                         "x".join(str(v) for v in prob.n[:prob.dim]), dofs, t1 - t0)}
 
 
 def oracle_timings(args):
@@ -107,7 +119,7 @@ def oracle_timings(args):
         return out, t1 - t0, cpu / max(t1 - t0, 1e-9)
 
     res = {"host_cpus": os.cpu_count(), "rows": []}
-    for name, prob, full in (("cfg1", inputs.config1(), True), ("cfg2", inputs.config2(args.n), False)):
+    for name, prob, full in (("cfg1", inputs.config1(), True), ("cfg2", inputs.config2(), False)):
         op, t_setup, _ = timed(lambda: OracleProblem(prob), name + " setup")
         lv = op.outer
         rng = np.random.default_rng(0)
@@ -130,118 +142,96 @@ def oracle_timings(args):
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=32, help="cells per axis")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
-                    help="cfg2 (default) is the headline line; the others print a measurement line of "
-                         "their own (2-D square, 48^3 precision study, 32^3 beam gradient, cone mesh)")
-    ap.add_argument("--fd-cells", type=int, default=6, help="finite-difference cells for cfg4/cfg5")
-    ap.add_argument("--oracle-timings", action="store_true",
-                    help="only time the oracle on the host (sweep, scatter and V-cycle of the 2-D and 32^3 "
-                         "problems, full solve of the 2-D problem)")
-    ap.add_argument("--profile-kernels", action="store_true",
-                    help="only launch the kernels whose hardware counters are recorded: a 1 GiB device copy "
-                         "(counter calibration), then the finest-level FP64 and FP32 sweeps (3 launches each) "
-                         "and FP64 scatter GEMMs (2 launches) of the headline problem")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
-              "note, not built); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.oracle_timings:
-        print(json.dumps(oracle_timings(args)))
-        return
+def _chunked_rel_diff(x, y, chunk=1 << 27):
+    """|x - y| / |y| (2-norm) and max|x - y| / max|y| without full-size
+    temporaries."""
+    import torch
+    n = x.numel()
+    d2 = y2 = 0.0
+    dm = ym = 0.0
+    for i in range(0, n, chunk):
+        xa, ya = x[i:i + chunk], y[i:i + chunk]
+        t = xa - ya
+        d2 += float(torch.dot(t, t))
+        y2 += float(torch.dot(ya, ya))
+        dm = max(dm, float(t.abs().max()))
+        ym = max(ym, float(ya.abs().max()))
+        del t
+    return math.sqrt(d2 / y2), dm / ym
+
+
+def _timed_solves(tr, b, mode, steps, warmup, label):
+    """Warm-up solves, then `steps` timed solves with HIP events around every
+    launch (component and kernel times over the timed region)."""
+    import torch
+    for _ in range(warmup):
+        x, st = tr.solve(b, mode=mode)
+        del x
+    torch.cuda.synchronize()
+    acc = {}
+    t0 = time.perf_counter()
+    for i in range(steps):
+        x, st = tr.solve(b, mode=mode, timing=True)
+        for k, v in st.items():
+            if k.startswith("ms_") or k.startswith("n_"):
+                acc[k] = acc.get(k, 0) + v
+        print("%s step %d: iters %d rel_res %.2e %.1f ms" % (label, i, st["iters"], st["rel_res"], st["ms_total"]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return x, st, ms, acc
+
+
+def headline(args):
     import torch
     from paper_2010_04559_amd import inputs
     from paper_2010_04559_amd.transport import Transport
-
-    if args.profile_kernels:
-        print(json.dumps(profile_kernels(args)))
-        return
-    if args.workload != "cfg2":
-        print(json.dumps(other_workload(args)))
-        return
-    prob = inputs.config2(args.n)
+    make = {"cfg2": inputs.config2, "cfg3": inputs.config3}[args.workload]
+    prob = make()
     t_setup = time.perf_counter()
     tr = Transport(prob)
     b = tr.rhs()
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
-    print("setup %.1f s, patches %s, S=%d" % (t_setup, tr.patches, tr.S), file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        x, st = tr.solve(b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        x, st = tr.solve(b)
-        print("step %d: iters %d rel_res %.2e" % (i, st["iters"], st["rel_res"]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) / args.steps * 1e3
-    value = st["sweep_dof_updates"] / (ms_step * 1e-3)
-
-    # explicit residual check of the last solve through the library's operator
-    r = b - tr.apply(x)
-    rel_res = float(torch.linalg.norm(r) / torch.linalg.norm(b))
-
-    # FP32 V-cycle inside FP64 GMRES
-    mixed = None
-    if not args.no_mixed:
-        xm, stm = tr.solve(b, mode="mixed")
-        torch.cuda.synchronize()
-        tm0 = time.perf_counter()
-        for _ in range(args.steps):
-            xm, stm = tr.solve(b, mode="mixed")
-        torch.cuda.synchronize()
-        ms_mixed = (time.perf_counter() - tm0) / args.steps * 1e3
-        dx = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
-        mixed = {"ms": ms_mixed, "iters": stm["iters"], "rel_res": stm["rel_res"], "rel_diff_vs_fp64": dx}
-        print("mixed: %.1f ms, iters %d" % (ms_mixed, stm["iters"]), file=sys.stderr, flush=True)
-        # the same V-cycle with split-BF16 scatter products; used only where
-        # its iteration count equals the FP32 one
-        xs, sts = tr.solve(b, mode="mixed_bf16")
-        torch.cuda.synchronize()
-        tm0 = time.perf_counter()
-        for _ in range(args.steps):
-            xs, sts = tr.solve(b, mode="mixed_bf16")
-        torch.cuda.synchronize()
-        ms_split = (time.perf_counter() - tm0) / args.steps * 1e3
-        mixed["split_bf16"] = {"ms": ms_split, "iters": sts["iters"], "rel_res": sts["rel_res"],
-                               "rel_diff_vs_fp64": float(torch.linalg.norm(xs - x) / torch.linalg.norm(x)),
-                               "same_iterations_as_fp32": sts["iters"] == stm["iters"]}
-        print("mixed split-bf16: %.1f ms, iters %d" % (ms_split, sts["iters"]), file=sys.stderr, flush=True)
-
-    # component breakdown (HIP events around every launch group)
-    _, stt = tr.solve(b, timing=True)
-    breakdown = {k: round(stt[k], 3) for k in ("ms_total", "ms_sweep", "ms_scatter", "ms_transfer", "ms_coarse",
-                                               "ms_apply", "ms_orth", "ms_other")}
-
-    # roofline of the finest-level FP64 sweep kernel: algorithmic bytes per
-    # DoF-update = 16 (read the right-hand side, write the solution)
+    free, total = torch.cuda.mem_get_info()
+    print("setup %.1f s, patches %s, S=%d, scatter forms %s, device memory %.1f of %.1f GB free"
+          % (t_setup, tr.patches, tr.S, tr.scatter_forms, free / 1e9, total / 1e9), file=sys.stderr, flush=True)
     L = tr.nlev - 1
-    dofs = 3 * tr.patches[L] * tr.S
-    ms_sweep = tr.time_sweep_kernel(L, "f64", reps=20)
-    achieved = dofs * 16 / (ms_sweep * 1e-3) / 1e9
-    digest = kernel_sources_digest()
-    traffic = measured_traffic("k_sweep_lds<double,3,false,false,true,true>", digest)
-    ms_sweep32 = tr.time_sweep_kernel(L, "f32", reps=20)
-    ms_gemm = tr.time_scatter_kernel(L, outer=False, prec="f64", reps=10)
     A = 3 * tr.patches[L]
-    gemm_tfs = 2.0 * A * A * tr.S / (ms_gemm * 1e-3) / 1e12
-    ms_gemm32 = tr.time_scatter_kernel(L, outer=False, prec="f32", reps=10)
-    gemm32_tfs = 2.0 * A * A * tr.S / (ms_gemm32 * 1e-3) / 1e12
-    ms_gemm16 = tr.time_scatter_kernel(L, outer=False, prec="bf16x3", reps=10)
-    gemm16_tfs = 2.0 * A * A * tr.S / (ms_gemm16 * 1e-3) / 1e12
+    dofs = A * tr.S
 
+    # the step: FP32 angular-MG preconditioner inside FP64 flexible GMRES
+    xm, stm, ms_step, accm = _timed_solves(tr, b, "mixed", args.steps, args.warmup, "fp32-mg")
+    value = stm["sweep_dof_updates"] / (ms_step * 1e-3)
+    # the plain FP64 solve of the same problem
+    reps64 = max(1, min(args.steps, args.fp64_steps))
+    x64, st64, ms64, acc64 = _timed_solves(tr, b, "f64", reps64, 1, "fp64")
+    rel2, relmax = _chunked_rel_diff(xm, x64)
+    free, _ = torch.cuda.mem_get_info()
+    print("after solves: %.1f GB free" % (free / 1e9), file=sys.stderr, flush=True)
+
+    def per_solve(acc, n):
+        return {k[3:]: round(v / n, 3) for k, v in acc.items() if k.startswith("ms_")}
+
+    # dominant kernels of the step, from the events around every launch of
+    # the timed region: the finest-level FP32 sweep (HBM) and the scatter
+    # products (matrix cores)
+    ms_sw = accm["ms_sweep_finest"] / accm["n_sweep_finest"]
+    sweep_bytes = dofs * 8  # FP32: read the right-hand side + write the solution, 4 B each
+    achieved = sweep_bytes / (ms_sw * 1e-3) / 1e9
+    digest = kernel_sources_digest()
+    sweep_kernel = tr.sweep_kernel_name(L, "f32")
+    traffic = measured_traffic(args.workload, sweep_kernel, digest)
+    ms_outer = accm["ms_scatter_outer"] / accm["n_scatter_outer"]
+    fl_outer = tr.scatter_flops(L, outer=True)
+    tf_outer = fl_outer / (ms_outer * 1e-3) / 1e12
+    # back-to-back launches of single kernels (the same kernels, outside a solve)
+    ms_sw64 = tr.time_sweep_kernel(L, "f64", reps=5)
+    ms_sw32 = tr.time_sweep_kernel(L, "f32", reps=5)
+    ms_g32 = tr.time_scatter_kernel(L, outer=False, prec="f32", reps=5)
+    fl_lv = tr.scatter_flops(L)
     line = {
-        "metric": "sweep DoF-updates/s; time-to-1e-8 residual, FP32-MG vs FP64 plain, 1 GPU",
+        "metric": METRIC,
         "value": value,
         "unit": "DoF-updates/s",
         "n_gpus": 1,
@@ -251,47 +241,93 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "3-D unit cube %d^3 trilinear DG, angular level 2 (128 patches x 3), HG g=0.95 "
-                               "L=16, lognormal sigma_t (median 5, log-sd 1, seed 0), c=0.98, central 4^3 unit "
-                               "source, vacuum; GMRES(10) + FP64 angular MG V(1,1), tol 1e-8" % args.n,
+        "config": {"workload": prob.name + ": " + (make.__doc__ or "").strip().replace("\n", " "),
                    "cells": tr.C, "spatial_dofs": tr.S, "angular_dofs": A, "dofs": dofs,
+                   "step": "one solve to 1e-8: FP64 flexible GMRES(%d) + FP32 angular MG V(1,1), FP64 coarsest "
+                           "level (10 Gauss-Seidel sweeps)" % prob.restart,
                    "parallelism": "single GPU"},
-        "time_to_tol_ms": {"fp64_plain": ms_step, "fp32_mg": mixed["ms"] if mixed else None,
-                           "fp32_mg_split_bf16": mixed["split_bf16"]["ms"] if mixed else None},
-        "iters": {"fp64_plain": st["iters"], "fp32_mg": mixed["iters"] if mixed else None,
-                  "fp32_mg_split_bf16": mixed["split_bf16"]["iters"] if mixed else None},
-        "explicit_rel_res": rel_res,
-        "mixed": mixed,
-        "breakdown_ms": breakdown,
+        "time_to_tol_ms": {"fp32_mg": ms_step, "fp64_plain": ms64, "fp64_over_fp32_mg": ms64 / ms_step},
+        "iters": {"fp32_mg": stm["iters"], "fp64_plain": st64["iters"]},
+        "explicit_rel_res": {"fp32_mg": stm["rel_res"], "fp64_plain": st64["rel_res"]},
+        "fp32_mg_vs_fp64_solution": {"rel_l2": rel2, "rel_max": relmax},
+        "sweep_dof_updates_per_s": {"fp32_mg": value, "fp64_plain": st64["sweep_dof_updates"] / (ms64 * 1e-3)},
+        "breakdown_ms_per_solve": {"fp32_mg": per_solve(accm, args.steps), "fp64_plain": per_solve(acc64, reps64)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep_lds<double,3,false,false,true,true> (finest-level FP64 transport sweep)",
-                     "ms_per_launch": ms_sweep, "bytes_per_launch": dofs * 16},
-        "sweep_kernel": {"fp64_dof_per_s": dofs / (ms_sweep * 1e-3), "fp32_dof_per_s": dofs / (ms_sweep32 * 1e-3),
-                         "fp32_ms": ms_sweep32},
-        "scatter_gemm": {"fp64_ms": ms_gemm, "fp64_tflops": gemm_tfs, "fp64_frac": gemm_tfs / FP64_PEAK_TFS,
-                         "fp32_ms": ms_gemm32, "fp32_tflops": gemm32_tfs, "fp32_frac": gemm32_tfs / FP32_PEAK_TFS,
-                         "split_bf16_ms": ms_gemm16, "split_bf16_tflops_fp32_equiv": gemm16_tfs,
-                         "split_bf16_mfma_frac": 3 * gemm16_tfs / BF16_PEAK_TFS},
-        "coarse_gs": coarse_gs_line(stt),
+                     "kernel": sweep_kernel + " (finest-level FP32 transport sweep)",
+                     "ms_per_launch": ms_sw, "launches": accm["n_sweep_finest"], "bytes_per_launch": sweep_bytes},
+        "roofline_scatter": {"bound": "mfma", "achieved": tf_outer, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                             "frac": tf_outer / FP64_PEAK_TFS,
+                             "kernel": "problem-operator scatter, FP64 %s form" % ("octant-block" if tr.outer_axes
+                                                                                  else "dense"),
+                             "ms_per_launch": ms_outer, "launches": accm["n_scatter_outer"],
+                             "flop_per_launch": fl_outer,
+                             "dense_equivalent_tflops": 2.0 * A * A * tr.S / (ms_outer * 1e-3) / 1e12},
+        "kernels_back_to_back": {
+            "sweep_f64_ms": ms_sw64, "sweep_f64_dof_per_s": dofs / (ms_sw64 * 1e-3),
+            "sweep_f64_hbm_frac": dofs * 16 / (ms_sw64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "sweep_f32_ms": ms_sw32, "sweep_f32_dof_per_s": dofs / (ms_sw32 * 1e-3),
+            "sweep_f32_hbm_frac": dofs * 8 / (ms_sw32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "scatter_f32_finest_ms": ms_g32, "scatter_f32_finest_tflops": fl_lv / (ms_g32 * 1e-3) / 1e12,
+            "scatter_f32_finest_frac": fl_lv / (ms_g32 * 1e-3) / 1e12 / FP32_PEAK_TFS},
+        "scatter_forms": [list(f) for f in tr.scatter_forms],
+        "coarse_gs": coarse_gs_line(accm, args.steps),
         "setup_s": t_setup,
     }
+    del xm, x64, b
+    tr.close()
+    torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(prob)
-    print(json.dumps(line))
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_patches)
+    return line
 
 
-def coarse_gs_line(stt):
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed FP64-preconditioned solves (at most --steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-patches", type=int, default=64, help="patches in the oracle sweep sample")
+    ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="cfg3 (default, the 48^3 precision problem) and cfg2 (32^3) print the benchmark line; "
+                         "the others a measurement line of their own (2-D square, 32^3 beam gradient, cone mesh)")
+    ap.add_argument("--fd-cells", type=int, default=6, help="finite-difference cells for cfg4/cfg5")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the oracle on the host (sweep, scatter and V-cycle of the 2-D and 32^3 "
+                         "problems, full solve of the 2-D problem)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch the kernels whose hardware counters are recorded: a 1 GiB device copy "
+                         "(counter calibration), then the finest-level sweeps and scatter products of the workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
+              "note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.oracle_timings:
+        print(json.dumps(oracle_timings(args)))
+        return
+    if args.profile_kernels:
+        print(json.dumps(profile_kernels(args)))
+        return
+    if args.workload not in ("cfg2", "cfg3"):
+        print(json.dumps(other_workload(args)))
+        return
+    print(json.dumps(headline(args)))
+
+
+def coarse_gs_line(acc, steps):
     """Latency figures of the coarsest-level Gauss-Seidel solve: time per
-    solve and per dependent step of its step schedule."""
-    if not stt["n_coarse"] or not stt["coarse_steps"]:
+    solve and per dependent step of its schedule."""
+    if not acc.get("n_coarse") or not acc.get("coarse_steps"):
         return None
-    ms = stt["ms_coarse"] / stt["n_coarse"]
-    return {"ms_per_solve": ms, "dependent_steps": stt["coarse_steps"],
-            "us_per_step": 1e3 * ms / stt["coarse_steps"]}
+    ms = acc["ms_coarse"] / acc["n_coarse"]
+    nsteps = acc["coarse_steps"] / steps
+    return {"ms_per_solve": ms, "dependent_steps": nsteps, "us_per_step": 1e3 * ms / nsteps}
 
 
 def profile_kernels(args):
@@ -305,14 +341,18 @@ def profile_kernels(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     print("copy of %d bytes done" % (8 * n_copy), file=sys.stderr, flush=True)
-    prob = inputs.config2(args.n)
+    del src, dst
+    prob = {"cfg2": inputs.config2, "cfg3": inputs.config3}.get(args.workload, inputs.config3)()
     tr = Transport(prob)
     L = tr.nlev - 1
-    out = {"copy_bytes": 8 * n_copy, "dofs": 3 * tr.patches[L] * tr.S,
+    out = {"copy_bytes": 8 * n_copy, "workload": prob.name, "dofs": 3 * tr.patches[L] * tr.S,
            "sweep_f64_ms": tr.time_sweep_kernel(L, "f64", reps=3),
            "sweep_f32_ms": tr.time_sweep_kernel(L, "f32", reps=3),
-           "gemm_f64_ms": tr.time_scatter_kernel(L, outer=False, prec="f64", reps=2)}
+           "scatter_outer_f64_ms": tr.time_scatter_kernel(L, outer=True, prec="f64", reps=2),
+           "scatter_f32_ms": tr.time_scatter_kernel(L, outer=False, prec="f32", reps=2),
+           "sweep_kernel_f32": tr.sweep_kernel_name(L, "f32"), "sources_digest": kernel_sources_digest()}
     torch.cuda.synchronize()
+    tr.close()
     return out
 
 

@@ -111,6 +111,8 @@ typedef struct {
   int scatter_axes[16];         /* R of the OCTANT form, else 0                    */
   int scatter_k[16];            /* K of the FACTORED form, else 0                  */
   int outer_axes;               /* R of the problem operator's scatter, 0 = dense  */
+  int sweep_lds[2];             /* 1: the FP64 / FP32 forward sweeps keep the      */
+                                /* previous diagonal plane in LDS (planes fit)     */
 } tr_info_t;
 
 typedef struct {
@@ -141,6 +143,8 @@ typedef struct {
   double sweep_dof_updates;     /* sum over transport sweeps of (ordinates x spatial dofs) */
   int coarse_steps;             /* dependent steps of one coarse Gauss-Seidel solve */
   int flexible;                 /* preconditioned vectors kept: 64 / 32 (bits), 0 recomputed */
+  double ms_scatter_outer;      /* time in the problem operator's scatter products */
+  int n_scatter_outer;          /* (included in ms_scatter / n_scatter)            */
 } tr_solve_stats;
 
 /* Build the angular mesh, quadrature, level operators, prolongations and

@@ -36,7 +36,8 @@ class TrInfo(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("cells", ctypes.c_int), ("spatial_dofs", ctypes.c_int),
                 ("n_levels", ctypes.c_int), ("patches", ctypes.c_int * 16), ("order_outer", ctypes.c_int),
                 ("device_bytes", ctypes.c_size_t), ("scatter_form", ctypes.c_int * 16),
-                ("scatter_axes", ctypes.c_int * 16), ("scatter_k", ctypes.c_int * 16), ("outer_axes", ctypes.c_int)]
+                ("scatter_axes", ctypes.c_int * 16), ("scatter_k", ctypes.c_int * 16), ("outer_axes", ctypes.c_int),
+                ("sweep_lds", ctypes.c_int * 2)]
 
 
 class TrInflow(ctypes.Structure):
@@ -59,7 +60,7 @@ class TrSolveStats(ctypes.Structure):
                 ("n_coarse", ctypes.c_int), ("ms_sweep_finest", ctypes.c_double),
                 ("n_sweep_finest", ctypes.c_int), ("n_precond", ctypes.c_int),
                 ("sweep_dof_updates", ctypes.c_double), ("coarse_steps", ctypes.c_int),
-                ("flexible", ctypes.c_int)]
+                ("flexible", ctypes.c_int), ("ms_scatter_outer", ctypes.c_double), ("n_scatter_outer", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -422,17 +422,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // That is 2 A^2 / 2^R multiply-adds per column instead of 2 A^2.  One
 // kernel does all of it: a workgroup owns a BM x BN tile of transformed rows
 // for every chi at once; per k-slice the loader threads fetch the 2^R
-// canonical rows of each transformed index (urow[i][t], i the sign pattern
-// in the order of its bits) and transform them in registers into the 2^R
-// B tiles, the other threads stage the 2^R A tiles; after the k loop each
+// canonical rows of each transformed index (row = t + off[c][i], c the
+// coset of t, i the sign pattern in the order of its bits: computed, no
+// dependent loads) and transform them in registers into the 2^R B tiles, the other threads stage the 2^R A tiles; after the k loop each
 // lane holds, for its accumulator positions, the values of every chi, and
 // the inverse transform is taken in registers before the store (with the
 // epilogue of k_gemm).  U and C each cross HBM once.
+template <int R>
+__device__ __forceinline__ int oct_row(const OctMap &om, int t, int i) {
+  // coset of t (cosets are runs of transformed rows), then its offset
+  constexpr int NCOS = 8 >> R;
+  int off = om.off[0][i];
+#pragma unroll
+  for (int c = 1; c < NCOS; ++c)
+    if (t >= om.cstart[c]) off = om.off[c][i];
+  return t + off;
+}
+
 template <typename T, int R, int BM, int BN, int BK, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_oct(
-    const T *__restrict__ Bh, int ldb, const T *__restrict__ U, T *__restrict__ C, const int *__restrict__ urow,
-    int nc, int N, int mblocks, int nblocks, const T *__restrict__ bias, const double *__restrict__ colscale,
-    int cell, const int *__restrict__ pos, const OrdInfo *__restrict__ rord, long long ncells) {
+    const T *__restrict__ Bh, int ldb, const T *__restrict__ U, T *__restrict__ C, OctMap om, int nc, int N,
+    int mblocks, int nblocks, const T *__restrict__ bias, const double *__restrict__ colscale, int cell,
+    const int *__restrict__ pos, const OrdInfo *__restrict__ rord, long long ncells) {
   constexpr int NCHI = 1 << R;
   using acc_t = typename Mma<T>::acc_t;
   using V = Vec16<T>;
@@ -480,7 +491,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
       for (int i = 0; i < NCHI; ++i) {
         if (gk < nc) {
-          const long long row = urow[i * nc + gk];
+          const long long row = oct_row<R>(om, gk, i);
           if (gn + VN <= N) {
             rx[i] = *reinterpret_cast<const V *>(U + row * N + gn);
           } else {
@@ -605,7 +616,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             }
 #pragma unroll
         for (int q = 0; q < NCHI; ++q) {
-          const long long row = urow[q * nc + t];
+          const long long row = oct_row<R>(om, t, q);
           long long col = gn;
           if (pos) col = (long long)pos_s[rord[row].flip][(int)((gn - n0) / cell)] * cell + (gn % cell);
           const long long o = row * N + col;
@@ -643,37 +654,51 @@ void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t 
   else
     launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
 }
-// Octant-group product (see k_gemm_oct): FP64 tiles 32 x 64 x 4, FP32
-// 64 x 64 x 4, 256 threads, LDS double buffering.
+// Octant-group product (see k_gemm_oct): 256 threads, LDS double buffering.
 template <typename T, int R, int BM, int BN, int BK, int WPE>
-static void launch_oct_shape(const T *Bh, int ldb, const T *U, T *C, const int *urow, int nc, int N, hipStream_t st,
+static void launch_oct_shape(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, int nc, int N, hipStream_t st,
                              const T *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   const int mblocks = (nc + BM - 1) / BM;
   const int nblocks = (int)(((long long)N + BN - 1) / BN);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
   const long long grid = (long long)mblocks * nb_pad;
-  hipLaunchKernelGGL((k_gemm_oct<T, R, BM, BN, BK, WPE>), dim3((unsigned)grid), dim3(256), 0, st, Bh, ldb, U, C, urow,
+  hipLaunchKernelGGL((k_gemm_oct<T, R, BM, BN, BK, WPE>), dim3((unsigned)grid), dim3(256), 0, st, Bh, ldb, U, C, om,
                      nc, N, mblocks, nblocks, bias, colscale, cell, pos, rord, (long long)(N / cell));
 }
 
 template <typename T>
-void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const int *urow, int R, int nc, int N, hipStream_t st,
-                     const T *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
+void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, int N, hipStream_t st, const T *bias,
+                     const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
-  constexpr bool F64 = sizeof(T) == 8;
-  constexpr int BM = F64 ? 32 : 64, BN = 64, BK = 4;
-  switch (R) {
-    case 1: launch_oct_shape<T, 1, BM, BN, BK, 2>(Bh, ldb, U, C, urow, nc, N, st, bias, colscale, cell, pos, rord); break;
-    case 2: launch_oct_shape<T, 2, BM, BN, BK, 2>(Bh, ldb, U, C, urow, nc, N, st, bias, colscale, cell, pos, rord); break;
-    case 3: launch_oct_shape<T, 3, BM, BN, BK, 2>(Bh, ldb, U, C, urow, nc, N, st, bias, colscale, cell, pos, rord); break;
-    default: throw std::runtime_error("octant-group GEMM: 1 to 3 reflected axes");
+  const int nc = om.nc;
+#define TR_OCT(BM, BN, BK)                                                                                        \
+  switch (om.R) {                                                                                                 \
+    case 1: launch_oct_shape<T, 1, BM, BN, BK, 2>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+      break;                                                                                                      \
+    case 2: launch_oct_shape<T, 2, BM, BN, BK, 2>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+      break;                                                                                                      \
+    case 3: launch_oct_shape<T, 3, BM, BN, BK, 2>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+      break;                                                                                                      \
+    default: throw std::runtime_error("octant-group GEMM: 1 to 3 reflected axes");                                \
   }
+  // shapes measured on MI355X (nc = 192 and 48, N = 884736, three axes):
+  // FP64 32 x 64 x 4 17.2 ms / 32 x 32 x 8 2.14 ms, FP32 32 x 64 x 8 8.8 / 1.2 ms
+  if constexpr (sizeof(T) == 8) {
+    if (nc > 64) {
+      TR_OCT(32, 64, 4)
+    } else {
+      TR_OCT(32, 32, 8)
+    }
+  } else {
+    TR_OCT(32, 64, 8)
+  }
+#undef TR_OCT
 }
-template void launch_gemm_oct<double>(const double *, int, const double *, double *, const int *, int, int, int,
+template void launch_gemm_oct<double>(const double *, int, const double *, double *, const OctMap &, int,
                                       hipStream_t, const double *, const double *, int, const int *,
                                       const OrdInfo *);
-template void launch_gemm_oct<float>(const float *, int, const float *, float *, const int *, int, int, int,
-                                     hipStream_t, const float *, const double *, int, const int *, const OrdInfo *);
+template void launch_gemm_oct<float>(const float *, int, const float *, float *, const OctMap &, int, hipStream_t,
+                                     const float *, const double *, int, const int *, const OrdInfo *);
 
 int split_rows_kp(int K) { return (K + 31) / 32 * 32; }
 

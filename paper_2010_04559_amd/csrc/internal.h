@@ -163,13 +163,21 @@ template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias = nullptr,
                  const double *colscale = nullptr, int cell = 8,
                  const int *pos = nullptr, const OrdInfo *rord = nullptr);
+// Row map of the octant-group form: transformed row t (t < nc = rows / 2^R)
+// lies in coset c (cstart[c] <= t < cstart[c + 1], cosets = the octants with
+// the reflected sign bits clear); under sign pattern i it is canonical row
+// t + off[c][i].
+struct OctMap {
+  int R, nc, ncos;
+  int cstart[9];
+  int off[8][8];
+};
 // C = M U for a scatter matrix M with the octant reflection structure, via
 // its 2^R Walsh-Hadamard blocks Bh ([2^R][nc][ldb], the factor 2^-R folded
-// in; nc = rows / 2^R, ldb >= nc a multiple of 4, zero-padded) and the row
-// map urow[i][t] (canonical row of transformed index t under sign pattern
-// i); same epilogue as launch_gemm.  U, C: [2^R nc][N].
+// in; ldb >= nc a multiple of 4, zero-padded); same epilogue as
+// launch_gemm.  U, C: [2^R nc][N].
 template <typename T>
-void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const int *urow, int R, int nc, int N, hipStream_t st,
+void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, int N, hipStream_t st,
                      const T *bias = nullptr, const double *colscale = nullptr, int cell = 8,
                      const int *pos = nullptr, const OrdInfo *rord = nullptr);
 // FP32 C = A B with split-BF16 operands (three BF16 MFMA products, FP32

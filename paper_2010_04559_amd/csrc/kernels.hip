@@ -243,7 +243,6 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs<T> a) {
 // the next plane and the store waves read it: a plane's values overwrite
 // those of two planes back, whose readers all passed the barrier between.
 // With one buffer a second barrier precedes the overwrite.
-constexpr int kSweepLdsThreads = 1024;
 
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -279,8 +278,9 @@ struct StageRegs {
   int4 lk;
 };
 
+// One cell per compute lane (planes up to 960 cells), 1024 threads.
 template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, bool PIN, int FLIP>
-__device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
+__device__ __forceinline__ void sweep_lds_body1(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
                                                float4 *stage, int tc) {
   constexpr int NS = 1 << DIM;
   constexpr int Q = NS * (int)sizeof(T) / 16;  // 16-byte chunks per cell
@@ -492,7 +492,7 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
       const int n = off[p + 1] - off[p];
       const T *pb = lds + (DBUF ? (pp & 1) : 0) * NS * maxp;
       const int *jb = jbuf + (DBUF ? (pp & 1) : 0) * maxp;
-      for (int base = (tid - tc) / 64 * CPI; base < n; base += (kSweepLdsThreads - tc) / 64 * CPI) {
+      for (int base = (tid - tc) / 64 * CPI; base < n; base += (1024 - tc) / 64 * CPI) {
         const int q = base + lane % CPI;
         if (q < n) {
           T w[EPC];
@@ -505,8 +505,277 @@ __device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *
   }
 }
 
-template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, bool PIN>
-__global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a, int tc) {
+// Several cells per compute lane (larger planes; FP32, 3-D).
+template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, bool PIN, int FLIP, int CPT, int NT>
+__device__ __forceinline__ void sweep_lds_body(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
+                                               float4 *stage, int tc) {
+  constexpr int NS = 1 << DIM;
+  constexpr int Q = NS * (int)sizeof(T) / 16;  // 16-byte chunks per cell
+  constexpr int CPI = 64 / Q;                   // cells per 16-byte wave access
+  constexpr int EPC = 16 / (int)sizeof(T);      // elements per chunk
+  using Regs = StageRegs<Q, HAS_S>;
+  const OrdInfo o = a.ord[k];
+  const T c[3] = {T(o.c[0]), T(o.c[1]), T(o.c[2])};
+  const T av[3] = {T(o.a[0]), T(o.a[1]), T(o.a[2])};
+  const ModeConst<T, DIM> mc = mode_const<T, DIM>(c);
+  const long long S = a.g.S;
+  const T *fk = a.f + (long long)k * S;
+  const T *sk = HAS_S ? a.s + (long long)k * S : nullptr;
+  T *uk = a.u + (long long)k * S;
+  const long long C = a.g.C;
+  const double *sgt = a.sig_pl + (long long)FLIP * C;
+  const double *sgs = a.sig_pl + (8LL + FLIP) * C;
+  const int np = a.pl.nplanes;
+  const int maxp = a.pl.max_plane;
+  const int4 *link = a.pl.link[ADJ ? 1 : 0];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const bool compute = tid < tc;
+  // this wave's staging area: Q KB for f, then Q KB for s (the CPT cell
+  // groups of a lane pass through it one after the other)
+  float4 *stg = stage + (size_t)(tid >> 6) * (HAS_S ? 2 : 1) * Q * 64;
+  auto plane_of = [&](int pp) { return ADJ ? np - 1 - pp : pp; };
+  // Every global load below is unconditional, from an address clamped to
+  // valid memory, and its validity is applied only after the wait: a load
+  // under a branch, or a select on its result, would make the compiler
+  // wait for it (and for everything issued before it) at once.  Cell group
+  // r of a compute lane is plane position tid + r tc.
+  auto link_valid = [&](int pp, int r) {
+    const int p = plane_of(pp);
+    return off[p] + tid + r * tc < off[p + 1];
+  };
+  auto load_link = [&](int pp, int r) {
+    const int p = plane_of(pp);
+    return link[min(off[p] + tid + r * tc, (int)C - 1)];
+  };
+  // loads of plane pp for this wave's 64 cells of group r; q.lk holds the
+  // lane's own entry (its cell index is shuffled to the lanes that load
+  // its chunks)
+  auto load_plane = [&](int pp, int r, Regs &q) {
+    const int p = plane_of(pp);
+    const int idx = min(off[p] + tid + r * tc, (int)C - 1);
+    const int j = q.lk.x >= 0 ? (int)flipped_cell(q.lk.x, FLIP, a.g) : 0;
+    const int ch = lane / CPI;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int jj = __shfl(j, CPI * i + lane % CPI, 64);
+      // plane layout: the wave's cells are consecutive list positions
+      const long long fi =
+          PIN ? (long long)min(off[p] + (tid & ~63) + r * tc + CPI * i + lane % CPI, (int)C - 1) : jj;
+      q.f[i] = *reinterpret_cast<const float4 *>(fk + fi * NS + ch * EPC);
+      if (HAS_S) q.s[HAS_S ? i : 0] = *reinterpret_cast<const float4 *>(sk + (long long)jj * NS + ch * EPC);
+    }
+    q.st = sgt[idx];
+    if (HAS_S) q.ss = sgs[idx];
+  };
+  // staged chunks -> LDS staging (same wave writes and reads it)
+  auto stage_plane = [&](Regs &q) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      stg[i * 64 + lane] = q.f[i];
+      if (HAS_S) stg[(Q + i) * 64 + lane] = q.s[HAS_S ? i : 0];
+    }
+  };
+  auto read_cell = [&](T *fv, T *sv) {
+    const int i = lane / CPI, cc = lane % CPI;
+#pragma unroll
+    for (int ch = 0; ch < Q; ++ch) {
+      const float4 x = stg[i * 64 + ch * CPI + cc];
+      const T *xe = reinterpret_cast<const T *>(&x);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) fv[ch * EPC + e] = xe[e];
+      if (HAS_S) {
+        const float4 y = stg[(Q + i) * 64 + ch * CPI + cc];
+        const T *ye = reinterpret_cast<const T *>(&y);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) sv[ch * EPC + e] = ye[e];
+      }
+    }
+  };
+  auto pin_regs = [&](Regs &q) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      pin_reg(q.f[i]);
+      if (HAS_S) pin_reg(q.s[HAS_S ? i : 0]);
+    }
+    pin_reg(q.st);
+    if (HAS_S) pin_reg(q.ss);
+  };
+
+  Regs cur[CPT], nxt[CPT];
+#pragma unroll
+  for (int r = 0; r < CPT; ++r) {
+    cur[r].lk = make_int4(-1, -1, -1, -1);
+    nxt[r].lk = make_int4(-1, -1, -1, -1);
+  }
+  if (compute) {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      cur[r].lk = load_link(0, r);
+      pin_reg(cur[r].lk);
+      if (!link_valid(0, r)) cur[r].lk.x = -1;
+      load_plane(0, r, cur[r]);
+      nxt[r].lk = load_link(min(1, np - 1), r);
+    }
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      pin_regs(cur[r]);
+      pin_reg(nxt[r].lk);
+      if (np < 2 || !link_valid(1, r)) nxt[r].lk.x = -1;
+    }
+    stage_plane(cur[0]);
+  }
+
+  // Compute and store waves run separate loops with the same barriers per
+  // plane (a workgroup barrier counts waves, not program locations).
+  // Inside the compute loop nothing branches around the loads or between
+  // them and their waits, so no load is awaited early.
+  if (compute) {
+    for (int pp = 0; pp < np; ++pp) {
+      int4 lk2[CPT];
+      const T *rd = lds + (DBUF ? ((pp + 1) & 1) : 0) * NS * maxp;  // previous plane
+      T *wr = lds + (DBUF ? (pp & 1) : 0) * NS * maxp;
+      T res[DBUF ? 1 : CPT][NS];  // single buffer: results held until every read is done
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        // part of the right-hand side independent of the sweep: forward,
+        // the prepared right-hand side itself (f~ = N^{-1} f, or f~ +
+        // sigma_s G u formed by the scatter GEMM); adjoint v = f + sigma_s N s
+        if (r > 0) stage_plane(cur[r]);
+        T v[NS], sv[NS];
+        read_cell(v, sv);
+        if (!ADJ && HAS_S) {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) v[b] += T(cur[r].ss) * sv[b];
+        } else if (ADJ && HAS_S) {
+          mass_shape<T, DIM, false>(sv);
+          const T fs = T(cur[r].ss) * T(a.g.vol);
+#pragma unroll
+          for (int b = 0; b < NS; ++b) v[b] += fs * sv[b];
+        }
+        if (r == 0) {
+          // the next plane's loads, in flight during this plane's work
+          // (past the last plane the last one is loaded again, unused)
+#pragma unroll
+          for (int r2 = 0; r2 < CPT; ++r2) {
+            load_plane(min(pp + 1, np - 1), r2, nxt[r2]);
+            lk2[r2] = load_link(min(pp + 2, np - 1), r2);
+          }
+        }
+        // neighbour traces from LDS: forward, the upwind neighbour's
+        // outflow face; adjoint, the downwind neighbour's inflow face
+        // (cells without a neighbour, or lanes without a cell, read
+        // position 0 and drop it)
+        const int nbp[3] = {cur[r].lk.y, cur[r].lk.z, cur[r].lk.w};
+        T tr[DIM][NS / 2];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int fl = (FLIP >> d) & 1;
+          const int nbit = ADJ ? (fl ? 1 : 0) : (fl ? 0 : 1);
+          const int q = nbp[d] >= 0 ? nbp[d] : 0;
+#pragma unroll
+          for (int t = 0; t < NS / 2; ++t) {
+            const T x = rd[insert_bit(t, d, nbit) * maxp + q];  // may be uninitialised: select, not scale
+            tr[d][t] = nbp[d] >= 0 ? x : T(0);
+          }
+        }
+        if (!ADJ) {
+          // inflow: 4 c on the own inflow face, -2 c on the opposite face
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const int own0 = (FLIP >> d) & 1;
+            const T c4 = T(4) * c[d], c2 = T(2) * c[d];
+#pragma unroll
+            for (int t = 0; t < NS / 2; ++t) {
+              v[insert_bit(t, d, own0)] += c4 * tr[d][t];
+              v[insert_bit(t, d, 1 - own0)] -= c2 * tr[d][t];
+            }
+          }
+        } else {
+          // outflow coupling a_xi (face mass) on the own outflow face
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const int own1 = ((FLIP >> d) & 1) ? 0 : 1;
+            mass_shape<T, DIM - 1, false>(tr[d]);
+            T hs = av[d];
+#pragma unroll
+            for (int e = 0; e < DIM; ++e)
+              if (e != d) hs *= T(a.g.h[e]);
+#pragma unroll
+            for (int t = 0; t < NS / 2; ++t) v[insert_bit(t, d, own1)] += hs * tr[d][t];
+          }
+        }
+        oriented_solve<T, DIM, ADJ, FLIP>(v, mc, T(cur[r].st));
+        if (ADJ) {
+          mass_shape<T, DIM, true>(v);
+          const T iv = T(1.0 / a.g.vol);
+#pragma unroll
+          for (int b = 0; b < NS; ++b) v[b] *= iv;
+        }
+        if (DBUF) {
+          // the plane goes to the other buffer: write at once
+          if (cur[r].lk.x >= 0) {
+#pragma unroll
+            for (int b = 0; b < NS; ++b) wr[b * maxp + tid + r * tc] = v[b];
+            jbuf[(pp & 1) * maxp + tid + r * tc] = (int)flipped_cell(cur[r].lk.x, FLIP, a.g);
+          }
+        } else {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) res[DBUF ? 0 : r][b] = v[b];
+        }
+      }
+      if (!DBUF) {
+        // single buffer: every read of the previous plane must be done first
+        lds_barrier();
+#pragma unroll
+        for (int r = 0; r < CPT; ++r)
+          if (cur[r].lk.x >= 0) {
+#pragma unroll
+            for (int b = 0; b < NS; ++b) wr[b * maxp + tid + r * tc] = res[DBUF ? 0 : r][b];
+            jbuf[tid + r * tc] = (int)flipped_cell(cur[r].lk.x, FLIP, a.g);
+          }
+      }
+      lds_barrier();  // the plane is complete in LDS
+      // the next plane's loads are awaited only now, after the barriers
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        pin_regs(nxt[r]);
+        pin_reg(lk2[r]);
+      }
+      stage_plane(nxt[0]);
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        if (pp + 2 >= np || !link_valid(pp + 2, r)) lk2[r].x = -1;
+        cur[r] = nxt[r];
+        nxt[r].lk = lk2[r];
+      }
+    }
+  } else {
+    // store waves: chunk lane / CPI of cell CPI i + lane % CPI of each
+    // group of 64 cells, whole cells per access
+    const int ch = lane / CPI;
+    for (int pp = 0; pp < np; ++pp) {
+      if (!DBUF) lds_barrier();
+      lds_barrier();
+      const int p = plane_of(pp);
+      const int n = off[p + 1] - off[p];
+      const T *pb = lds + (DBUF ? (pp & 1) : 0) * NS * maxp;
+      const int *jb = jbuf + (DBUF ? (pp & 1) : 0) * maxp;
+      for (int base = (tid - tc) / 64 * CPI; base < n; base += (NT - tc) / 64 * CPI) {
+        const int q = base + lane % CPI;
+        if (q < n) {
+          T w[EPC];
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) w[e] = pb[(ch * EPC + e) * maxp + q];
+          *reinterpret_cast<float4 *>(uk + (long long)jb[q] * NS + ch * EPC) = *reinterpret_cast<float4 *>(w);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int DIM, bool ADJ, bool HAS_S, bool DBUF, bool PIN, int CPT, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_lds(SweepArgs<T> a, int tc) {
   extern __shared__ __align__(16) unsigned char sweep_smem[];
   constexpr int NS = 1 << DIM;
   constexpr int Q = NS * (int)sizeof(T) / 16;
@@ -520,16 +789,22 @@ __global__ __launch_bounds__(kSweepLdsThreads) void k_sweep_lds(SweepArgs<T> a, 
   for (int i = threadIdx.x; i <= a.pl.nplanes; i += blockDim.x) off[i] = a.pl.off[i];
   __syncthreads();
   const int k = blockIdx.x;
+#define TR_SWEEP_LDS(F)                                                                     \
+  if constexpr (CPT == 1)                                                                   \
+    sweep_lds_body1<T, DIM, ADJ, HAS_S, DBUF, PIN, F>(a, k, lds, jbuf, off, stage, tc);     \
+  else                                                                                      \
+    sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, F, CPT, NT>(a, k, lds, jbuf, off, stage, tc)
   switch (a.ord[k].flip) {
-    case 0: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 0>(a, k, lds, jbuf, off, stage, tc); break;
-    case 1: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 1>(a, k, lds, jbuf, off, stage, tc); break;
-    case 2: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 2>(a, k, lds, jbuf, off, stage, tc); break;
-    case 3: sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 3>(a, k, lds, jbuf, off, stage, tc); break;
-    case 4: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 4>(a, k, lds, jbuf, off, stage, tc); break;
-    case 5: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 5>(a, k, lds, jbuf, off, stage, tc); break;
-    case 6: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 6>(a, k, lds, jbuf, off, stage, tc); break;
-    default: if (DIM == 3) sweep_lds_body<T, DIM, ADJ, HAS_S, DBUF, PIN, 7>(a, k, lds, jbuf, off, stage, tc); break;
+    case 0: TR_SWEEP_LDS(0); break;
+    case 1: TR_SWEEP_LDS(1); break;
+    case 2: TR_SWEEP_LDS(2); break;
+    case 3: TR_SWEEP_LDS(3); break;
+    case 4: if (DIM == 3) TR_SWEEP_LDS(4); break;
+    case 5: if (DIM == 3) TR_SWEEP_LDS(5); break;
+    case 6: if (DIM == 3) TR_SWEEP_LDS(6); break;
+    default: if (DIM == 3) TR_SWEEP_LDS(7); break;
   }
+#undef TR_SWEEP_LDS
 }
 
 // Cross sections per orientation in cell-list order (coalesced reads in
@@ -2211,44 +2486,89 @@ int grid_for(long long n, int block = kBlock) {
 }  // namespace
 
 // ------------------------------------------------------------- launchers
-// LDS sweep: compute waves cover the largest plane (rounded up to whole
-// waves), the remaining waves of the 1024-thread workgroup store; needs at
-// least one store wave and at most 160 KB of LDS.
+// LDS sweep: the compute lanes hold CPT cells of a plane each (cells
+// tid + r tc), the compute waves cover the largest plane, the remaining
+// waves of the NT-thread workgroup store; at least one store wave and at
+// most 160 KB of LDS (staging, one or two plane buffers, plane offsets).
+// Configurations in order of preference: one cell per lane in 1024
+// threads; for 3-D FP32 planes beyond 960 cells two cells per lane (forward
+// sweeps without s; registers allow no more in 1024 threads), or four per
+// lane in 512 threads.  FP64 keeps one cell per lane: the register budget of
+// more, with the single plane buffer such planes leave room for, spills.
+struct LdsCfg {
+  int cpt = 0, nt = 0, tc = 0;
+  bool dbuf = false;
+  size_t lds = 0;
+};
+
+static bool lds_config(int tsize, int dim, const Planes &pl, bool has_s, LdsCfg &cfg) {
+  const int ns = 1 << dim;
+  const int cands[3][2] = {{1, 1024}, {2, 1024}, {4, 512}};
+  for (auto &cd : cands) {
+    const int cpt = cd[0], nt = cd[1];
+    if (cpt > 1 && (dim != 3 || tsize == 8)) continue;
+    if (cpt == 2 && has_s) continue;
+    const int tc = ((pl.max_plane + cpt - 1) / cpt + 63) / 64 * 64;
+    if (tc > nt - 64) continue;
+    const size_t stage = (size_t)(tc / 64) * (has_s ? 2 : 1) * 64 * tsize * ns;
+    const size_t plane = ((size_t)tsize * ns + sizeof(int)) * (size_t)pl.max_plane;
+    const size_t tail = sizeof(int) * (pl.nplanes + 1);
+    if (stage + plane + tail > 160 * 1024) continue;
+    cfg.cpt = cpt;
+    cfg.nt = nt;
+    cfg.tc = tc;
+    // two plane buffers (one barrier per plane) where they fit, else one
+    cfg.dbuf = stage + 2 * plane + tail <= 160 * 1024;
+    cfg.lds = stage + (cfg.dbuf ? 2 : 1) * plane + tail;
+    return true;
+  }
+  return false;
+}
+
+template <typename T, int DIM, bool ADJ, bool HAS_S, int CPT, int NT>
+static void launch_sweep_lds_cfg(const SweepArgs<T> &a, int n_ord, const LdsCfg &cfg, bool pin, hipStream_t st) {
+  auto fn = cfg.dbuf ? (pin ? k_sweep_lds<T, DIM, ADJ, HAS_S, true, !ADJ && !HAS_S, CPT, NT>
+                            : k_sweep_lds<T, DIM, ADJ, HAS_S, true, false, CPT, NT>)
+                     : (pin ? k_sweep_lds<T, DIM, ADJ, HAS_S, false, !ADJ && !HAS_S, CPT, NT>
+                            : k_sweep_lds<T, DIM, ADJ, HAS_S, false, false, CPT, NT>);
+  if (cfg.lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds) != hipSuccess)
+    throw std::runtime_error("LDS sweep: cannot reserve its shared memory");
+  hipLaunchKernelGGL(fn, dim3(n_ord), dim3(NT), cfg.lds, st, a, cfg.tc);
+}
+
 template <typename T, int DIM, bool ADJ, bool HAS_S>
 static bool launch_sweep_lds(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
-  const int tc = (a.pl.max_plane + 63) / 64 * 64;
-  if (tc > kSweepLdsThreads - 64 || !a.sig_pl) return false;
+  LdsCfg cfg;
+  if (!a.sig_pl || !lds_config((int)sizeof(T), DIM, a.pl, HAS_S, cfg)) return false;
   // whole-cell accesses are 16-byte vector loads and stores
   auto aligned = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
   if (!aligned(a.f) || !aligned(a.u) || (a.s && !aligned(a.s))) return false;
-  const size_t stage = (size_t)(tc / 64) * (HAS_S ? 2 : 1) * 64 * sizeof(T) * (1 << DIM);
-  const size_t plane = (sizeof(T) * (size_t)(1 << DIM) + sizeof(int)) * (size_t)a.pl.max_plane;
-  const size_t tail = sizeof(int) * (a.pl.nplanes + 1);
-  // two plane buffers (one barrier per plane) where they fit, else one
-  const bool dbuf = stage + 2 * plane + tail <= 160 * 1024;
-  const size_t lds = stage + (dbuf ? 2 : 1) * plane + tail;
-  if (lds > 160 * 1024) return false;
   // right-hand side in plane layout: forward sweeps without s only
   const bool pin = a.plane_in && !ADJ && !HAS_S;
   if (a.plane_in && !pin) throw std::runtime_error("plane-layout input needs a forward sweep without s");
-  auto fn = dbuf ? (pin ? k_sweep_lds<T, DIM, ADJ, HAS_S, true, !ADJ && !HAS_S>
-                        : k_sweep_lds<T, DIM, ADJ, HAS_S, true, false>)
-                 : (pin ? k_sweep_lds<T, DIM, ADJ, HAS_S, false, !ADJ && !HAS_S>
-                        : k_sweep_lds<T, DIM, ADJ, HAS_S, false, false>);
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return false;
-  hipLaunchKernelGGL(fn, dim3(n_ord), dim3(kSweepLdsThreads), lds, st, a, tc);
-  return true;
+  if (cfg.cpt == 1) {
+    launch_sweep_lds_cfg<T, DIM, ADJ, HAS_S, 1, 1024>(a, n_ord, cfg, pin, st);
+    return true;
+  }
+  if constexpr (DIM == 3 && sizeof(T) == 4) {
+    if (cfg.cpt == 2) {
+      if constexpr (!HAS_S) {
+        launch_sweep_lds_cfg<T, DIM, ADJ, HAS_S, 2, 1024>(a, n_ord, cfg, pin, st);
+        return true;
+      }
+    } else {
+      launch_sweep_lds_cfg<T, DIM, ADJ, HAS_S, 4, 512>(a, n_ord, cfg, pin, st);
+      return true;
+    }
+  }
+  throw std::runtime_error("internal: LDS sweep configuration without a kernel");
 }
 
 template <typename T>
 bool sweep_lds_fits(const Planes &pl, const Grid &g, bool has_s) {
-  const int tc = (pl.max_plane + 63) / 64 * 64;
-  if (tc > kSweepLdsThreads - 64) return false;
-  const size_t stage = (size_t)(tc / 64) * (has_s ? 2 : 1) * 64 * sizeof(T) * g.ns;
-  const size_t plane = (sizeof(T) * (size_t)g.ns + sizeof(int)) * (size_t)pl.max_plane;
-  return stage + plane + sizeof(int) * (pl.nplanes + 1) <= 160 * 1024;  // as launch_sweep_lds
+  LdsCfg cfg;
+  return lds_config((int)sizeof(T), g.dim, pl, has_s, cfg);
 }
 template bool sweep_lds_fits<double>(const Planes &, const Grid &, bool);
 template bool sweep_lds_fits<float>(const Planes &, const Grid &, bool);

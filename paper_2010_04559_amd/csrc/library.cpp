@@ -67,8 +67,9 @@ void mat3_mul(const double *a, const double *b, double *c) {
 struct DevLevel {
   int P = 0, A = 0, order = 0;
   // forward sweep inputs (f and the post-smoothing right-hand side) are
-  // kept in plane layout (see tr::SweepArgs::plane_in)
-  bool pin = false;
+  // kept in plane layout (see tr::SweepArgs::plane_in), per precision of
+  // the V-cycle
+  bool pin64 = false, pin32 = false;
   OrdInfo *ord = nullptr;
   double *w = nullptr, *winv = nullptr, *ipsi = nullptr;
   double *St64 = nullptr;      // canonical S~ (order of this level), A x A
@@ -86,7 +87,7 @@ struct DevLevel {
   // onto itself by the reflections of symR axes): Walsh-Hadamard blocks of
   // G, G^T and the canonical S~ ([2^symR][sym_nc][sym_ldb]) and the row map
   int symR = 0, sym_nc = 0, sym_ldb = 0;
-  int *urow = nullptr;
+  tr::OctMap om{};
   double *Bh64 = nullptr, *Bht64 = nullptr, *Bc64 = nullptr;
   float *Bh32 = nullptr, *Bht32 = nullptr, *Bc32 = nullptr;
   int *owner = nullptr;                    // level >= 1: owner patch on level l-1
@@ -152,7 +153,7 @@ struct TmpBuf {
   T *as() { return static_cast<T *>(p); }
 };
 
-enum { C_SWEEP = 0, C_SCATTER, C_TRANSFER, C_COARSE, C_APPLY, C_ORTH, C_OTHER, C_SWEEP_FINE, C_N };
+enum { C_SWEEP = 0, C_SCATTER, C_TRANSFER, C_COARSE, C_APPLY, C_ORTH, C_OTHER, C_SWEEP_FINE, C_SCATTER_OUTER, C_N };
 
 }  // namespace
 
@@ -172,7 +173,7 @@ struct tr_handle {
   std::vector<DevLevel> lv;
   double *Souter = nullptr;  // canonical S~ at the problem's order on the finest level
   double *Bouter = nullptr;  // its octant-group blocks (mesh with reflection structure), else null
-  int *outer_urow = nullptr;
+  tr::OctMap outer_om{};
   int outer_R = 0, outer_nc = 0, outer_ldb = 0;
   double *iom = nullptr;     // [A][3] int Omega^xi psi on the finest level
   double *dot_partial = nullptr, *dot_out = nullptr;
@@ -322,6 +323,33 @@ int octant_symmetry(const tr::HostAngular &ang, int l, std::vector<int> &urow, i
   }
   if (t != nc) return 0;
   return R;
+}
+
+// The kernel's form of the row map: cosets as runs of transformed rows,
+// canonical row = t + off[coset][i] (checked against urow).
+tr::OctMap oct_map(const std::vector<int> &urow, int R, int nc) {
+  tr::OctMap om{};
+  om.R = R;
+  om.nc = nc;
+  const int nchi = 1 << R;
+  // a new coset starts where the canonical row of pattern 0 jumps
+  int c = 0;
+  om.cstart[0] = 0;
+  for (int t = 1; t < nc; ++t)
+    if (urow[t] != urow[t - 1] + 1) {
+      if (++c >= 8) throw std::runtime_error("internal: octant row map with more than 8 cosets");
+      om.cstart[c] = t;
+    }
+  om.ncos = c + 1;
+  for (int k = om.ncos; k <= 8; ++k) om.cstart[k] = nc;
+  for (int k = 0; k < om.ncos; ++k)
+    for (int i = 0; i < nchi; ++i) om.off[k][i] = urow[(size_t)i * nc + om.cstart[k]] - om.cstart[k];
+  for (int k = 0; k < om.ncos; ++k)
+    for (int t = om.cstart[k]; t < om.cstart[k + 1]; ++t)
+      for (int i = 0; i < nchi; ++i)
+        if (urow[(size_t)i * nc + t] != t + om.off[k][i]) throw std::runtime_error("internal: octant row map");
+  if (om.ncos > (8 >> R)) throw std::runtime_error("internal: octant row map cosets");
+  return om;
 }
 
 // Whether the A x A matrix M has the octant-group structure of urow:
@@ -536,8 +564,8 @@ void build(tr_handle *h, const tr_problem *p) {
     // forward sweep inputs in plane layout on the V-cycle's smoothing levels
     // when their sweeps run in the LDS kernel (one pre-smoothing sweep: the
     // restricted residual then needs no plane-layout input)
-    D.pin = l >= 1 && l < nlev && h->prob.nu_pre == 1 && tr::sweep_lds_fits<double>(h->pl, g, false) &&
-            tr::sweep_lds_fits<float>(h->pl, g, false);
+    D.pin64 = l >= 1 && l < nlev && h->prob.nu_pre == 1 && tr::sweep_lds_fits<double>(h->pl, g, false);
+    D.pin32 = l >= 1 && l < nlev && h->prob.nu_pre == 1 && tr::sweep_lds_fits<float>(h->pl, g, false);
     D.w = h->upload(H.w);
     D.winv = h->upload(winv);
     D.ipsi = h->upload(H.ipsi);
@@ -603,7 +631,7 @@ void build(tr_handle *h, const tr_problem *p) {
       D.symR = R;
       D.sym_nc = nc;
       D.sym_ldb = (nc + 3) / 4 * 4;
-      D.urow = h->upload(urow);
+      D.om = oct_map(urow, R, nc);
       auto up2 = [&](const std::vector<double> &M, double *&b64, float *&b32) {
         std::vector<double> B = octant_blocks(M, A, urow, R, nc, D.sym_ldb);
         b64 = h->upload(B);
@@ -632,16 +660,15 @@ void build(tr_handle *h, const tr_problem *p) {
         int ncc = 0;
         const int Ro = l >= 1 ? octant_symmetry(h->ang, l, ur, ncc) : 0;
         if (Ro && octant_structured(So, A, ur, Ro, ncc)) {
-          // the row map depends on the mesh only: share the level's when it has one
-          h->outer_urow = D.urow ? D.urow : h->upload(ur);
+          h->outer_om = oct_map(ur, Ro, ncc);
           h->outer_R = Ro;
           h->outer_nc = ncc;
           h->outer_ldb = (ncc + 3) / 4 * 4;
           h->Bouter = h->upload(octant_blocks(So, A, ur, Ro, ncc, h->outer_ldb));
         }
       }
-      if (h->Bouter && !h->outer_urow) {
-        h->outer_urow = D.urow;
+      if (h->Bouter && !h->outer_R) {
+        h->outer_om = D.om;
         h->outer_R = D.symR;
         h->outer_nc = D.sym_nc;
         h->outer_ldb = D.sym_ldb;
@@ -756,6 +783,7 @@ struct LevelBuf<double> {
   static const double *G(DevLevel &D, bool adj) { return adj ? D.Gt64 : D.G64; }
   static const double *St(DevLevel &D) { return D.St64; }
   static const double *Bh(DevLevel &D, bool adj) { return adj ? D.Bht64 : D.Bh64; }
+  static bool pin(const DevLevel &D) { return D.pin64; }
   static const double *Bc(DevLevel &D) { return D.Bc64; }
 };
 template <>
@@ -770,6 +798,7 @@ struct LevelBuf<float> {
   static const float *G(DevLevel &D, bool adj) { return adj ? D.Gt32 : D.G32; }
   static const float *St(DevLevel &D) { return D.St32; }
   static const float *Bh(DevLevel &D, bool adj) { return adj ? D.Bht32 : D.Bh32; }
+  static bool pin(const DevLevel &D) { return D.pin32; }
   static const float *Bc(DevLevel &D) { return D.Bc32; }
 };
 
@@ -785,7 +814,7 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   a.ord = h->lv[l].ord;
   a.pl = h->pl;
   a.g = h->g;
-  a.plane_in = !adj && h->lv[l].pin;
+  a.plane_in = !adj && (sizeof(T) == 8 ? h->lv[l].pin64 : h->lv[l].pin32);
   const bool fine = l == h->top();
   h->sweep_dofs += (double)h->lv[l].A * (double)h->g.S;
   tbegin(h, fine ? C_SWEEP_FINE : C_SWEEP);
@@ -1067,7 +1096,7 @@ void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t 
   if (D.symR) {
     // octant-group blocks (split-BF16 products are not used on these levels)
     tbegin(h, C_SCATTER);
-    tr::launch_gemm_oct<T>(LevelBuf<T>::Bh(D, adj), D.sym_ldb, u, y, D.urow, D.symR, D.sym_nc, (int)h->g.S, st, bias,
+    tr::launch_gemm_oct<T>(LevelBuf<T>::Bh(D, adj), D.sym_ldb, u, y, D.om, (int)h->g.S, st, bias,
                            scale_sn ? h->sig_s : nullptr, h->g.ns, rord ? h->pos_pl : nullptr, rord);
     tend(h);
     return;
@@ -1110,7 +1139,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   T *s_prev = nullptr;
   for (int it = 1; it < nu_pre; ++it) {
     if (!adj) {
-      level_scatter<T>(h, l, adj, u, sa, st, true, f, D.pin);
+      level_scatter<T>(h, l, adj, u, sa, st, true, f, LevelBuf<T>::pin(D));
       do_sweep<T>(h, l, sa, nullptr, u, adj, st);
     } else {
       level_scatter<T>(h, l, adj, u, sa, st);
@@ -1131,7 +1160,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
                                    adj, h->g, st);
   else
     tr::launch_restrict<T, T>(sa, s_prev, LevelBuf<T>::f(Dc), adj ? D.Ra : D.Ru, D.first_child, D.n_child, Dc.P,
-                              h->sig_s, adj, h->g, st, !adj && Dc.pin ? h->pos_pl : nullptr, Dc.ord);
+                              h->sig_s, adj, h->g, st, !adj && LevelBuf<T>::pin(Dc) ? h->pos_pl : nullptr, Dc.ord);
   tend(h);
   if (l - 1 == 0)
     do_coarse(h, Dc.f64, Dc.u64, h->prob.nu_coarse, adj, st);
@@ -1145,7 +1174,7 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   tend(h);
   for (int it = 0; it < nu_post; ++it) {
     if (!adj) {
-      level_scatter<T>(h, l, adj, u, sa, st, true, f, D.pin);
+      level_scatter<T>(h, l, adj, u, sa, st, true, f, LevelBuf<T>::pin(D));
       do_sweep<T>(h, l, sa, nullptr, u, adj, st);
     } else {
       level_scatter<T>(h, l, adj, u, sa, st);
@@ -1164,7 +1193,7 @@ void convert_in(tr_handle *h, int level, bool adj, const Tin *r, Tout *f, hipStr
   if (adj)
     tr::launch_convert<Tin, Tout>(r, f, D.P, h->g.S, nullptr, nullptr, st, scale);
   else
-    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st, D.pin ? h->pos_pl : nullptr, D.ord,
+    tr::launch_convert_minv<Tin, Tout>(r, f, D.P, h->g, nullptr, D.winv, st, LevelBuf<Tout>::pin(D) ? h->pos_pl : nullptr, D.ord,
                                        scale);
 }
 
@@ -1228,8 +1257,7 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
 void outer_scatter(tr_handle *h, const double *x, double *t, hipStream_t st) {
   DevLevel &D = h->lv[h->top()];
   if (h->Bouter)
-    tr::launch_gemm_oct<double>(h->Bouter, h->outer_ldb, x, t, h->outer_urow, h->outer_R, h->outer_nc, (int)h->g.S,
-                                st);
+    tr::launch_gemm_oct<double>(h->Bouter, h->outer_ldb, x, t, h->outer_om, (int)h->g.S, st);
   else
     tr::launch_gemm<double>(h->Souter, x, t, D.A, (int)h->g.S, D.A, st);
 }
@@ -1237,7 +1265,7 @@ void outer_scatter(tr_handle *h, const double *x, double *t, hipStream_t st) {
 // y = A x (adj: A^T x), canonical FP64 on the finest level
 void apply_A(tr_handle *h, bool adj, const double *x, double *y, hipStream_t st) {
   DevLevel &D = h->lv[h->top()];
-  tbegin(h, C_SCATTER);
+  tbegin(h, C_SCATTER_OUTER);
   outer_scatter(h, x, h->tmp, st);
   tend(h);
   tbegin(h, C_APPLY);
@@ -1469,6 +1497,8 @@ void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
   s->n_sweep = s->n_scatter = s->n_coarse = 0;
   s->ms_sweep_finest = 0;
   s->n_sweep_finest = 0;
+  s->ms_scatter_outer = 0;
+  s->n_scatter_outer = 0;
   if (!h->timer) return;
   for (auto &r : h->timer->recs) {
     float ms = 0;
@@ -1477,6 +1507,9 @@ void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
       case C_SWEEP: s->ms_sweep += ms; s->n_sweep++; break;
       case C_SWEEP_FINE: s->ms_sweep += ms; s->n_sweep++; s->ms_sweep_finest += ms; s->n_sweep_finest++; break;
       case C_SCATTER: s->ms_scatter += ms; s->n_scatter++; break;
+      case C_SCATTER_OUTER:
+        s->ms_scatter += ms; s->n_scatter++; s->ms_scatter_outer += ms; s->n_scatter_outer++;
+        break;
       case C_TRANSFER: s->ms_transfer += ms; break;
       case C_COARSE: s->ms_coarse += ms; s->n_coarse++; break;
       case C_APPLY: s->ms_apply += ms; break;
@@ -1602,6 +1635,8 @@ int tr_info(const tr_handle *h, tr_info_t *out) {
     out->scatter_k[l] = D.Kf;
   }
   out->outer_axes = h->Bouter ? h->outer_R : 0;
+  out->sweep_lds[0] = tr::sweep_lds_fits<double>(h->pl, h->g, false) ? 1 : 0;
+  out->sweep_lds[1] = tr::sweep_lds_fits<float>(h->pl, h->g, false) ? 1 : 0;
   return TR_OK;
 }
 
@@ -1814,7 +1849,7 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
       if (outer)
         outer_scatter(h, (const double *)phi, t, S(st));
       else if (D.symR)
-        tr::launch_gemm_oct<double>(D.Bc64, D.sym_ldb, (const double *)phi, t, D.urow, D.symR, D.sym_nc, Sn, S(st));
+        tr::launch_gemm_oct<double>(D.Bc64, D.sym_ldb, (const double *)phi, t, D.om, Sn, S(st));
       else
         tr::launch_gemm<double>(D.St64, (const double *)phi, t, D.A, Sn, D.A, S(st));
       tr::launch_scale_sn<double>(t, (double *)s, h->sig_s, D.A, h->g, S(st));
@@ -1823,7 +1858,7 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
       if (prec == TR_F32_SPLIT)
         tr::launch_gemm_bf16x3(split_of(h, D.St32, D.A, D.A, S(st)), (const float *)phi, t, D.A, Sn, D.A, S(st));
       else if (D.symR)
-        tr::launch_gemm_oct<float>(D.Bc32, D.sym_ldb, (const float *)phi, t, D.urow, D.symR, D.sym_nc, Sn, S(st));
+        tr::launch_gemm_oct<float>(D.Bc32, D.sym_ldb, (const float *)phi, t, D.om, Sn, S(st));
       else
         tr::launch_gemm<float>(D.St32, (const float *)phi, t, D.A, Sn, D.A, S(st));
       tr::launch_scale_sn<float>(t, (float *)s, h->sig_s, D.A, h->g, S(st));

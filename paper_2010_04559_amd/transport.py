@@ -112,6 +112,7 @@ class Transport:
         self.scatter_forms = [(names[info.scatter_form[l]], info.scatter_axes[l] or info.scatter_k[l])
                               for l in range(info.n_levels)]
         self.outer_axes = info.outer_axes
+        self.sweep_lds = {"f64": bool(info.sweep_lds[0]), "f32": bool(info.sweep_lds[1])}
         self.dev = torch.device("cuda")
 
     def close(self):
@@ -259,6 +260,11 @@ class Transport:
         _lib.check(self.lib.tr_time_sweep_kernel(self.h, level, _lib.TR_F64 if prec == "f64" else _lib.TR_F32,
                                                  reps, ctypes.byref(ms), _stream()))
         return ms.value
+
+    def sweep_kernel_name(self, level=None, prec="f64"):
+        """Name of the forward-sweep kernel the library launches."""
+        t = "double" if prec == "f64" else "float"
+        return ("k_sweep_lds<%s,%d>" if self.sweep_lds[prec] else "k_sweep<%s,%d>") % (t, self.prob.dim)
 
     def scatter_flops(self, level=None, outer=False):
         """Multiply-add flops per application of a level's scatter product as

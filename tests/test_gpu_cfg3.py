@@ -1,0 +1,134 @@
+"""GPU checks of the 48^3 precision problem (512 patches, order 32, MG orders
+8, 8, 8, 32) in the launch configurations the benchmark times, against the
+oracle on sampled blocks:
+
+* finest-level transport sweeps (1536 ordinates, diagonal planes of up to
+  1728 cells: the FP32 sweep keeps the previous plane in LDS with two cells
+  per lane, the FP64 sweep runs the register kernel): the block equation of
+  sampled (cell, patch) blocks, from the oracle's block matrices of those
+  patches;
+* the scatter products in octant-block form: the problem operator (order
+  32, A = 1536) and the level-2 multigrid operator (order 8, A = 384) on
+  sampled cells and patches, against rows of S~ by the addition theorem;
+* the solves: FP64 and FP32-preconditioned GMRES converge, their solutions
+  agree, and the explicit residual through the operator is below 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle import angular as ang, spatial as sp, transport as otr
+from paper_2010_04559_amd import inputs
+from gpu_util import rel, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    import gc
+    from paper_2010_04559_amd.transport import Transport
+    # the problem needs most of the device: release what earlier tests hold
+    gc.collect()
+    torch_mod().cuda.empty_cache()
+    prob = inputs.config3()
+    print("case", prob.name, flush=True)
+    tr = Transport(prob)
+    grid = sp.Grid(prob.dim, prob.n, prob.length)
+    mesh = ang.AngularMesh.uniform(prob.angular.base_level)
+    rng = np.random.default_rng(31)
+    leaves = mesh.leaves()
+    qs = sorted(set(int(q) for q in rng.choice(len(leaves), 12, replace=False)) | {0, 255, 511})
+    cells = sorted(set(int(j) for j in rng.choice(grid.C, 40, replace=False)) | {0, grid.C - 1, grid.C // 2})
+    yield prob, tr, grid, mesh, qs, cells
+    tr.close()
+    torch_mod().cuda.empty_cache()
+
+
+def _sweep_residual(prob, grid, patch, xq, gq, cells):
+    """max over cells of |(L x - g)_(j,q)| / |g_(j,q)| with the oracle's block
+    matrices of patch q (the sweep must invert L exactly); xq, gq: the
+    patch's three angular rows (3, S)."""
+    lv = otr.Level(grid, [patch], prob.sigma_t, prob.sigma_s, [1.0])
+    xb = xq.reshape(3, grid.C, grid.ns)
+    gb = gq.reshape(3, grid.C, grid.ns)
+    blk = lambda v, j: v[:, j, :].reshape(-1)
+    worst = 0.0
+    for j in cells:
+        r = lv.K_stream[0] @ blk(xb, j) + lv.sigma_t[j] * (lv.K_mass[0] @ blk(xb, j))
+        for xi, side, Cm in lv.couple[0]:
+            nb = lv.nbr[(xi, side)][j]
+            if nb >= 0:
+                r = r + Cm @ blk(xb, nb)
+        r = r - blk(gb, j)
+        worst = max(worst, np.abs(r).max() / np.abs(blk(gb, j)).max())
+    return worst
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cfg3_sweep_blocks(cfg3, prec):
+    prob, tr, grid, mesh, qs, cells = cfg3
+    torch = torch_mod()
+    L = tr.nlev - 1
+    A = 3 * tr.patches[L]
+    leaves = mesh.leaves()
+    dt = torch.float64 if prec == "f64" else torch.float32
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    g_dev = torch.randn(A * grid.S, dtype=dt, device="cuda", generator=gen)
+    phi = tr.sweep(L, g_dev)
+    # only the sampled patches' rows come back to the host
+    rows = torch.tensor([3 * q + m for q in qs for m in range(3)], device="cuda")
+    gs = g_dev.view(A, grid.S)[rows].double().cpu().numpy()
+    ps = phi.view(A, grid.S)[rows].double().cpu().numpy()
+    del phi, g_dev
+    tol = 1e-11 if prec == "f64" else 1e-4
+    for k, q in enumerate(qs):
+        worst = _sweep_residual(prob, grid, leaves[q], ps[3 * k:3 * k + 3], gs[3 * k:3 * k + 3], cells)
+        assert worst < tol, (q, worst)
+
+
+def test_cfg3_scatter_outer_and_level2(cfg3):
+    """Octant-block products against S~ rows by the addition theorem
+    (convention-free), on sampled patches and cells."""
+    prob, tr, grid, mesh, qs, cells = cfg3
+    torch = torch_mod()
+    assert tr.scatter_forms[1:] == [("octant", 3)] * 3 and tr.outer_axes == 3
+    for level, outer, order in ((tr.nlev - 1, True, prob.order), (2, False, prob.mg_orders[2])):
+        leaves = mesh.levels()[level]
+        A = 3 * len(leaves)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(11 + level)
+        x = torch.randn(A * grid.S, dtype=torch.float64, device="cuda", generator=gen)
+        s = tr.scatter(level, x, outer=outer)
+        cols = torch.tensor([j * grid.ns + i for j in cells for i in range(grid.ns)], device="cuda")
+        xs = x.view(A, grid.S)[:, cols].cpu().numpy().reshape(A, len(cells), grid.ns)
+        ss = s.view(A, grid.S)[:, cols].cpu().numpy().reshape(A, len(cells), grid.ns)
+        del x, s
+        mom = prob.moments(order)
+        # addition-theorem rows cost tens of seconds each at order 32
+        for q in ([qs[0], qs[len(qs) // 2]] if outer else qs[:4]):
+            qq = q % len(leaves)
+            rows = ang.scatter_rows_addition(leaves, mom, qq)
+            for k, j in enumerate(cells):
+                ref = prob.sigma_s[j] * (rows @ xs[:, k, :]) @ grid.N.T
+                assert rel(ss[3 * qq:3 * qq + 3, k, :], ref) < 1e-10, (level, qq, j)
+
+
+def test_cfg3_solves(cfg3):
+    prob, tr, grid, mesh, qs, cells = cfg3
+    torch = torch_mod()
+    b = tr.rhs()
+    xm, stm = tr.solve(b, mode="mixed")
+    assert stm["converged"] == 1 and stm["flexible"] == 32 and stm["iters"] <= 11
+    x, st = tr.solve(b)
+    assert st["converged"] == 1 and st["iters"] <= 11
+    # |xm - x| in chunks (no full-size temporary next to the solver's workspace)
+    d2 = 0.0
+    for i in range(0, x.numel(), 1 << 27):
+        t = xm[i:i + (1 << 27)] - x[i:i + (1 << 27)]
+        d2 += float(torch.dot(t, t))
+    assert d2 ** 0.5 / float(torch.linalg.norm(x)) < 1e-7
+    del xm
+    y = tr.apply(x)
+    y -= b
+    assert float(torch.linalg.norm(y) / torch.linalg.norm(b)) < 1e-8
