@@ -439,7 +439,7 @@ __device__ __forceinline__ int oct_row(const OctMap &om, int t, int i) {
   return t + off;
 }
 
-template <typename T, int R, int BM, int BN, int BK, int WPE>
+template <typename T, int R, int BM, int BN, int BK, int WPE, bool DB, bool ALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_oct(
     const T *__restrict__ Bh, int ldb, const T *__restrict__ U, T *__restrict__ C, OctMap om, int nc, int N,
     int mblocks, int nblocks, const T *__restrict__ bias, const double *__restrict__ colscale, int cell,
@@ -451,13 +451,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int PAD = 2;
-  constexpr int BPAIRS = BK * BN / VN;             // loader threads of U: one (k, column vector) each
-  constexpr int ATHREADS = 256 - BPAIRS;           // the others stage the A tiles
+  // U loader threads: one (k, column vector) each; the A tiles are staged
+  // by the other threads, or (ALL) by every thread
+  constexpr int BPAIRS = BK * BN / VN;
+  constexpr int ATHREADS = ALL ? 256 : 256 - BPAIRS;
   constexpr int AVT = NCHI * BM * BK / VN;         // A vectors per slice
   constexpr int AV = (AVT + ATHREADS - 1) / ATHREADS;
-  static_assert(BK % 4 == 0 && BK % VN == 0 && BPAIRS <= 128, "tile shape");
-  __shared__ T As[2][NCHI][BK][BM + PAD];
-  __shared__ T Bs[2][NCHI][BK][BN + PAD];
+  static_assert(BK % 4 == 0 && BK % VN == 0 && BPAIRS <= (ALL ? 256 : 128), "tile shape");
+  constexpr int NBUF = DB ? 2 : 1;
+  __shared__ T As[NBUF][NCHI][BK][BM + PAD];
+  __shared__ T Bs[NBUF][NCHI][BK][BN + PAD];
   __shared__ int pos_s[8][BN / 4 + 1];
 
   const int b = blockIdx.x;
@@ -483,6 +486,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   V rx[NCHI];   // U rows of one (k, column vector), loader threads
   V ra[AV];     // A vectors, staging threads
   const bool loader = tid < BPAIRS;
+  const bool aload = ALL || !loader;
   const int bk = tid / (BN / VN), bnv = (tid % (BN / VN)) * VN;
   auto load = [&](int k0) {
     if (loader) {
@@ -503,8 +507,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
           for (int e = 0; e < VN; ++e) rx[i].v[e] = T(0);
         }
       }
-    } else {
-      const int idx = tid - BPAIRS;
+    }
+    if (aload) {
+      const int idx = ALL ? tid : tid - BPAIRS;
 #pragma unroll
       for (int q = 0; q < AV; ++q) {
         const int v = idx + ATHREADS * q;
@@ -540,8 +545,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       for (int j = 0; j < NCHI; ++j)
 #pragma unroll
         for (int e = 0; e < VN; ++e) Bs[buf][j][bk][bnv + e] = rx[j].v[e];
-    } else {
-      const int idx = tid - BPAIRS;
+    }
+    if (aload) {
+      const int idx = ALL ? tid : tid - BPAIRS;
 #pragma unroll
       for (int q = 0; q < AV; ++q) {
         const int v = idx + ATHREADS * q;
@@ -579,17 +585,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       pos_s[fl][c] = pos[(long long)fl * ncells + min(n0 / cell + c, ncells - 1)];
     }
   }
+  // DB: two LDS buffers, the next slice stored during the MFMAs, one
+  // barrier per slice; else one buffer, the next slice's loads in flight
+  // during the MFMAs, two barriers per slice
   load(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = 0; k0 < nc; k0 += BK) {
-    const bool more = k0 + BK < nc;
-    if (more) load(k0 + BK);
-    mma_slice(buf);
-    if (more) store(buf ^ 1);
+  if (DB) {
+    store(0);
     __syncthreads();
-    buf ^= 1;
+    int buf = 0;
+    for (int k0 = 0; k0 < nc; k0 += BK) {
+      const bool more = k0 + BK < nc;
+      if (more) load(k0 + BK);
+      mma_slice(buf);
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    for (int k0 = 0; k0 < nc; k0 += BK) {
+      store(0);
+      __syncthreads();
+      if (k0 + BK < nc) load(k0 + BK);
+      mma_slice(0);
+      __syncthreads();
+    }
   }
   // inverse transform and store
 #pragma unroll
@@ -655,14 +674,14 @@ void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t 
     launch_shape<T, 128, 128, 16, true, 0>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
 }
 // Octant-group product (see k_gemm_oct): 256 threads, LDS double buffering.
-template <typename T, int R, int BM, int BN, int BK, int WPE>
+template <typename T, int R, int BM, int BN, int BK, int WPE, bool DB, bool ALL>
 static void launch_oct_shape(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, int nc, int N, hipStream_t st,
                              const T *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   const int mblocks = (nc + BM - 1) / BM;
   const int nblocks = (int)(((long long)N + BN - 1) / BN);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
   const long long grid = (long long)mblocks * nb_pad;
-  hipLaunchKernelGGL((k_gemm_oct<T, R, BM, BN, BK, WPE>), dim3((unsigned)grid), dim3(256), 0, st, Bh, ldb, U, C, om,
+  hipLaunchKernelGGL((k_gemm_oct<T, R, BM, BN, BK, WPE, DB, ALL>), dim3((unsigned)grid), dim3(256), 0, st, Bh, ldb, U, C, om,
                      nc, N, mblocks, nblocks, bias, colscale, cell, pos, rord, (long long)(N / cell));
 }
 
@@ -671,26 +690,27 @@ void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, i
                      const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
   const int nc = om.nc;
-#define TR_OCT(BM, BN, BK)                                                                                        \
+#define TR_OCT(BM, BN, BK, DB, ALL)                                                                              \
   switch (om.R) {                                                                                                 \
-    case 1: launch_oct_shape<T, 1, BM, BN, BK, 2>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+    case 1:                                                                                                       \
+      launch_oct_shape<T, 1, BM, BN, BK, 2, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
       break;                                                                                                      \
-    case 2: launch_oct_shape<T, 2, BM, BN, BK, 2>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+    case 2:                                                                                                       \
+      launch_oct_shape<T, 2, BM, BN, BK, 2, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
       break;                                                                                                      \
-    case 3: launch_oct_shape<T, 3, BM, BN, BK, 2>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+    case 3:                                                                                                       \
+      launch_oct_shape<T, 3, BM, BN, BK, 2, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
       break;                                                                                                      \
     default: throw std::runtime_error("octant-group GEMM: 1 to 3 reflected axes");                                \
   }
-  // shapes measured on MI355X (nc = 192 and 48, N = 884736, three axes):
-  // FP64 32 x 64 x 4 17.2 ms / 32 x 32 x 8 2.14 ms, FP32 32 x 64 x 8 8.8 / 1.2 ms
+  // shapes measured on MI355X (three axes, N = 884736): FP64 32 x 64 x 8
+  // with one LDS buffer and every thread loading, 14.5 ms at nc = 192 (36
+  // TF/s) and 1.9 ms at nc = 48; FP32 32 x 64 x 8 double-buffered, 9.0 and
+  // 1.2 ms
   if constexpr (sizeof(T) == 8) {
-    if (nc > 64) {
-      TR_OCT(32, 64, 4)
-    } else {
-      TR_OCT(32, 32, 8)
-    }
+    TR_OCT(32, 64, 8, false, true)
   } else {
-    TR_OCT(32, 64, 8)
+    TR_OCT(32, 64, 8, true, false)
   }
 #undef TR_OCT
 }
