@@ -84,6 +84,9 @@ typedef struct {
   double cone_half_angle_deg;   /* ... for vertices strictly inside this cone     */
   int cone_extra_levels;        /* extra levels inside the cone (0 = none)        */
   int irregularity_closure;     /* 1: refine until neighbours differ <= 2 levels  */
+  int band_lmax;                /* > 0: the z-band rule of Section 5.5 instead of */
+                                /* uniform refinement (levels lmax .. lmax-4 by   */
+                                /* the largest vertex Omega_z: 0.97/0.9/0.8/0.6)  */
   const double *sigma_t;        /* [cells] total cross section (> 0)              */
   const double *sigma_s;        /* [cells] scatter cross section sigma_{s,0}      */
   int order;                    /* Legendre order L of the problem operator       */
@@ -246,6 +249,18 @@ int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, doub
  * TR_ERR_NOCONV (x and stats still written) at max_restarts. */
 int tr_gmres_solve(tr_handle *h, const double *b, double *x, const tr_solve_opts *opts,
                    tr_solve_stats *stats, tr_stream st);
+
+/* Solve A x = b with right-preconditioned BiCGStab from x = 0, the Krylov
+ * method of the paper (Section 3): per iteration two preconditioner and two
+ * operator applications; the recurrence residual is confirmed by the
+ * explicit residual ||b - A x|| / ||b|| < tol (a failed confirmation
+ * restarts the recurrences from it).  Iteration limit restart x
+ * (max_restarts + 1); opts->z_store is ignored.  FP64 throughout except the
+ * preconditioner per prec_mode (an FP32 preconditioner makes the method
+ * inexact; it receives unit-norm inputs).  stats->iters counts BiCGStab
+ * iterations.  TR_ERR_NOCONV at the limit (x and stats still written). */
+int tr_bicgstab_solve(tr_handle *h, const double *b, double *x, const tr_solve_opts *opts, tr_solve_stats *stats,
+                      tr_stream st);
 
 /* Detector-response gradient by the adjoint method: solves A^T lambda = w
  * with GMRES and the adjoint V-cycle, then per cell j

@@ -26,7 +26,7 @@ class TrProblem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("len", ctypes.c_double * 3),
                 ("ang_base_level", ctypes.c_int), ("cone_axis", ctypes.c_double * 3),
                 ("cone_half_angle_deg", ctypes.c_double), ("cone_extra_levels", ctypes.c_int),
-                ("irregularity_closure", ctypes.c_int), ("sigma_t", _dp), ("sigma_s", _dp),
+                ("irregularity_closure", ctypes.c_int), ("band_lmax", ctypes.c_int), ("sigma_t", _dp), ("sigma_s", _dp),
                 ("order", ctypes.c_int), ("moments", _dp), ("n_levels", ctypes.c_int),
                 ("mg_order", _ip), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("nu_coarse", ctypes.c_int), ("octant_order", ctypes.c_int * 8)]
@@ -88,6 +88,8 @@ SIGNATURES = {
     "tr_coarse_gs_noalloc": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "tr_mg_vcycle": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "tr_gmres_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.POINTER(TrSolveOpts), ctypes.POINTER(TrSolveStats), _vp]),
+    "tr_bicgstab_solve": (ctypes.c_int, [_h, _vp, _vp, ctypes.POINTER(TrSolveOpts), ctypes.POINTER(TrSolveStats),
+                                         _vp]),
     "tr_adjoint_grad": (ctypes.c_int, [_h, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(TrSolveOpts),
                                        ctypes.POINTER(TrSolveStats), _vp]),
     "tr_time_sweep_kernel": (ctypes.c_int, [_h, ctypes.c_int, ctypes.c_int, ctypes.c_int,

@@ -43,6 +43,14 @@ void split(std::vector<PatchNode> &t, int i) {
 }
 
 int required_level(const RefineSpec &s, const PatchNode &p) {
+  if (s.band_lmax > 0) {
+    // Section 5.5: bands of the largest vertex Omega_z, strict thresholds
+    double z = p.v[0].z;
+    for (int e = 1; e < 3; ++e) z = std::max(z, p.v[e].z);
+    const int lev = z > 0.97 ? s.band_lmax : z > 0.9 ? s.band_lmax - 1 : z > 0.8 ? s.band_lmax - 2
+                  : z > 0.6 ? s.band_lmax - 3 : s.band_lmax - 4;
+    return std::max(lev, 0);
+  }
   if (s.cone_extra_levels <= 0) return s.base_level;
   V3 ax = unit(s.cone_axis);
   double c = std::cos(s.cone_half_angle_deg * kPi / 180.0);
@@ -265,6 +273,10 @@ bool build_angular(const RefineSpec &spec, HostAngular &out, std::string &err) {
   if (spec.base_level < 0 || spec.base_level > 6 || spec.cone_extra_levels < 0 ||
       spec.base_level + spec.cone_extra_levels > 8) {
     err = "angular refinement levels out of range (base 0..6, base+extra <= 8)";
+    return false;
+  }
+  if (spec.band_lmax < 0 || spec.band_lmax > 8 || (spec.band_lmax > 0 && spec.cone_extra_levels > 0)) {
+    err = "z-band refinement: band_lmax in 0..8 (0 = off), not together with a cone";
     return false;
   }
   std::vector<PatchNode> &t = out.tree;

@@ -29,6 +29,11 @@ struct RefineSpec {
   double cone_half_angle_deg = 0;
   int cone_extra_levels = 0;
   bool closure = true;
+  // Section 5.5's z-band rule instead of the uniform level (0 = off): level
+  // band_lmax where the largest vertex Omega_z exceeds 0.97, one less above
+  // 0.9, two less above 0.8, three less above 0.6, four less elsewhere
+  // (at least 0)
+  int band_lmax = 0;
 };
 
 // One nested angular mesh T_l with everything the kernels need.

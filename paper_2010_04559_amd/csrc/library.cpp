@@ -438,6 +438,7 @@ void build(tr_handle *h, const tr_problem *p) {
   spec.cone_half_angle_deg = p->cone_half_angle_deg;
   spec.cone_extra_levels = p->cone_extra_levels;
   spec.closure = p->irregularity_closure != 0;
+  spec.band_lmax = p->band_lmax;
   if (spec.cone_extra_levels > 0 &&
       !(std::fabs(spec.cone_axis.x) + std::fabs(spec.cone_axis.y) + std::fabs(spec.cone_axis.z) > 0))
     throw ArgError{"cone axis must be nonzero"};
@@ -1488,6 +1489,110 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
   return TR_ERR_NOCONV;
 }
 
+// Right-preconditioned BiCGStab (the paper's Krylov method, Section 3) from
+// x = 0, van der Vorst's recurrences: per iteration two preconditioner
+// applications and two operator applications.  When the recurrence residual
+// falls below tol |b| the explicit residual b - A x decides; a failed test
+// restarts the recurrences from it.  Iteration limit: restart x (max_restarts
+// + 1), the GMRES budget.  FP32 preconditioners receive unit-norm inputs.
+int bicgstab(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
+             hipStream_t st) {
+  ensure_krylov(h, 7, TR_PREC_F64, TR_Z_RECOMPUTE);
+  const long long n = h->vec_len(h->top());
+  double *r = h->V[0], *rhat = h->V[1], *p = h->V[2], *v = h->V[3], *s = h->V[4], *t = h->V[5], *ph = h->V[6],
+         *sh = h->V[7];
+  const bool mixed = mixed_mode(o->prec_mode);
+  const long long max_iters = (long long)o->restart * (o->max_restarts + 1);
+  tr::launch_fill<double>(x, n, 0.0, st);
+  tbegin(h, C_ORTH);
+  const double bnorm = std::sqrt(dot(h, b, b, n, st));
+  tend(h);
+  stats->iters = stats->restarts = stats->converged = 0;
+  stats->rel_res = 0;
+  stats->flexible = 0;
+  if (bnorm == 0.0) {
+    stats->converged = 1;
+    return TR_OK;
+  }
+  auto prec = [&](const double *in, double *out) {
+    double sc = 1.0;
+    if (mixed) {
+      const double nn = std::sqrt(dot(h, in, in, n, st));
+      if (nn > 0) sc = 1.0 / nn;
+    }
+    precondition(h, o->prec_mode, adj, in, out, st, sc, 1.0 / sc);
+  };
+  HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  long long iters = 0;
+  while (iters < max_iters) {
+    HIPCHK(hipMemcpyAsync(rhat, r, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    tr::launch_fill<double>(p, n, 0.0, st);
+    tr::launch_fill<double>(v, n, 0.0, st);
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    while (iters < max_iters) {
+      tbegin(h, C_ORTH);
+      const double rho = dot(h, rhat, r, n, st);
+      tend(h);
+      if (rho == 0.0) break;
+      const double beta = (rho / rho_prev) * (alpha / omega);
+      tbegin(h, C_ORTH);
+      tr::launch_scal(n, beta, p, st);  // p = r + beta (p - omega v)
+      {
+        const double *xs[2] = {r, v};
+        const double cs2[2] = {1.0, -beta * omega};
+        tr::launch_multi_axpy(n, 2, xs, cs2, p, st);
+      }
+      tend(h);
+      prec(p, ph);
+      apply_A(h, adj, ph, v, st);
+      tbegin(h, C_ORTH);
+      alpha = rho / dot(h, rhat, v, n, st);
+      tr::launch_axpby(n, 1.0, r, -alpha, v, s, st);
+      const double sn = std::sqrt(dot(h, s, s, n, st));
+      tend(h);
+      ++iters;
+      if (sn / bnorm < o->tol) {
+        tbegin(h, C_ORTH);
+        tr::launch_axpy(n, alpha, ph, x, st);
+        tend(h);
+        std::swap(h->V[0], h->V[4]);
+        r = h->V[0];
+        s = h->V[4];
+        break;
+      }
+      prec(s, sh);
+      apply_A(h, adj, sh, t, st);
+      tbegin(h, C_ORTH);
+      const double ts = dot(h, t, s, n, st), tt = dot(h, t, t, n, st);
+      omega = tt > 0 ? ts / tt : 0.0;
+      {
+        const double *xs[2] = {ph, sh};
+        const double cs2[2] = {alpha, omega};
+        tr::launch_multi_axpy(n, 2, xs, cs2, x, st);
+      }
+      tr::launch_axpby(n, 1.0, s, -omega, t, r, st);
+      const double rn = std::sqrt(dot(h, r, r, n, st));
+      tend(h);
+      rho_prev = rho;
+      if (rn / bnorm < o->tol || omega == 0.0) break;
+    }
+    // acceptance by the explicit residual r = b - A x
+    apply_A(h, adj, x, t, st);
+    tbegin(h, C_ORTH);
+    tr::launch_axpby(n, 1.0, b, -1.0, t, r, st);
+    const double rel = std::sqrt(dot(h, r, r, n, st)) / bnorm;
+    tend(h);
+    stats->iters = (int)iters;
+    stats->rel_res = rel;
+    if (rel < o->tol) {
+      stats->converged = 1;
+      return TR_OK;
+    }
+    stats->restarts++;
+  }
+  return TR_ERR_NOCONV;
+}
+
 void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
   s->ms_total = ms_total;
   s->n_precond = (int)h->n_precond;
@@ -1968,7 +2073,7 @@ int tr_mg_vcycle(tr_handle *h, int prec_mode, int adjoint, const double *r, doub
 }
 
 static int solve_common(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opts *o,
-                        tr_solve_stats *stats, tr_stream st) {
+                        tr_solve_stats *stats, tr_stream st, bool bicg = false) {
   if (!h || !b || !x || !o || !stats) return fail(TR_ERR_ARG, "null argument");
   TR_CHECK_ALIGNED(b, x);
   if (o->restart < 1 || o->restart > 200 || o->max_restarts < 0 || !(o->tol > 0) || !valid_zstore(o->z_store))
@@ -1988,7 +2093,7 @@ static int solve_common(tr_handle *h, bool adj, const double *b, double *x, cons
     h->n_precond = 0;
     h->sweep_dofs = 0;
     HIPCHK(hipEventRecord(e0, S(st)));
-    int r = gmres(h, adj, b, x, o, stats, S(st));
+    int r = bicg ? bicgstab(h, adj, b, x, o, stats, S(st)) : gmres(h, adj, b, x, o, stats, S(st));
     HIPCHK(hipEventRecord(e1, S(st)));
     check_barrier(h, S(st));
     HIPCHK(hipEventSynchronize(e1));
@@ -2001,13 +2106,20 @@ static int solve_common(tr_handle *h, bool adj, const double *b, double *x, cons
     return r;
   });
   h->timer = nullptr;
-  if (rc == TR_ERR_NOCONV) g_err = "GMRES reached max_restarts before the tolerance";
+  if (rc == TR_ERR_NOCONV)
+    g_err = bicg ? "BiCGStab reached its iteration limit before the tolerance"
+                 : "GMRES reached max_restarts before the tolerance";
   return rc;
 }
 
 int tr_gmres_solve(tr_handle *h, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
                    tr_stream st) {
   return solve_common(h, false, b, x, o, stats, st);
+}
+
+int tr_bicgstab_solve(tr_handle *h, const double *b, double *x, const tr_solve_opts *o, tr_solve_stats *stats,
+                      tr_stream st) {
+  return solve_common(h, false, b, x, o, stats, st, true);
 }
 
 int tr_adjoint_grad(tr_handle *h, const double *w, const double *phi, double *lambda, double *grad_t, double *grad_s,

@@ -20,12 +20,18 @@ import numpy as np
 class AngularSpec:
     """Uniform refinement to ``base_level``; optionally ``extra_levels`` more
     inside a cone of ``cone_half_angle_deg`` around ``cone_axis`` with the
-    two-irregularity closure."""
+    two-irregularity closure; or (band_lmax > 0) the z-band rule of the
+    paper's pencil-beam study (levels band_lmax .. band_lmax - 4)."""
     base_level: int = 1
     cone_axis: Tuple[float, float, float] = (1.0, 0.0, 0.0)
     cone_half_angle_deg: float = 0.0
     extra_levels: int = 0
     closure: bool = True
+    band_lmax: int = 0
+
+    @property
+    def n_levels(self):
+        return (self.band_lmax if self.band_lmax > 0 else self.base_level + self.extra_levels) + 1
 
 
 @dataclass
@@ -70,14 +76,23 @@ class Problem:
     length: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     fd_cells: Optional[np.ndarray] = None
     extras: dict = field(default_factory=dict)
+    # Fokker-Planck-equivalent moments of order fp_N instead of HG (the
+    # paper's Section 5 workloads): sigma_{s,n} / sigma_{s,0} = 1 - n (n+1) /
+    # (N (N+1)) for n <= N, zero beyond
+    fp_N: Optional[int] = None
 
     @property
     def cells(self):
         return int(np.prod(self.n[:self.dim]))
 
     def moments(self, order=None):
-        """HG Legendre coefficients f_n = g^n, n <= order (plain truncation)."""
+        """Normalised Legendre coefficients f_n (sigma_{s,n} = sigma_s f_n),
+        n <= order: HG f_n = g^n (plain truncation), or the
+        Fokker-Planck-equivalent ratios when fp_N is set."""
         L = self.order if order is None else order
+        if self.fp_N is not None:
+            N = self.fp_N
+            return np.array([1.0 - k * (k + 1) / (N * (N + 1)) if k <= N else 0.0 for k in range(L + 1)])
         return np.array([self.hg_g ** k for k in range(L + 1)], dtype=np.float64)
 
     def with_sigma(self, sigma_t, sigma_s):
@@ -204,9 +219,49 @@ def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=Tru
     ss = c * st * rng.uniform(0.8, 1.0, C)
     q = rng.uniform(0.0, 1.0, C) if source else np.zeros(C)
     spec = angular if angular is not None else AngularSpec(level)
-    nlev = spec.base_level + spec.extra_levels + 1
+    nlev = spec.n_levels
     mg = mg_orders if mg_orders is not None else [order] * nlev
-    tag = f"ang{level}" if angular is None else f"cone{spec.base_level}+{spec.extra_levels}"
+    tag = (f"ang{level}" if angular is None else f"band{spec.band_lmax}" if spec.band_lmax
+           else f"cone{spec.base_level}+{spec.extra_levels}")
     return Problem(f"small-{dim}d-{n}-{tag}-L{order}-s{seed}", dim, nn, spec,
                    st, ss, g, order, mg, q, Inflow("iso", 0, 0, value=1.0) if inflow else None,
                    restart=restart)
+
+
+# ------------------------------------------------------ the paper's workloads
+
+def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_lmax=0, restart=20):
+    """The cube of the paper's Section 5 experiments: 5 x 5 x 5 cm, n^3
+    hexahedra (30^3 in the paper), vacuum boundaries, Fokker-Planck-
+    equivalent scatter moments of order N with transport cross section 1
+    (alpha = 1: sigma_{s,0} = N (N + 1) / 2), no absorption (sigma_t =
+    sigma_{s,0}, a reading: the paper gives only the transport cross
+    section).  Volume-source study (Sections 5.1-5.4): a uniform isotropic
+    unit source in the whole cube, uniform angular level ``level``.  Pencil
+    beam (Section 5.5, ``beam``): no volume source, a unit beam along +z on
+    the z = 0 face over 2 < x, y < 3 cm, angular mesh by the z-band rule with
+    ``band_lmax``.  Multigrid: order N on the finest level, ``nr`` (default
+    N) on the coarser ones."""
+    nn = (n, n, n)
+    C = n ** 3
+    sig = 0.5 * N * (N + 1)
+    st = np.full(C, sig)
+    spec = AngularSpec(level) if not band_lmax else AngularSpec(0, band_lmax=band_lmax)
+    nlev = spec.n_levels
+    nr = N if nr is None else nr
+    mg = [nr] * (nlev - 1) + [N]
+    name = "paper-box-%d^3-N%d-%s-nr%d-V%d%d" % (n, N, ("band%d" % band_lmax) if band_lmax else ("lev%d" % level),
+                                               nr, nu_pre, nu_post)
+    inflow = None
+    q = np.ones(C)
+    if beam:
+        # cells whose centres lie in 2 < x, y < 3 cm (exactly the band for n = 30)
+        h = 5.0 / n
+        cen = (np.arange(n) + 0.5) * h
+        inside = np.nonzero((cen > 2.0) & (cen < 3.0))[0]
+        lo_c, hi_c = int(inside[0]), int(inside[-1])
+        inflow = Inflow("beam", 2, 0, (lo_c, lo_c, 0), (hi_c, hi_c, 0), 1.0, (0.0, 0.0, 1.0))
+        q = np.zeros(C)
+        name += "-zbeam"
+    return Problem(name, 3, nn, spec, st, st.copy(), 0.0, N, mg, q, inflow, restart=restart, nu_pre=nu_pre,
+                   nu_post=nu_post, length=(5.0, 5.0, 5.0), fp_N=N)

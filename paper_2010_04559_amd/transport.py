@@ -31,6 +31,7 @@ def problem_struct(prob: Problem):
     p.cone_half_angle_deg = float(a.cone_half_angle_deg)
     p.cone_extra_levels = int(a.extra_levels)
     p.irregularity_closure = 1 if a.closure else 0
+    p.band_lmax = int(a.band_lmax)
     st = np.ascontiguousarray(prob.sigma_t, dtype=np.float64)
     ss = np.ascontiguousarray(prob.sigma_s, dtype=np.float64)
     mom = np.ascontiguousarray(prob.moments(max([prob.order] + list(prob.mg_orders))), dtype=np.float64)
@@ -235,11 +236,14 @@ class Transport:
         return solve_opts(self.prob, tol, restart, max_restarts, mode, timing, z_store)
 
     def solve(self, b, tol=None, restart=None, max_restarts=200, mode="f64", timing=False, check=True,
-              z_store="auto"):
+              z_store="auto", method="gmres"):
+        """GMRES(restart) (method "gmres") or BiCGStab ("bicgstab", at most
+        restart x (max_restarts + 1) iterations)."""
         x = _torch().empty_like(b)
         o = self._opts(tol, restart, max_restarts, mode, timing, z_store)
         st = _lib.TrSolveStats()
-        rc = self.lib.tr_gmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st), _stream())
+        fn = {"gmres": self.lib.tr_gmres_solve, "bicgstab": self.lib.tr_bicgstab_solve}[method]
+        rc = fn(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st), _stream())
         _lib.check(rc, allow=() if check else (_lib.TR_ERR_NOCONV,))
         return x, st.as_dict()
 

@@ -3,7 +3,7 @@
 // builds the patch tree and levels for a refinement spec, forms the finest
 // level's scatter matrix for HG moments, and writes every table as raw
 // doubles (each array preceded by its length as a double).
-//   setup_dump base cone_x cone_y cone_z half_angle extra closure order g out.bin
+//   setup_dump base cone_x cone_y cone_z half_angle extra closure band_lmax order g out.bin
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -18,8 +18,8 @@ static void put(FILE *f, const std::vector<double> &v) {
 }
 
 int main(int argc, char **argv) {
-  if (argc != 11) {
-    std::fprintf(stderr, "usage: setup_dump base cx cy cz half extra closure order g out\n");
+  if (argc != 12) {
+    std::fprintf(stderr, "usage: setup_dump base cx cy cz half extra closure band order g out\n");
     return 2;
   }
   tr::RefineSpec spec;
@@ -28,15 +28,16 @@ int main(int argc, char **argv) {
   spec.cone_half_angle_deg = std::atof(argv[5]);
   spec.cone_extra_levels = std::atoi(argv[6]);
   spec.closure = std::atoi(argv[7]) != 0;
-  const int order = std::atoi(argv[8]);
-  const double g = std::atof(argv[9]);
+  spec.band_lmax = std::atoi(argv[8]);
+  const int order = std::atoi(argv[9]);
+  const double g = std::atof(argv[10]);
   tr::HostAngular ang;
   std::string err;
   if (!tr::build_angular(spec, ang, err)) {
     std::fprintf(stderr, "build_angular: %s\n", err.c_str());
     return 1;
   }
-  FILE *f = std::fopen(argv[10], "wb");
+  FILE *f = std::fopen(argv[11], "wb");
   if (!f) return 1;
   put(f, {(double)ang.lv.size()});
   for (const tr::HostLevel &L : ang.lv) {

@@ -14,6 +14,8 @@ from oracle import multigrid as mgm
 
 
 def angular_mesh(spec):
+    if spec.band_lmax > 0:
+        return ang.AngularMesh.band_z(spec.band_lmax)
     if spec.extra_levels > 0:
         return ang.AngularMesh.cone(spec.cone_axis, spec.cone_half_angle_deg, spec.base_level,
                                     spec.extra_levels, closure=spec.closure)

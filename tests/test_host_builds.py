@@ -94,6 +94,17 @@ def setup_dump(tmp_path_factory):
     return exe, d
 
 
+def test_band_meshes_match_the_paper_counts(setup_dump):
+    """Section 5.5: the z-band rule gives 20, 32, 44, 128, 440, 1388
+    elements for l_max = 1..6 (tests/golden/band_mesh_counts.txt)."""
+    rows = [tuple(int(v) for v in line.split()) for line in open(os.path.join(HERE, "golden", "band_mesh_counts.txt"))
+            if line.strip() and not line.startswith("#")]
+    for lmax, count in rows:
+        levels, _ = _run_dump(setup_dump, (0, 0, 0, 1, 0, 0, 0, lmax, 0, 0.5))
+        assert levels[-1]["P"] == count, (lmax, levels[-1]["P"])
+        assert len(levels) == lmax + 1
+
+
 def _run_dump(setup_dump, args):
     exe, d = setup_dump
     out = str(d / ("t_%d.bin" % abs(hash(tuple(args)))))
@@ -120,12 +131,14 @@ def _run_dump(setup_dump, args):
     return levels, St
 
 
-@pytest.mark.parametrize("spec", [(2, 0, 0, 1, 0, 0, 1, 8, 0.9), (1, 1, 0, 0, 15.0, 2, 1, 6, 0.85),
-                                  (1, 0.3, 0.5, 0.81, 25.0, 2, 1, 4, 0.8)])
+@pytest.mark.parametrize("spec", [(2, 0, 0, 1, 0, 0, 1, 0, 8, 0.9), (1, 1, 0, 0, 15.0, 2, 1, 0, 6, 0.85),
+                                  (1, 0.3, 0.5, 0.81, 25.0, 2, 1, 0, 4, 0.8), (0, 0, 0, 1, 0, 0, 0, 3, 6, 0.9)])
 def test_setup_tables_match_oracle(setup_dump, spec):
-    base, cx, cy, cz, half, extra, closure, order, g = spec
+    base, cx, cy, cz, half, extra, closure, band, order, g = spec
     levels, St = _run_dump(setup_dump, spec)
-    if extra:
+    if band:
+        mesh = ang.AngularMesh.band_z(band)
+    elif extra:
         mesh = ang.AngularMesh.cone((cx, cy, cz), half, base, extra, closure=bool(closure))
     else:
         mesh = ang.AngularMesh.uniform(base)
