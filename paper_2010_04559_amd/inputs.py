@@ -230,7 +230,8 @@ def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=Tru
 
 # ------------------------------------------------------ the paper's workloads
 
-def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_lmax=0, restart=20):
+def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_lmax=0, restart=20,
+              nr_levels="all", nu_coarse=10):
     """The cube of the paper's Section 5 experiments: 5 x 5 x 5 cm, n^3
     hexahedra (30^3 in the paper), vacuum boundaries, Fokker-Planck-
     equivalent scatter moments of order N with transport cross section 1
@@ -240,8 +241,11 @@ def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_l
     unit source in the whole cube, uniform angular level ``level``.  Pencil
     beam (Section 5.5, ``beam``): no volume source, a unit beam along +z on
     the z = 0 face over 2 < x, y < 3 cm, angular mesh by the z-band rule with
-    ``band_lmax``.  Multigrid: order N on the finest level, ``nr`` (default
-    N) on the coarser ones."""
+    ``band_lmax``.  Multigrid scatter orders: ``nr`` (default N) on every
+    preconditioner level (``nr_levels="all"``, Sections 5.3-5.5) or on the
+    coarsest level only with N elsewhere (``"coarsest"``, the Section 5.1
+    study); the problem operator keeps order N.  ``nu_coarse`` Gauss-Seidel
+    sweeps on the coarsest level (10 in Sections 5.3-5.5)."""
     nn = (n, n, n)
     C = n ** 3
     sig = 0.5 * N * (N + 1)
@@ -249,9 +253,15 @@ def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_l
     spec = AngularSpec(level) if not band_lmax else AngularSpec(0, band_lmax=band_lmax)
     nlev = spec.n_levels
     nr = N if nr is None else nr
-    mg = [nr] * (nlev - 1) + [N]
-    name = "paper-box-%d^3-N%d-%s-nr%d-V%d%d" % (n, N, ("band%d" % band_lmax) if band_lmax else ("lev%d" % level),
-                                               nr, nu_pre, nu_post)
+    if nr_levels == "all":
+        mg = [nr] * nlev
+    elif nr_levels == "coarsest":
+        mg = [nr] + [N] * (nlev - 1)
+    else:
+        raise ValueError("nr_levels is 'all' or 'coarsest'")
+    name = "paper-box-%d^3-N%d-%s-nr%d%s-V%d%d-gs%d" % (n, N, ("band%d" % band_lmax) if band_lmax else ("lev%d" % level),
+                                                      nr, "c" if nr_levels == "coarsest" else "", nu_pre, nu_post,
+                                                      nu_coarse)
     inflow = None
     q = np.ones(C)
     if beam:
@@ -264,4 +274,4 @@ def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_l
         q = np.zeros(C)
         name += "-zbeam"
     return Problem(name, 3, nn, spec, st, st.copy(), 0.0, N, mg, q, inflow, restart=restart, nu_pre=nu_pre,
-                   nu_post=nu_post, length=(5.0, 5.0, 5.0), fp_N=N)
+                   nu_post=nu_post, nu_coarse=nu_coarse, length=(5.0, 5.0, 5.0), fp_N=N)

@@ -192,3 +192,19 @@ def test_particle_balance_of_a_converged_solve(dim, n, level, order, beam):
     assert abs(lhs - (source + inflow)) < 1e-10 * scale
     # every term is non-trivial (a dropped term would not balance)
     assert leak > 1e-3 * scale and scatter_in > 1e-3 * scale
+
+
+@pytest.mark.parametrize("N", [4, 16])
+def test_paper_box_moments_follow_fp_moments(N):
+    """The cube workloads' cross sections and moment ratios are eq.
+    scatter_moments with transport cross section 1: sigma_s f_n equals the
+    oracle's fp_moments(1, N) (pinned above), sigma_t = sigma_{s,0}, and the
+    ratios beyond N vanish."""
+    from paper_2010_04559_amd import inputs
+    p = inputs.paper_box(N, level=1, n=3)
+    fp = ang.fp_moments(1.0, N)
+    m = p.moments(N + 3)
+    assert np.allclose(p.sigma_s[0] * m[:N + 1], fp, rtol=0, atol=1e-12 * fp[0])
+    assert not m[N + 1:].any()
+    assert np.all(p.sigma_t == fp[0]) and np.all(p.sigma_s == fp[0])
+    assert abs(p.sigma_s[0] * (m[0] - m[1]) - 1.0) < 1e-12
