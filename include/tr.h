@@ -116,6 +116,9 @@ typedef struct {
   int outer_axes;               /* R of the problem operator's scatter, 0 = dense  */
   int sweep_lds[2];             /* 1: the FP64 / FP32 forward sweeps keep the      */
                                 /* previous diagonal plane in LDS (planes fit)     */
+  int sweep_pair[2];            /* 1: the FP64 / FP32 forward sweeps run over      */
+                                /* bricks of two x-adjacent cells (3-D grids with  */
+                                /* an even cell count along x, planes fit in LDS)  */
 } tr_info_t;
 
 typedef struct {

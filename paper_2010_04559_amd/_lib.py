@@ -37,7 +37,7 @@ class TrInfo(ctypes.Structure):
                 ("n_levels", ctypes.c_int), ("patches", ctypes.c_int * 16), ("order_outer", ctypes.c_int),
                 ("device_bytes", ctypes.c_size_t), ("scatter_form", ctypes.c_int * 16),
                 ("scatter_axes", ctypes.c_int * 16), ("scatter_k", ctypes.c_int * 16), ("outer_axes", ctypes.c_int),
-                ("sweep_lds", ctypes.c_int * 2)]
+                ("sweep_lds", ctypes.c_int * 2), ("sweep_pair", ctypes.c_int * 2)]
 
 
 class TrInflow(ctypes.Structure):

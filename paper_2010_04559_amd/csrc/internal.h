@@ -52,6 +52,15 @@ struct SweepArgs {
   // f is stored in plane order: ordinate k's cell at list position i of its
   // orientation's sweep occupies f[k][i][node] (forward sweeps without s)
   bool plane_in = false;
+  // Brick schedule of the pair sweep (3-D grids with an even number of
+  // cells along x; nplanes = 0 otherwise): bricks of the two cells 2b, 2b+1
+  // of the (+,+,+) frame, packed b | iy << 10 | iz << 20, grouped by
+  // diagonal plane b + iy + iz; link[0] per brick = {packed brick, position
+  // of its x, y, z upwind bricks in the previous plane or -1}.  With pairs
+  // the plane layout holds brick i's cells at positions 2i, 2i + 1 (slot
+  // order of the sweep frame), and sig_pb the cross sections in that order.
+  Planes bpl{};
+  const double *sig_pb = nullptr;
 };
 
 // Sweep-input ("plane") layout: pos[flip][cell] = the cell's position in
@@ -62,6 +71,10 @@ struct SweepArgs {
 // for this level and element type.
 template <typename T>
 bool sweep_lds_fits(const Planes &pl, const Grid &g, bool has_s);
+// Whether the pair sweep runs forward sweeps of element type T on the
+// brick schedule bpl.
+template <typename T>
+bool sweep_pair_fits(const Planes &bpl);
 
 // Fill SweepArgs::sig_pl from the per-cell cross sections.
 void launch_sigma_planes(const double *sig_t, const double *sig_s, const Planes &pl, const Grid &g, double *out,

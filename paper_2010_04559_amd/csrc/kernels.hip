@@ -807,6 +807,290 @@ __global__ __launch_bounds__(NT) void k_sweep_lds(SweepArgs<T> a, int tc) {
 #undef TR_SWEEP_LDS
 }
 
+// ------------------------------------------------------------ pair sweep
+// The forward 3-D sweep over bricks of two x-adjacent cells: cells 2b and
+// 2b + 1 of the sweep frame, which reflection keeps an aligned pair of
+// memory when the grid has an even number of cells along x.  Bricks are
+// walked in the diagonal planes of the brick grid (b + iy + iz); a lane
+// solves its brick's two cells in sweep order, the second taking its x
+// inflow from the first in registers, and the previous plane's bricks are
+// kept in LDS as in the cell kernel above.  A brick's values are 2 ns
+// contiguous elements (64 bytes in FP32, 128 in FP64), so every global
+// access moves whole 64-byte units: FP32 cells written one at a time are
+// 32-byte partial writes, which the memory serves at a fraction of the
+// rate of whole units (measured: those stores took 60% of the cell
+// kernel's time at 48^3).
+// Inputs in plane layout hold brick i's cells at positions 2i and 2i + 1
+// (slot order: slot 0 is the upwind cell); in spatial order the pair is
+// read as stored (physical x order) and mapped to slots.  Each lane loads
+// its brick's chunks itself (no staging: the brick is one aligned unit).
+// LDS: [buffer][slot][node][brick position] values, per buffer the first
+// (lower-address) cell of each brick of the plane, then the plane offsets.
+
+template <typename T, bool HAS_S>
+struct PairRegs {
+  static constexpr int PQ = 2 * 8 * (int)sizeof(T) / 16;  // 16-byte chunks per brick
+  float4 f[PQ], s[HAS_S ? PQ : 1];
+  double2 st, ss;  // cross sections of slots 0 and 1
+  int4 lk;
+};
+
+template <typename T, bool HAS_S>
+__device__ __forceinline__ void pin_regs_pair(PairRegs<T, HAS_S> &q) {
+#pragma unroll
+  for (int i = 0; i < PairRegs<T, HAS_S>::PQ; ++i) {
+    pin_reg(q.f[i]);
+    if (HAS_S) pin_reg(q.s[HAS_S ? i : 0]);
+  }
+  pin_reg(q.st.x);
+  pin_reg(q.st.y);
+  if (HAS_S) {
+    pin_reg(q.ss.x);
+    pin_reg(q.ss.y);
+  }
+}
+
+// element m (0 .. 2 ns - 1, memory order of the brick) of a chunk array
+template <typename T, int N>
+__device__ __forceinline__ T pair_elem(const float4 (&arr)[N], int m) {
+  constexpr int EPC = 16 / (int)sizeof(T);
+  const float4 x = arr[m / EPC];
+  return reinterpret_cast<const T *>(&x)[m % EPC];
+}
+
+template <typename T, bool HAS_S, bool DBUF, bool PIN, int FLIP, int CPT, int NT>
+__device__ __forceinline__ void sweep_pair_body(const SweepArgs<T> &a, int k, T *lds, int *jbuf, const int *off,
+                                                int tc) {
+  constexpr int NS = 8;
+  constexpr int EPC = 16 / (int)sizeof(T);
+  using Regs = PairRegs<T, HAS_S>;
+  constexpr int PQ = Regs::PQ;
+  constexpr int FX = FLIP & 1;  // x reflected: slot 0 is the pair's upper cell in memory
+  const OrdInfo o = a.ord[k];
+  const T c[3] = {T(o.c[0]), T(o.c[1]), T(o.c[2])};
+  const ModeConst<T, 3> mc = mode_const<T, 3>(c);
+  const long long S = a.g.S;
+  const T *fk = a.f + (long long)k * S;
+  const T *sk = HAS_S ? a.s + (long long)k * S : nullptr;
+  T *uk = a.u + (long long)k * S;
+  const long long C = a.g.C;
+  const int nbr = (int)(C / 2);  // bricks
+  const double *sgt = a.sig_pb + (long long)FLIP * C;
+  const double *sgs = a.sig_pb + (8LL + FLIP) * C;
+  const int np = a.bpl.nplanes;
+  const int maxp = a.bpl.max_plane;
+  const int4 *link = a.bpl.link[0];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const bool compute = tid < tc;
+  // lower-address cell of the brick packed bp in this orientation
+  auto base_cell = [&](int bp) -> long long {
+    const int bx = bp & 1023, iy = (bp >> 10) & 1023, iz = (bp >> 20) & 1023;
+    const int ix = (FLIP & 1) ? a.g.n[0] - 2 - 2 * bx : 2 * bx;
+    const int jy = (FLIP & 2) ? a.g.n[1] - 1 - iy : iy;
+    const int jz = (FLIP & 4) ? a.g.n[2] - 1 - iz : iz;
+    return ix + (long long)a.g.n[0] * (jy + (long long)a.g.n[1] * jz);
+  };
+  // As in the cell kernels: every global load is unconditional, from an
+  // address clamped to valid memory, its validity applied after the wait.
+  // Brick group r of a compute lane is plane position tid + r tc.
+  auto link_valid = [&](int pp, int r) { return off[pp] + tid + r * tc < off[pp + 1]; };
+  auto load_link = [&](int pp, int r) { return link[min(off[pp] + tid + r * tc, nbr - 1)]; };
+  auto load_plane = [&](int pp, int r, Regs &q) {
+    const int bi = min(off[pp] + tid + r * tc, nbr - 1);
+    const long long jb = base_cell(q.lk.x >= 0 ? q.lk.x : 0);
+    const float4 *src = reinterpret_cast<const float4 *>(fk + (PIN ? 2LL * bi : jb) * NS);
+#pragma unroll
+    for (int i = 0; i < PQ; ++i) q.f[i] = src[i];
+    if (HAS_S) {
+      const float4 *ss = reinterpret_cast<const float4 *>(sk + jb * NS);
+#pragma unroll
+      for (int i = 0; i < PQ; ++i) q.s[HAS_S ? i : 0] = ss[i];
+    }
+    q.st = *reinterpret_cast<const double2 *>(sgt + 2LL * bi);
+    if (HAS_S) q.ss = *reinterpret_cast<const double2 *>(sgs + 2LL * bi);
+  };
+
+  Regs cur[CPT], nxt[CPT];
+#pragma unroll
+  for (int r = 0; r < CPT; ++r) {
+    cur[r].lk = make_int4(-1, -1, -1, -1);
+    nxt[r].lk = make_int4(-1, -1, -1, -1);
+  }
+  if (compute) {
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      cur[r].lk = load_link(0, r);
+      pin_reg(cur[r].lk);
+      if (!link_valid(0, r)) cur[r].lk.x = -1;
+      load_plane(0, r, cur[r]);
+      nxt[r].lk = load_link(min(1, np - 1), r);
+    }
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      pin_regs_pair(cur[r]);
+      pin_reg(nxt[r].lk);
+      if (np < 2 || !link_valid(1, r)) nxt[r].lk.x = -1;
+    }
+  }
+
+  if (compute) {
+    for (int pp = 0; pp < np; ++pp) {
+      int4 lk2[CPT];
+      const T *rd = lds + (DBUF ? ((pp + 1) & 1) : 0) * 2 * NS * maxp;  // previous plane
+      T *wr = lds + (DBUF ? (pp & 1) : 0) * 2 * NS * maxp;
+      T res[DBUF ? 1 : CPT][2][NS];  // single buffer: held until every read is done
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        if (r == 0) {
+          // the next plane's loads, in flight during this plane's work
+#pragma unroll
+          for (int r2 = 0; r2 < CPT; ++r2) {
+            load_plane(min(pp + 1, np - 1), r2, nxt[r2]);
+            lk2[r2] = load_link(min(pp + 2, np - 1), r2);
+          }
+        }
+        const int nbp[3] = {cur[r].lk.y, cur[r].lk.z, cur[r].lk.w};
+        // the upwind neighbour's outflow face along d, from slot sl of the
+        // neighbouring brick in the previous plane (zero at the boundary)
+        auto lds_trace = [&](int d, int sl, T *tr) {
+          const int nbit = ((FLIP >> d) & 1) ? 0 : 1;
+          const int q = nbp[d] >= 0 ? nbp[d] : 0;
+#pragma unroll
+          for (int t = 0; t < NS / 2; ++t) {
+            const T x = rd[(sl * NS + insert_bit(t, d, nbit)) * maxp + q];  // may be uninitialised: select
+            tr[t] = nbp[d] >= 0 ? x : T(0);
+          }
+        };
+        // inflow along d: 4 c on the own inflow face, -2 c on the opposite one
+        auto inflow = [&](T *v, int d, const T *tr) {
+          const int own0 = (FLIP >> d) & 1;
+          const T c4 = T(4) * c[d], c2 = T(2) * c[d];
+#pragma unroll
+          for (int t = 0; t < NS / 2; ++t) {
+            v[insert_bit(t, d, own0)] += c4 * tr[t];
+            v[insert_bit(t, d, 1 - own0)] -= c2 * tr[t];
+          }
+        };
+        T v[2][NS];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int mf = ((PIN || !FX) ? sl : 1 - sl) * NS;
+          const int ms = (FX ? 1 - sl : sl) * NS;
+          const T sg = T(sl ? cur[r].ss.y : cur[r].ss.x);
+#pragma unroll
+          for (int b = 0; b < NS; ++b) {
+            v[sl][b] = pair_elem<T>(cur[r].f, mf + b);
+            if (HAS_S) v[sl][b] += sg * pair_elem<T>(cur[r].s, ms + b);
+          }
+        }
+        T tr[NS / 2], ty[NS / 2], tz[NS / 2];
+        lds_trace(0, 1, tr);  // slot 0's x inflow: slot 1 of the x-upwind brick
+        inflow(v[0], 0, tr);
+        lds_trace(1, 0, tr);
+        inflow(v[0], 1, tr);
+        lds_trace(2, 0, tr);
+        inflow(v[0], 2, tr);
+        lds_trace(1, 1, ty);
+        lds_trace(2, 1, tz);
+        oriented_solve<T, 3, false, FLIP>(v[0], mc, T(cur[r].st.x));
+        {
+          const int nbit = (FLIP & 1) ? 0 : 1;  // slot 0's outflow face along x
+#pragma unroll
+          for (int t = 0; t < NS / 2; ++t) tr[t] = v[0][insert_bit(t, 0, nbit)];
+        }
+        inflow(v[1], 0, tr);
+        inflow(v[1], 1, ty);
+        inflow(v[1], 2, tz);
+        oriented_solve<T, 3, false, FLIP>(v[1], mc, T(cur[r].st.y));
+        if (DBUF) {
+          if (cur[r].lk.x >= 0) {
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+              for (int b = 0; b < NS; ++b) wr[(sl * NS + b) * maxp + tid + r * tc] = v[sl][b];
+            jbuf[(pp & 1) * maxp + tid + r * tc] = (int)base_cell(cur[r].lk.x);
+          }
+        } else {
+#pragma unroll
+          for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+            for (int b = 0; b < NS; ++b) res[DBUF ? 0 : r][sl][b] = v[sl][b];
+        }
+      }
+      if (!DBUF) {
+        lds_barrier();  // every read of the previous plane done
+#pragma unroll
+        for (int r = 0; r < CPT; ++r)
+          if (cur[r].lk.x >= 0) {
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+              for (int b = 0; b < NS; ++b) wr[(sl * NS + b) * maxp + tid + r * tc] = res[DBUF ? 0 : r][sl][b];
+            jbuf[tid + r * tc] = (int)base_cell(cur[r].lk.x);
+          }
+      }
+      lds_barrier();  // the plane is complete in LDS
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        pin_regs_pair(nxt[r]);
+        pin_reg(lk2[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        if (pp + 2 >= np || !link_valid(pp + 2, r)) lk2[r].x = -1;
+        cur[r] = nxt[r];
+        nxt[r].lk = lk2[r];
+      }
+    }
+  } else {
+    // store waves: chunk ch (memory order) of CPB bricks per access
+    constexpr int CPB = 64 / PQ;
+    const int ch = lane / CPB;
+    const int m0 = ch * EPC;
+    const int sl = (FLIP & 1) ? 1 - m0 / NS : m0 / NS;
+    const int b0 = m0 % NS;
+    for (int pp = 0; pp < np; ++pp) {
+      if (!DBUF) lds_barrier();
+      lds_barrier();
+      const int n = off[pp + 1] - off[pp];
+      const T *pb = lds + (DBUF ? (pp & 1) : 0) * 2 * NS * maxp;
+      const int *jb = jbuf + (DBUF ? (pp & 1) : 0) * maxp;
+      for (int base = (tid - tc) / 64 * CPB; base < n; base += (NT - tc) / 64 * CPB) {
+        const int q = base + lane % CPB;
+        if (q < n) {
+          T w[EPC];
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) w[e] = pb[(sl * NS + b0 + e) * maxp + q];
+          *reinterpret_cast<float4 *>(uk + (long long)jb[q] * NS + m0) = *reinterpret_cast<float4 *>(w);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, bool HAS_S, bool DBUF, bool PIN, int CPT, int NT, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_sweep_pair(SweepArgs<T> a, int tc) {
+  extern __shared__ __align__(16) unsigned char sweep_smem[];
+  T *lds = reinterpret_cast<T *>(sweep_smem);
+  constexpr int NB = DBUF ? 2 : 1;
+  int *jbuf = reinterpret_cast<int *>(lds + (size_t)NB * 16 * a.bpl.max_plane);
+  int *off = jbuf + NB * a.bpl.max_plane;
+  for (int i = threadIdx.x; i <= a.bpl.nplanes; i += blockDim.x) off[i] = a.bpl.off[i];
+  __syncthreads();
+  const int k = blockIdx.x;
+  switch (a.ord[k].flip) {
+    case 0: sweep_pair_body<T, HAS_S, DBUF, PIN, 0, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    case 1: sweep_pair_body<T, HAS_S, DBUF, PIN, 1, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    case 2: sweep_pair_body<T, HAS_S, DBUF, PIN, 2, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    case 3: sweep_pair_body<T, HAS_S, DBUF, PIN, 3, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    case 4: sweep_pair_body<T, HAS_S, DBUF, PIN, 4, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    case 5: sweep_pair_body<T, HAS_S, DBUF, PIN, 5, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    case 6: sweep_pair_body<T, HAS_S, DBUF, PIN, 6, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+    default: sweep_pair_body<T, HAS_S, DBUF, PIN, 7, CPT, NT>(a, k, lds, jbuf, off, tc); break;
+  }
+}
+
 // Cross sections per orientation in cell-list order (coalesced reads in
 // the LDS sweep).
 __global__ void k_sigma_planes(const double *__restrict__ sig_t, const double *__restrict__ sig_s, Planes pl,
@@ -2573,8 +2857,102 @@ bool sweep_lds_fits(const Planes &pl, const Grid &g, bool has_s) {
 template bool sweep_lds_fits<double>(const Planes &, const Grid &, bool);
 template bool sweep_lds_fits<float>(const Planes &, const Grid &, bool);
 
+struct PairCfg {
+  int cpt = 0, nt = 0, tc = 0;
+  bool dbuf = false;
+  size_t lds = 0;
+};
+
+// Launch shape of the pair sweep: bricks per compute lane and threads (at
+// least one store wave), one or two plane buffers in the 160 KB of LDS.
+// Chosen by measurement (48^3 FP32: 2 bricks per lane and 768 threads,
+// 3.2 ms; 1024 threads 5.7 ms (register cap), 4 per lane 13 ms, store
+// waves' work done by the compute lanes themselves 3.4 ms).  FP64 bricks
+// (128 bytes) take one per lane, 768 threads (512: 0.63 ms at 32^3
+// against 0.52 ms).
+static bool pair_config(int tsize, const Planes &bpl, PairCfg &cfg) {
+  if (bpl.nplanes <= 0) return false;
+  const int cands[4][2] = {{1, 512}, {1, 768}, {2, 768}, {1, 1024}};
+  for (auto &cd : cands) {
+    const int cpt = cd[0], nt = cd[1];
+    if (tsize == 8 && !(cpt == 1 && nt == 768)) continue;
+    const int tc = ((bpl.max_plane + cpt - 1) / cpt + 63) / 64 * 64;
+    if (tc > nt - 64) continue;
+    const size_t plane = ((size_t)tsize * 16 + sizeof(int)) * (size_t)bpl.max_plane;
+    const size_t tail = sizeof(int) * (bpl.nplanes + 1);
+    if (plane + tail > 160 * 1024) continue;
+    cfg.cpt = cpt;
+    cfg.nt = nt;
+    cfg.tc = tc;
+    cfg.dbuf = 2 * plane + tail <= 160 * 1024;
+    cfg.lds = (cfg.dbuf ? 2 : 1) * plane + tail;
+    return true;
+  }
+  return false;
+}
+
+template <typename T, bool HAS_S, int CPT, int NT, int MINW>
+static void launch_pair_cfg(const SweepArgs<T> &a, int n_ord, const PairCfg &cfg, bool pin, hipStream_t st) {
+  auto fn = cfg.dbuf ? (pin ? k_sweep_pair<T, HAS_S, true, !HAS_S, CPT, NT, MINW>
+                            : k_sweep_pair<T, HAS_S, true, false, CPT, NT, MINW>)
+                     : (pin ? k_sweep_pair<T, HAS_S, false, !HAS_S, CPT, NT, MINW>
+                            : k_sweep_pair<T, HAS_S, false, false, CPT, NT, MINW>);
+  if (cfg.lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds) != hipSuccess)
+    throw std::runtime_error("pair sweep: cannot reserve its shared memory");
+  hipLaunchKernelGGL(fn, dim3(n_ord), dim3(NT), cfg.lds, st, a, cfg.tc);
+}
+
+template <typename T, bool HAS_S>
+static bool launch_sweep_pair(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
+  PairCfg cfg;
+  if (!a.sig_pb || !pair_config((int)sizeof(T), a.bpl, cfg)) return false;
+  auto aligned = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+  if (!aligned(a.f) || !aligned(a.u) || (a.s && !aligned(a.s))) return false;
+  if (a.plane_in && HAS_S) throw std::runtime_error("plane-layout input needs a forward sweep without s");
+  const bool pin = a.plane_in;
+  if (cfg.cpt == 1 && cfg.nt == 512) {
+    // FP32: two workgroups per CU (registers for four waves per SIMD)
+    if constexpr (sizeof(T) == 4)
+      launch_pair_cfg<T, HAS_S, 1, 512, 4>(a, n_ord, cfg, pin, st);
+    else
+      throw std::runtime_error("internal: FP64 pair sweep with 512 threads");
+  } else if (cfg.cpt == 1 && cfg.nt == 768) {
+    launch_pair_cfg<T, HAS_S, 1, 768, 3>(a, n_ord, cfg, pin, st);
+  } else if (cfg.cpt == 1 && cfg.nt == 1024) {
+    if constexpr (sizeof(T) == 4)
+      launch_pair_cfg<T, HAS_S, 1, 1024, 4>(a, n_ord, cfg, pin, st);
+    else
+      throw std::runtime_error("internal: FP64 pair sweep with 1024 threads");
+  } else if (cfg.cpt == 2 && cfg.nt == 768) {
+    if constexpr (sizeof(T) == 4)
+      launch_pair_cfg<T, HAS_S, 2, 768, 3>(a, n_ord, cfg, pin, st);
+    else
+      throw std::runtime_error("internal: FP64 pair sweep with two bricks per lane");
+  } else {
+    throw std::runtime_error("internal: pair sweep configuration without a kernel");
+  }
+  return true;
+}
+
+template <typename T>
+bool sweep_pair_fits(const Planes &bpl) {
+  PairCfg cfg;
+  return pair_config((int)sizeof(T), bpl, cfg);
+}
+template bool sweep_pair_fits<double>(const Planes &);
+template bool sweep_pair_fits<float>(const Planes &);
+
 template <typename T, int DIM, bool ADJ>
 static void launch_sweep_r(const SweepArgs<T> &a, int n_ord, hipStream_t st) {
+  if constexpr (DIM == 3 && !ADJ) {
+    // forward sweeps of prepared right-hand sides (no separate scatter term)
+    if (a.bpl.nplanes > 0 && !a.s) {
+      if (launch_sweep_pair<T, false>(a, n_ord, st)) return;
+      // with pairs the plane layout is the brick slot order: no other kernel reads it
+      if (a.plane_in) throw std::runtime_error("plane-layout input needs the pair sweep");
+    }
+  }
   if (a.s ? launch_sweep_lds<T, DIM, ADJ, true>(a, n_ord, st) : launch_sweep_lds<T, DIM, ADJ, false>(a, n_ord, st))
     return;
   if (a.plane_in) throw std::runtime_error("plane-layout input needs the LDS sweep");

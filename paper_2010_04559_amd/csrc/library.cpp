@@ -169,6 +169,12 @@ struct tr_handle {
   int *d_cells = nullptr, *d_off = nullptr;
   double *sig_t = nullptr, *sig_s = nullptr;
   double *sig_pl = nullptr;  // [2][8][cells] cross sections per orientation, cell-list order
+  // brick schedule of the pair sweep (3-D, even cells along x), its slot
+  // list (the cells brick by brick in sweep-frame order) and the cross
+  // sections per orientation in slot order
+  tr::Planes bpl{};
+  int *d_slots = nullptr;
+  double *sig_pb = nullptr;
   tr::HostAngular ang;
   std::vector<DevLevel> lv;
   double *Souter = nullptr;  // canonical S~ at the problem's order on the finest level
@@ -394,6 +400,13 @@ std::vector<double> octant_blocks(const std::vector<double> &M, int A, const std
 const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj);
 void ensure_coarse_buffers(tr_handle *h);
 
+// The slot list as a cell list (for the per-orientation cross-section tables).
+tr::Planes slot_planes(const tr_handle *h) {
+  tr::Planes sp{};
+  sp.cells = h->d_slots;
+  return sp;
+}
+
 void build(tr_handle *h, const tr_problem *p) {
   if (p->dim != 2 && p->dim != 3) throw ArgError{"dim must be 2 or 3"};
   for (int d = 0; d < p->dim; ++d) {
@@ -506,13 +519,66 @@ void build(tr_handle *h, const tr_problem *p) {
     h->pl.link[1] = reinterpret_cast<const int4 *>(h->upload(link_dn));
     h->plane_off_host = off;
     h->cells_host = cells;
+    // Brick schedule of the pair sweep: bricks of cells 2b, 2b + 1 along x
+    // in the (+,+,+) frame, grouped by diagonal plane b + iy + iz, with the
+    // positions of each brick's upwind bricks in the previous plane; the
+    // slot list holds the cells brick by brick (slot 0 the upwind one).
+    std::vector<int> slots;
+    if (g.dim == 3 && g.n[0] % 2 == 0) {
+      const int nb = g.n[0] / 2;
+      const int npb = nb + g.n[1] + g.n[2] - 2;
+      std::vector<std::vector<int>> bb(npb);
+      for (int iz = 0; iz < g.n[2]; ++iz)
+        for (int iy = 0; iy < g.n[1]; ++iy)
+          for (int bx = 0; bx < nb; ++bx) bb[bx + iy + iz].push_back(bx | (iy << 10) | (iz << 20));
+      std::vector<int> bricks, boff{0};
+      int bmx = 0;
+      for (auto &b : bb) {
+        bricks.insert(bricks.end(), b.begin(), b.end());
+        boff.push_back((int)bricks.size());
+        bmx = std::max(bmx, (int)b.size());
+      }
+      std::vector<int> bpos((size_t)nb * g.n[1] * g.n[2]);
+      auto blin = [&](int bx, int iy, int iz) { return bx + (long long)nb * (iy + (long long)g.n[1] * iz); };
+      for (int pl = 0; pl < npb; ++pl)
+        for (int i = boff[pl]; i < boff[pl + 1]; ++i) {
+          const int c = bricks[i];
+          bpos[blin(c & 1023, (c >> 10) & 1023, (c >> 20) & 1023)] = i - boff[pl];
+        }
+      std::vector<int> blink(4 * bricks.size());
+      slots.resize(2 * bricks.size());
+      for (size_t i = 0; i < bricks.size(); ++i) {
+        const int c = bricks[i];
+        const int ci[3] = {c & 1023, (c >> 10) & 1023, (c >> 20) & 1023};
+        blink[4 * i] = c;
+        for (int d = 0; d < 3; ++d) {
+          int q[3] = {ci[0], ci[1], ci[2]};
+          int up = -1;
+          if (ci[d] > 0) {
+            q[d] = ci[d] - 1;
+            up = bpos[blin(q[0], q[1], q[2])];
+          }
+          blink[4 * i + 1 + d] = up;
+        }
+        for (int sl = 0; sl < 2; ++sl) slots[2 * i + sl] = (2 * ci[0] + sl) | (ci[1] << 10) | (ci[2] << 20);
+      }
+      h->bpl.cells = h->upload(bricks);
+      h->bpl.off = h->upload(boff);
+      h->bpl.nplanes = npb;
+      h->bpl.max_plane = bmx;
+      h->bpl.link[0] = reinterpret_cast<const int4 *>(h->upload(blink));
+      h->bpl.link[1] = nullptr;
+      h->d_slots = h->upload(slots);
+    }
     // position of every cell in each orientation's sweep list (the plane
-    // layout of forward sweep inputs)
+    // layout of forward sweep inputs): the cell list, or with the pair
+    // sweep the slot list
     {
+      const std::vector<int> &order = slots.empty() ? cells : slots;
       std::vector<int> ppos(8 * (size_t)g.C);
       for (int fl = 0; fl < 8; ++fl)
-        for (size_t i = 0; i < cells.size(); ++i) {
-          const int c = cells[i];
+        for (size_t i = 0; i < order.size(); ++i) {
+          const int c = order[i];
           int ix[3] = {c & 1023, (c >> 10) & 1023, (c >> 20) & 1023};
           for (int d = 0; d < 3; ++d)
             if ((fl >> d) & 1) ix[d] = g.n[d] - 1 - ix[d];
@@ -530,8 +596,10 @@ void build(tr_handle *h, const tr_problem *p) {
   h->sig_t = h->upload(h->sig_t_host);
   h->sig_s = h->upload(h->sig_s_host);
   h->sig_pl = h->alloc<double>(16 * g.C);
+  if (h->d_slots) h->sig_pb = h->alloc<double>(16 * g.C);
   if (!h->dry) {
     tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, g, h->sig_pl, nullptr);
+    if (h->d_slots) tr::launch_sigma_planes(h->sig_t, h->sig_s, slot_planes(h), g, h->sig_pb, nullptr);
     HIPCHK(hipDeviceSynchronize());
   }
 
@@ -565,8 +633,13 @@ void build(tr_handle *h, const tr_problem *p) {
     // forward sweep inputs in plane layout on the V-cycle's smoothing levels
     // when their sweeps run in the LDS kernel (one pre-smoothing sweep: the
     // restricted residual then needs no plane-layout input)
-    D.pin64 = l >= 1 && l < nlev && h->prob.nu_pre == 1 && tr::sweep_lds_fits<double>(h->pl, g, false);
-    D.pin32 = l >= 1 && l < nlev && h->prob.nu_pre == 1 && tr::sweep_lds_fits<float>(h->pl, g, false);
+    // with the pair sweep the plane layout is its slot order, read by no
+    // other kernel
+    const bool pairs = h->bpl.nplanes > 0;
+    D.pin64 = l >= 1 && l < nlev && h->prob.nu_pre == 1 &&
+              (pairs ? tr::sweep_pair_fits<double>(h->bpl) : tr::sweep_lds_fits<double>(h->pl, g, false));
+    D.pin32 = l >= 1 && l < nlev && h->prob.nu_pre == 1 &&
+              (pairs ? tr::sweep_pair_fits<float>(h->bpl) : tr::sweep_lds_fits<float>(h->pl, g, false));
     D.w = h->upload(H.w);
     D.winv = h->upload(winv);
     D.ipsi = h->upload(H.ipsi);
@@ -816,6 +889,8 @@ void do_sweep(tr_handle *h, int l, const T *f, const T *s, T *u, bool adj, hipSt
   a.pl = h->pl;
   a.g = h->g;
   a.plane_in = !adj && (sizeof(T) == 8 ? h->lv[l].pin64 : h->lv[l].pin32);
+  a.bpl = h->bpl;
+  a.sig_pb = h->sig_pb;
   const bool fine = l == h->top();
   h->sweep_dofs += (double)h->lv[l].A * (double)h->g.S;
   tbegin(h, fine ? C_SWEEP_FINE : C_SWEEP);
@@ -1742,6 +1817,8 @@ int tr_info(const tr_handle *h, tr_info_t *out) {
   out->outer_axes = h->Bouter ? h->outer_R : 0;
   out->sweep_lds[0] = tr::sweep_lds_fits<double>(h->pl, h->g, false) ? 1 : 0;
   out->sweep_lds[1] = tr::sweep_lds_fits<float>(h->pl, h->g, false) ? 1 : 0;
+  out->sweep_pair[0] = h->bpl.nplanes > 0 && tr::sweep_pair_fits<double>(h->bpl) ? 1 : 0;
+  out->sweep_pair[1] = h->bpl.nplanes > 0 && tr::sweep_pair_fits<float>(h->bpl) ? 1 : 0;
   return TR_OK;
 }
 
@@ -1762,6 +1839,7 @@ int tr_set_sigma(tr_handle *h, const double *sigma_t, const double *sigma_s, tr_
     HIPCHK(hipMemcpyAsync(h->sig_t, sigma_t, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
     HIPCHK(hipMemcpyAsync(h->sig_s, sigma_s, h->g.C * sizeof(double), hipMemcpyDeviceToDevice, S(st)));
     tr::launch_sigma_planes(h->sig_t, h->sig_s, h->pl, h->g, h->sig_pl, S(st));
+    if (h->d_slots) tr::launch_sigma_planes(h->sig_t, h->sig_s, slot_planes(h), h->g, h->sig_pb, S(st));
     h->sig_t_host = t;
     h->sig_s_host = sc;
     return TR_OK;

@@ -114,6 +114,7 @@ class Transport:
                               for l in range(info.n_levels)]
         self.outer_axes = info.outer_axes
         self.sweep_lds = {"f64": bool(info.sweep_lds[0]), "f32": bool(info.sweep_lds[1])}
+        self.sweep_pair = {"f64": bool(info.sweep_pair[0]), "f32": bool(info.sweep_pair[1])}
         self.dev = torch.device("cuda")
 
     def close(self):
@@ -268,6 +269,8 @@ class Transport:
     def sweep_kernel_name(self, level=None, prec="f64"):
         """Name of the forward-sweep kernel the library launches."""
         t = "double" if prec == "f64" else "float"
+        if self.sweep_pair[prec]:
+            return "k_sweep_pair<%s>" % t
         return ("k_sweep_lds<%s,%d>" if self.sweep_lds[prec] else "k_sweep<%s,%d>") % (t, self.prob.dim)
 
     def scatter_flops(self, level=None, outer=False):

@@ -180,9 +180,12 @@ def test_determinism(pair):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("n", [(28, 28, 28), (64, 64, 20)])
+@pytest.mark.parametrize("n", [(28, 28, 28), (64, 64, 20), (6, 5, 7), (2, 3, 9), (48, 10, 6), (7, 6, 4)])
 def test_sweep_large_planes(n):
-    """Planes of 588 and ~1280 cells: several cells per thread per plane."""
+    """Planes of 588 and ~1280 cells (several cells per thread per plane),
+    and grids of even and odd cell counts along x: with an even count the
+    forward sweep runs over bricks of two x-adjacent cells (FP32 and FP64
+    where the brick planes fit), with an odd one over cells."""
     from paper_2010_04559_amd import inputs
     torch = torch_mod()
     prob = inputs.small_problem(dim=3, n=4, level=0, order=2, seed=12)
@@ -197,8 +200,12 @@ def test_sweep_large_planes(n):
     pr = Pair(prob, with_mg=False)
     lv = pr.op.outer
     g = _rand(lv.A * lv.grid.S, 14)
-    assert rel(to_np(pr.tr.sweep(0, to_dev(g))), lv.sweep(g)) < 1e-12
+    ref = lv.sweep(g)
+    assert rel(to_np(pr.tr.sweep(0, to_dev(g))), ref) < 1e-12
     assert rel(to_np(pr.tr.sweep(0, to_dev(g), adjoint=True)), lv.sweep_T(g)) < 1e-12
+    got32 = pr.tr.sweep(0, to_dev(g).float()).double().cpu().numpy()
+    assert rel(got32, ref) < 2e-5
+    assert pr.tr.sweep_pair["f32"] == (n[0] % 2 == 0)
 
 
 def test_coarse_gs_multiblock_planes():
