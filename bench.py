@@ -173,7 +173,7 @@ def _timed_solves(tr, b, mode, steps, warmup, label):
     for i in range(steps):
         x, st = tr.solve(b, mode=mode, timing=True)
         for k, v in st.items():
-            if k.startswith("ms_") or k.startswith("n_"):
+            if k.startswith("ms_") or k.startswith("n_") or k == "coarse_steps":
                 acc[k] = acc.get(k, 0) + v
         print("%s step %d: iters %d rel_res %.2e %.1f ms" % (label, i, st["iters"], st["rel_res"], st["ms_total"]),
               file=sys.stderr, flush=True)
