@@ -15,7 +15,7 @@ single steps.
 
 Modules
 -------
-angular    hierarchical spherical-triangle patches, Lin basis, quadrature,
+angular    hierarchical spherical-triangle patches, Lin and Const bases, quadrature,
            angular matrices, Legendre scatter kernel, prolongation
            (Sections 2.1-2.2, 4.1, 5.2, 5.5)
 spatial    trilinear/bilinear nodal DG matrices on a Cartesian mesh

@@ -4,7 +4,7 @@ Follows Section 2.1 (patches obtained by recursively splitting the eight
 octant triangles into four daughters through great-circle edge midpoints),
 Section 2.2 (the Lin basis: nodal functions that are the Lagrange functions
 of the flat triangle spanned by the patch vertices projected onto the
-octahedron face), Section 4.1 (nested meshes T_l, two-irregularity, Galerkin
+octahedron face; and the Const basis, one constant per patch), Section 4.1 (nested meshes T_l, two-irregularity, Galerkin
 prolongation with R = P^T), Section 5.2 (the harmonic expansion of the
 scatter source and the X integrals of eq. X) and Section 5.5 (the z-band
 anisotropic refinement rule with its element counts).
@@ -18,6 +18,8 @@ Readings where the paper is silent (each also listed in the design notes):
     three Lin functions exactly.  Three points for three functions make the
     rule collocated, so each (cell, patch) block decouples into three
     ordinates after a fixed 3x3 change of basis;
+  * the Const basis' transport terms (M_q = |q|, A^xi_q = int_q Omega_xi,
+    int psi = |q|) are integrated with the accurate rule below;
   * the X integrals of eq. X are integrals: they are evaluated with a
     high-order (collapsed Gauss) rule to round-off.  Evaluating them with
     the 3-point rule aliases high Legendre orders on coarse meshes (the
@@ -236,6 +238,20 @@ def lin_basis(patch, omegas):
     return np.linalg.solve(flat.T, x.T).T
 
 
+def const_basis(patch, omegas):
+    """psi_q = 1 on the patch: the Const set of Section 2.2 (one dof per
+    patch).  Returns shape (npoints, 1)."""
+    return np.ones((len(np.atleast_2d(omegas)), 1))
+
+
+# angular bases: name -> (basis function, dofs per patch)
+BASES = {"lin": (lin_basis, 3), "const": (const_basis, 1)}
+
+
+def basis_dofs(basis):
+    return BASES[basis][1]
+
+
 # ------------------------------------------------------------ quadrature
 
 def _flat_rule_on_patch(patch, bary, bary_w):
@@ -291,6 +307,13 @@ QUAD3_BARY = np.array([[2 / 3, 1 / 6, 1 / 6],
                        [1 / 6, 1 / 6, 2 / 3]])
 
 
+def quad_exact(patch):
+    """The rule of the Const basis' transport terms: the accurate reference
+    rule, so that M_q = |q| and A^xi_q = int_q Omega_xi to round-off (a
+    reading: the paper fixes no quadrature)."""
+    return quad_accurate(patch, 1)
+
+
 def quad3(patch):
     """The 3-point rule of the transport terms: points at barycentric
     (2/3, 1/6, 1/6) (and permutations) of the flat triangle, mapped to the
@@ -309,16 +332,20 @@ def quad3(patch):
 # ------------------------------------------------------ angular matrices
 
 class PatchRule:
-    """Quadrature points, weights and basis values for a list of patches."""
+    """Quadrature points, weights and basis values for a list of patches
+    (Lin basis: 3 functions per patch; Const: 1)."""
 
-    def __init__(self, patches, rule=quad3):
+    def __init__(self, patches, rule=None, basis="lin"):
+        fn, self.nd = BASES[basis]
+        if rule is None:
+            rule = quad3 if basis == "lin" else quad_exact
         self.patches = patches
         self.omega, self.w, self.psi, self.owner = [], [], [], []
         for q, p in enumerate(patches):
             om, w = rule(p)
             self.omega.append(om)
             self.w.append(w)
-            self.psi.append(lin_basis(p, om))      # (npts, 3): psi_d(Omega_k)
+            self.psi.append(fn(p, om))             # (npts, nd): psi_d(Omega_k)
             self.owner.append(np.full(len(w), q))
         self.omega = np.vstack(self.omega)
         self.w = np.concatenate(self.w)
@@ -342,11 +369,12 @@ class PatchRule:
 
     def weighted_basis(self):
         """Block matrix B (A x npts): B[(q,m), k] = w_k psi_{q,m}(Omega_k)."""
-        A, npts = 3 * len(self.patches), len(self.w)
+        nd = self.nd
+        A, npts = nd * len(self.patches), len(self.w)
         B = np.zeros((A, npts))
         for q in range(len(self.patches)):
             idx = np.nonzero(self.owner == q)[0]
-            B[3 * q:3 * q + 3, idx] = (self.psi[q] * self.w[idx][:, None]).T
+            B[nd * q:nd * q + nd, idx] = (self.psi[q] * self.w[idx][:, None]).T
         return B
 
 
@@ -383,35 +411,36 @@ def real_harmonics(order, omega):
     return Y
 
 
-def x_integrals(patches, order):
+def x_integrals(patches, order, basis="lin"):
     """X_{[q]m,no} = int_{D_q} psi_{q,m} Y_{n,o} (eq. X), shape (A, (order+1)^2),
     integrated with the accurate reference rule of each patch."""
-    X = np.zeros((3 * len(patches), (order + 1) ** 2))
+    fn, nd = BASES[basis]
+    X = np.zeros((nd * len(patches), (order + 1) ** 2))
     for q, p in enumerate(patches):
         om, w = quad_accurate(p, order)
-        psi = lin_basis(p, om)
-        X[3 * q:3 * q + 3] = (psi * w[:, None]).T @ real_harmonics(order, om)
+        psi = fn(p, om)
+        X[nd * q:nd * q + nd] = (psi * w[:, None]).T @ real_harmonics(order, om)
     return X
 
 
-def scatter_matrix(patches, moments):
+def scatter_matrix(patches, moments, basis="lin"):
     """Dense angular scatter matrix S~ (A x A) per unit sigma_s, Section 5.2:
     S~[(q,m),(p,d)] = sum_{n,o} f_n X_{[q]mno} X_{[p]dno}, with
     sigma_{s,n} = sigma_s f_n and f = ``moments`` (f_0 ... f_L)."""
     moments = np.asarray(moments, dtype=np.float64)
     L = len(moments) - 1
-    X = x_integrals(patches, L)
+    X = x_integrals(patches, L, basis)
     F = np.concatenate([np.full(2 * n + 1, moments[n]) for n in range(L + 1)])
     return (X * F[None, :]) @ X.T
 
 
-def scatter_matrix_addition(patches, moments):
+def scatter_matrix_addition(patches, moments, basis="lin"):
     """The same S~ through the addition theorem
     sum_o Y_no(a) Y_no(b) = (2n+1)/(4 pi) P_n(a . b): a harmonic-convention
     free cross-check (small meshes only: dense in all quadrature points)."""
     moments = np.asarray(moments, dtype=np.float64)
     L = len(moments) - 1
-    rule = PatchRule(patches, lambda p: quad_accurate(p, L))
+    rule = PatchRule(patches, lambda p: quad_accurate(p, L), basis)
     mu = np.clip(rule.omega @ rule.omega.T, -1.0, 1.0)
     P = legendre_table(L, mu)
     coef = moments * (2 * np.arange(L + 1) + 1) / (4 * math.pi)
@@ -420,19 +449,21 @@ def scatter_matrix_addition(patches, moments):
     return B @ kern @ B.T
 
 
-def scatter_rows_addition(patches, moments, q, chunk=4096):
-    """Rows 3q..3q+2 of S~ through the addition theorem, accumulating the
-    Legendre sum by its three-term recurrence over chunks of quadrature
-    points (for meshes where the dense kernel would not fit in memory)."""
+def scatter_rows_addition(patches, moments, q, chunk=4096, basis="lin"):
+    """Rows of patch q (3q..3q+2 for Lin) of S~ through the addition theorem,
+    accumulating the Legendre sum by its three-term recurrence over chunks
+    of quadrature points (for meshes where the dense kernel would not fit in
+    memory)."""
+    fn, nd = BASES[basis]
     moments = np.asarray(moments, dtype=np.float64)
     L = len(moments) - 1
     coef = moments * (2 * np.arange(L + 1) + 1) / (4 * math.pi)
     om_q, w_q = quad_accurate(patches[q], L)
-    bq = (lin_basis(patches[q], om_q) * w_q[:, None]).T          # (3, nq)
-    rows = np.zeros((3, 3 * len(patches)))
+    bq = (fn(patches[q], om_q) * w_q[:, None]).T                 # (nd, nq)
+    rows = np.zeros((nd, nd * len(patches)))
     for p, patch in enumerate(patches):
         om_p, w_p = quad_accurate(patch, L)
-        bp = (lin_basis(patch, om_p) * w_p[:, None]).T          # (3, np)
+        bp = (fn(patch, om_p) * w_p[:, None]).T                 # (nd, np)
         for c0 in range(0, len(w_p), chunk):
             mu = np.clip(om_q @ om_p[c0:c0 + chunk].T, -1.0, 1.0)
             p0, p1 = np.ones_like(mu), mu
@@ -440,7 +471,7 @@ def scatter_rows_addition(patches, moments, q, chunk=4096):
             for n in range(1, L):
                 p0, p1 = p1, ((2 * n + 1) * mu * p1 - n * p0) / (n + 1)
                 kern = kern + coef[n + 1] * p1
-            rows[:, 3 * p:3 * p + 3] += bq @ kern @ bp[:, c0:c0 + chunk].T
+            rows[:, nd * p:nd * p + nd] += bq @ kern @ bp[:, c0:c0 + chunk].T
     return rows
 
 
@@ -456,17 +487,22 @@ def fp_moments(alpha, N):
 
 # ------------------------------------------------------------ prolongation
 
-def prolongation(coarse, fine):
-    """Galerkin prolongation between nested Lin spaces (Section 4.1).  Each
-    fine patch is either a coarse patch itself or a daughter of one; the
-    coarse Lin functions are linear on the common projection plane, so the
-    fine nodal coefficients are the coarse functions evaluated at the fine
-    vertices.  Returns the dense (3 P_fine) x (3 P_coarse) matrix."""
+def prolongation(coarse, fine, basis="lin"):
+    """Galerkin prolongation between nested angular spaces (Section 4.1).
+    Each fine patch is either a coarse patch itself or a daughter of one.
+    Lin: the coarse functions are linear on the common projection plane, so
+    the fine nodal coefficients are the coarse functions evaluated at the
+    fine vertices.  Const: a daughter takes its parent's value.  Returns the
+    dense (nd P_fine) x (nd P_coarse) matrix."""
+    nd = basis_dofs(basis)
     index = {id(p): i for i, p in enumerate(coarse)}
     cut = max(p.level for p in coarse)
-    P = np.zeros((3 * len(fine), 3 * len(coarse)))
+    P = np.zeros((nd * len(fine), nd * len(coarse)))
     for c, p in enumerate(fine):
         owner = p if id(p) in index else p.ancestor_at(cut)
         o = index[id(owner)]
-        P[3 * c:3 * c + 3, 3 * o:3 * o + 3] = lin_basis(owner, p.verts)
+        if basis == "lin":
+            P[3 * c:3 * c + 3, 3 * o:3 * o + 3] = lin_basis(owner, p.verts)
+        else:
+            P[c, o] = 1.0
     return P

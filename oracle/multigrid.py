@@ -2,7 +2,8 @@
 
 Section 4 and Fig. lmg: the recursive linear V-cycle LMG(phi_l, f_l, l) with
 source-iteration smoothing L_l phi^{k+1} = S_l phi^k + f_l, restriction
-R = P^T, Galerkin prolongation P between the nested Lin spaces, coarse
+R = P^T, Galerkin prolongation P between the nested angular spaces (Lin or
+Const basis), coarse
 operators by direct rediscretisation on T_l (DCA), and on T_0 the block
 Gauss-Seidel sweep of Section 5.2: every (cell, patch) block is solved with
 its own scatter coupling implicit and all other unknowns at their latest
@@ -28,16 +29,16 @@ from .transport import Level
 class AngularMG:
     def __init__(self, grid, mesh, sigma_t, sigma_s, moments, orders,
                  nu_pre=1, nu_post=1, nu_coarse=10, octant_order=tuple(range(8)),
-                 rule=ang.quad3):
+                 rule=None, basis="lin"):
         self.grid = grid
         self.T = mesh.levels()
         self.nlev = len(self.T)
         if len(orders) != self.nlev:
             raise ValueError("one scatter order per level T_0..T_L is required")
         moments = np.asarray(moments, dtype=np.float64)
-        self.levels = [Level(grid, self.T[l], sigma_t, sigma_s, moments[:orders[l] + 1], rule)
+        self.levels = [Level(grid, self.T[l], sigma_t, sigma_s, moments[:orders[l] + 1], rule, basis)
                        for l in range(self.nlev)]
-        self.P = [None] + [ang.prolongation(self.T[l - 1], self.T[l]) for l in range(1, self.nlev)]
+        self.P = [None] + [ang.prolongation(self.T[l - 1], self.T[l], basis) for l in range(1, self.nlev)]
         self.nu_pre, self.nu_post, self.nu_coarse = nu_pre, nu_post, nu_coarse
         self.octant_order = tuple(octant_order)
 
@@ -58,7 +59,7 @@ class AngularMG:
         nu = self.nu_coarse if nu is None else nu
         lv = self.levels[0]
         g = self.grid
-        ns = g.ns
+        ns, nd = g.ns, lv.nd
         fb = lv.blocks(f)
         phi = np.zeros_like(fb)
         St = lv.Stilde
@@ -70,16 +71,16 @@ class AngularMG:
                     planes = planes[::-1]
                 for J in planes:
                     for q in Q:
-                        self_sc = np.kron(St[3 * q:3 * q + 3, 3 * q:3 * q + 3], g.N)
+                        self_sc = np.kron(St[nd * q:nd * q + nd, nd * q:nd * q + nd], g.N)
                         K = (lv.K_stream[q][None] + lv.sigma_t[J][:, None, None] * lv.K_mass[q][None]
                              - lv.sigma_s[J][:, None, None] * self_sc[None])
                         rhs = fb[q][J].copy()
                         for p in range(lv.P):
                             if p == q:
                                 continue
-                            blk = np.kron(St[3 * q:3 * q + 3, 3 * p:3 * p + 3], g.N)
+                            blk = np.kron(St[nd * q:nd * q + nd, nd * p:nd * p + nd], g.N)
                             if adjoint:
-                                blk = np.kron(St[3 * p:3 * p + 3, 3 * q:3 * q + 3], g.N).T
+                                blk = np.kron(St[nd * p:nd * p + nd, nd * q:nd * q + nd], g.N).T
                             rhs += lv.sigma_s[J][:, None] * (phi[p][J] @ blk.T)
                         for xi, side, Cm in lv.couple[q]:
                             if not adjoint:

@@ -2,9 +2,10 @@
 infrastructure only).
 
 Unknowns phi_{[j,q]}^{i,d} (eq. Expansion) are stored flat with index
-a * S + j * ns + i, a = 3 q + d the angular dof (patch-major), j the cell,
-i the spatial node.  A (j,q) block is ordered (d, i) -> d * ns + i, so an
-angular factor A and a spatial factor F combine as kron(A, F).
+a * S + j * ns + i, a = nd q + d the angular dof (patch-major; nd = 3 for
+the Lin basis, 1 for Const), j the cell, i the spatial node.  A (j,q)
+block is ordered (d, i) -> d * ns + i, so an angular factor A and a
+spatial factor F combine as kron(A, F).
 
 The weak form is eq. complete with eq. Surface_Integral: face streaming
 term, volume streaming term -sum_xi V_xi (x) A^xi, removal N (x) M, and the
@@ -27,23 +28,25 @@ class Level:
     """Transport operator L, scatter operator S and source terms on the
     angular mesh ``patches`` for a Cartesian ``grid``."""
 
-    def __init__(self, grid, patches, sigma_t, sigma_s, moments, rule=ang.quad3):
+    def __init__(self, grid, patches, sigma_t, sigma_s, moments, rule=None, basis="lin"):
         self.grid = grid
         self.patches = patches
+        self.basis = basis
+        self.nd = ang.basis_dofs(basis)
         self.P = len(patches)
-        self.A = 3 * self.P
+        self.A = self.nd * self.P
         self.sigma_t = np.asarray(sigma_t, dtype=np.float64)
         self.sigma_s = np.asarray(sigma_s, dtype=np.float64)
         self.moments = np.asarray(moments, dtype=np.float64)
-        self.rule = ang.PatchRule(patches, rule)
+        self.rule = ang.PatchRule(patches, rule, basis)
         self.signs = [ang.octant_signs(p.octant) for p in patches]
         d, ns = grid.dim, grid.ns
         self.Mq = [self.rule.mass(q) for q in range(self.P)]
         self.Aq = [[self.rule.jacobian(q, xi) for xi in range(3)] for q in range(self.P)]
-        self.Stilde = ang.scatter_matrix(patches, self.moments)
+        self.Stilde = ang.scatter_matrix(patches, self.moments, basis)
         self.K_stream, self.K_mass, self.couple = [], [], []
         for q in range(self.P):
-            K = np.zeros((3 * ns, 3 * ns))
+            K = np.zeros((self.nd * ns, self.nd * ns))
             cpl = []
             for xi in range(d):
                 Ax = self.Aq[q][xi]
@@ -63,13 +66,13 @@ class Level:
 
     # --------------------------------------------------------- layouts
     def blocks(self, x):
-        """flat (A*S,) -> (P, C, 3*ns) per-(cell, patch) blocks."""
-        g = self.grid
-        return x.reshape(self.P, 3, g.C, g.ns).transpose(0, 2, 1, 3).reshape(self.P, g.C, 3 * g.ns)
+        """flat (A*S,) -> (P, C, nd*ns) per-(cell, patch) blocks."""
+        g, nd = self.grid, self.nd
+        return x.reshape(self.P, nd, g.C, g.ns).transpose(0, 2, 1, 3).reshape(self.P, g.C, nd * g.ns)
 
     def flat(self, b):
-        g = self.grid
-        return b.reshape(self.P, g.C, 3, g.ns).transpose(0, 2, 1, 3).reshape(-1).copy()
+        g, nd = self.grid, self.nd
+        return b.reshape(self.P, g.C, nd, g.ns).transpose(0, 2, 1, 3).reshape(-1).copy()
 
     # --------------------------------------------------------- operators
     def apply_L(self, x):
@@ -119,7 +122,7 @@ class Level:
 
     def sweep(self, g_rhs):
         """phi = L^{-1} g: octant by octant, cells in upwind plane order, one
-        coupled (3 ns) x (3 ns) local solve per (cell, patch) (Section 3)."""
+        coupled (nd ns) x (nd ns) local solve per (cell, patch) (Section 3)."""
         gb = self.blocks(g_rhs)
         phi = np.zeros_like(gb)
         for o in range(8):
@@ -193,14 +196,15 @@ class Level:
                 continue
             sel = self.rule.owner == q
             om_psi = self.rule.psi[q].T @ (self.rule.w[sel] * self.rule.omega[sel, xi])
-            for m in range(3):
-                b[3 * q + m][cells] += -sigma_f * value * om_psi[m] * fi[None, :]
+            for m in range(self.nd):
+                b[self.nd * q + m][cells] += -sigma_f * value * om_psi[m] * fi[None, :]
         return b.reshape(-1)
 
     def rhs_beam(self, direction, xi, side, lo, hi, current=1.0):
         """Dirac beam in space-angle entering through face (xi, side): unit
         current per area in ``direction``.  The angular Dirac is split
-        equally over every patch whose closure contains the direction."""
+        equally over every patch whose closure contains the direction (the
+        Lin functions' values there; the Const function is 1)."""
         g = self.grid
         d = np.asarray(direction, float)
         d = d / np.linalg.norm(d)
@@ -210,13 +214,13 @@ class Level:
                 continue
             lam = ang.lin_basis(p, d[None, :])[0]
             if (lam >= -1e-12).all():
-                hits.append((q, lam))
+                hits.append((q, lam if self.nd == 3 else np.ones(1)))
         b = np.zeros((self.A, g.C, g.ns))
         cells = self._face_cells(xi, side, lo, hi)
         fi = g.face_int[xi][side]
         for q, lam in hits:
-            for m in range(3):
-                b[3 * q + m][cells] += current * lam[m] / len(hits) * fi[None, :]
+            for m in range(self.nd):
+                b[self.nd * q + m][cells] += current * lam[m] / len(hits) * fi[None, :]
         return b.reshape(-1)
 
     def detector_weights(self, lo, hi):

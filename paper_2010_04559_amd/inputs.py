@@ -21,13 +21,16 @@ class AngularSpec:
     """Uniform refinement to ``base_level``; optionally ``extra_levels`` more
     inside a cone of ``cone_half_angle_deg`` around ``cone_axis`` with the
     two-irregularity closure; or (band_lmax > 0) the z-band rule of the
-    paper's pencil-beam study (levels band_lmax .. band_lmax - 4)."""
+    paper's pencil-beam study (levels band_lmax .. band_lmax - 4).
+    ``basis``: the angular basis of Section 2.2, "lin" (three functions per
+    patch) or "const" (one)."""
     base_level: int = 1
     cone_axis: Tuple[float, float, float] = (1.0, 0.0, 0.0)
     cone_half_angle_deg: float = 0.0
     extra_levels: int = 0
     closure: bool = True
     band_lmax: int = 0
+    basis: str = "lin"
 
     @property
     def n_levels(self):

@@ -28,13 +28,14 @@ class OracleProblem:
         self.grid = sp.Grid(prob.dim, prob.n, prob.length)
         self.mesh = angular_mesh(prob.angular)
         self.T = self.mesh.levels()
-        self.outer = tr.Level(self.grid, self.T[-1], prob.sigma_t, prob.sigma_s, prob.moments())
+        basis = getattr(prob.angular, "basis", "lin")
+        self.outer = tr.Level(self.grid, self.T[-1], prob.sigma_t, prob.sigma_s, prob.moments(), basis=basis)
         self.mg = None
         if with_mg:
             full = prob.moments(max(prob.mg_orders))
             self.mg = mgm.AngularMG(self.grid, self.mesh, prob.sigma_t, prob.sigma_s, full,
                                     prob.mg_orders, prob.nu_pre, prob.nu_post, prob.nu_coarse,
-                                    octant_order=prob.octant_order)
+                                    octant_order=prob.octant_order, basis=basis)
 
     def rhs(self):
         p, lv = self.prob, self.outer
