@@ -96,7 +96,21 @@ typedef struct {
   int nu_pre, nu_post;          /* V(nu_pre, nu_post) smoothing (Fig. lmg), >= 1, >= 0 */
   int nu_coarse;                /* Gauss-Seidel sweeps on T_0 (Section 5.2)      */
   int octant_order[8];          /* Gauss-Seidel octant order (a permutation)     */
+  int angular_basis;            /* TR_BASIS_LIN or TR_BASIS_CONST (Section 2.2)  */
 } tr_problem;
+
+/* Angular basis (Section 2.2).  LIN: the three nodal functions of a patch.
+ * CONST: one constant per patch, carried by the Lin data layout and kernels
+ * as three coincident ordinates (the patch's mean direction int_q Omega /
+ * |q|, a third of its area each) that hold equal values: a Const function
+ * c_q is the vector with all three coefficients of patch q equal to c_q,
+ * and a Const weak-form vector (right-hand side, residual, detector
+ * weights) has a third of the Const entry in each of the three.  Every
+ * operator maps such vectors to such vectors, and restricted to them is
+ * exactly the Const discretisation (transport terms and X integrals
+ * integrated to round-off, daughters taking their parent's value).  The
+ * layout triples the work of a one-dof-per-patch path. */
+enum { TR_BASIS_LIN = 0, TR_BASIS_CONST = 1 };
 
 /* how a level's scatter product G_l u is formed (multiply-adds per spatial
  * dof): DENSE 2 A^2; FACTORED through the K = (order+1)^2 harmonics, 4 A K;

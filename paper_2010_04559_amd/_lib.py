@@ -17,6 +17,7 @@ TR_INFLOW_NONE, TR_INFLOW_ISO, TR_INFLOW_BEAM = 0, 1, 2
 TR_RESTRICT, TR_PROLONG = 0, 1
 TR_Z_AUTO, TR_Z_KEEP, TR_Z_RECOMPUTE = 0, 1, 2
 TR_SCATTER_DENSE, TR_SCATTER_FACTORED, TR_SCATTER_OCTANT = 0, 1, 2
+TR_BASIS_LIN, TR_BASIS_CONST = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -29,7 +30,7 @@ class TrProblem(ctypes.Structure):
                 ("irregularity_closure", ctypes.c_int), ("band_lmax", ctypes.c_int), ("sigma_t", _dp), ("sigma_s", _dp),
                 ("order", ctypes.c_int), ("moments", _dp), ("n_levels", ctypes.c_int),
                 ("mg_order", _ip), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
-                ("nu_coarse", ctypes.c_int), ("octant_order", ctypes.c_int * 8)]
+                ("nu_coarse", ctypes.c_int), ("octant_order", ctypes.c_int * 8), ("angular_basis", ctypes.c_int)]
 
 
 class TrInfo(ctypes.Structure):

@@ -220,7 +220,7 @@ void lin_basis(const PatchNode &p, const V3 &om, double psi[3]) {
   psi[2] = dot(f0, cross(f1, x)) / det;
 }
 
-void patch_x_integrals(const PatchNode &p, int order, std::vector<double> &X) {
+void patch_x_integrals(const PatchNode &p, int order, std::vector<double> &X, bool const_basis) {
   const int K = (order + 1) * (order + 1);
   X.assign(3 * K, 0.0);
   std::vector<V3> pts;
@@ -228,8 +228,8 @@ void patch_x_integrals(const PatchNode &p, int order, std::vector<double> &X) {
   accurate_rule(p, order, pts, wts);
   std::vector<double> Y(K);
   for (size_t t = 0; t < pts.size(); ++t) {
-    double psi[3];
-    lin_basis(p, pts[t], psi);
+    double psi[3] = {1.0 / 3, 1.0 / 3, 1.0 / 3};
+    if (!const_basis) lin_basis(p, pts[t], psi);
     real_harmonics(order, pts[t], Y.data());
     for (int m = 0; m < 3; ++m) {
       double c = wts[t] * psi[m];
@@ -248,7 +248,7 @@ void scatter_matrix(const HostAngular &ang, int level, const std::vector<double>
 #pragma omp parallel for schedule(dynamic)
   for (int q = 0; q < L.P; ++q) {
     std::vector<double> Xq;
-    patch_x_integrals(ang.tree[L.node[q]], order, Xq);
+    patch_x_integrals(ang.tree[L.node[q]], order, Xq, ang.const_basis);
     std::copy(Xq.begin(), Xq.end(), X.begin() + (size_t)3 * q * K);
   }
   std::vector<double> F(K);
@@ -313,6 +313,7 @@ bool build_angular(const RefineSpec &spec, HostAngular &out, std::string &err) {
   int maxlev = 0;
   for (int i : leaves(t, 1 << 30)) maxlev = std::max(maxlev, t[i].level);
   out.lv.assign(maxlev + 1, HostLevel());
+  out.const_basis = spec.const_basis;
 
   const double Psi[3][3] = {{4.0 / 6, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 4.0 / 6, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 4.0 / 6}};
   for (int l = 0; l <= maxlev; ++l) {
@@ -340,17 +341,36 @@ bool build_angular(const RefineSpec &spec, HostAngular &out, std::string &err) {
         lin_basis(p, pts[k], ps);
         for (int m = 0; m < 3; ++m) ip[m] += wts[k] * ps[m];
       }
-      for (int m = 0; m < 3; ++m) L.ipsi[3 * q + m] = ip[m];
-      // 3-point rule: barycentric (2/3, 1/6, 1/6); psi_d(Omega_k) = Psi[k][d];
-      // weights w = Psi^{-1} int psi (Psi^{-1} = 2 I - J / 3)
       double sum_ip = ip[0] + ip[1] + ip[2];
-      for (int k = 0; k < 3; ++k) {
-        V3 x = add(add(scale(f[0], Psi[k][0]), scale(f[1], Psi[k][1])), scale(f[2], Psi[k][2]));
-        V3 om = unit(x);
-        L.omega[3 * (3 * q + k) + 0] = om.x;
-        L.omega[3 * (3 * q + k) + 1] = om.y;
-        L.omega[3 * (3 * q + k) + 2] = om.z;
-        L.w[3 * q + k] = 2.0 * ip[k] - sum_ip / 3.0;
+      if (spec.const_basis) {
+        // Const: three coincident ordinates at the mean direction
+        // int_q Omega / |q| (not a unit vector), a third of |q| each
+        V3 mo{0, 0, 0};
+        double area = 0;
+        for (size_t k = 0; k < pts.size(); ++k) {
+          mo = add(mo, scale(pts[k], wts[k]));
+          area += wts[k];
+        }
+        const V3 om = scale(mo, 1.0 / area);
+        for (int k = 0; k < 3; ++k) {
+          L.ipsi[3 * q + k] = area / 3.0;
+          L.omega[3 * (3 * q + k) + 0] = om.x;
+          L.omega[3 * (3 * q + k) + 1] = om.y;
+          L.omega[3 * (3 * q + k) + 2] = om.z;
+          L.w[3 * q + k] = area / 3.0;
+        }
+      } else {
+        for (int m = 0; m < 3; ++m) L.ipsi[3 * q + m] = ip[m];
+        // 3-point rule: barycentric (2/3, 1/6, 1/6); psi_d(Omega_k) = Psi[k][d];
+        // weights w = Psi^{-1} int psi (Psi^{-1} = 2 I - J / 3)
+        for (int k = 0; k < 3; ++k) {
+          V3 x = add(add(scale(f[0], Psi[k][0]), scale(f[1], Psi[k][1])), scale(f[2], Psi[k][2]));
+          V3 om = unit(x);
+          L.omega[3 * (3 * q + k) + 0] = om.x;
+          L.omega[3 * (3 * q + k) + 1] = om.y;
+          L.omega[3 * (3 * q + k) + 2] = om.z;
+          L.w[3 * q + k] = 2.0 * ip[k] - sum_ip / 3.0;
+        }
       }
       for (int m = 0; m < 3; ++m)
         for (int xi = 0; xi < 3; ++xi) {
@@ -383,8 +403,8 @@ bool build_angular(const RefineSpec &spec, HostAngular &out, std::string &err) {
             }
             L.owner[c] = p;
             for (int e = 0; e < 3; ++e) {
-              double ps[3];
-              lin_basis(t[nd], t[L.node[c]].v[e], ps);
+              double ps[3] = {1.0 / 3, 1.0 / 3, 1.0 / 3};  // Const: the parent's value
+              if (!spec.const_basis) lin_basis(t[nd], t[L.node[c]].v[e], ps);
               for (int d = 0; d < 3; ++d) L.pblk[(size_t)c * 9 + e * 3 + d] = ps[d];
             }
           }

@@ -34,6 +34,9 @@ struct RefineSpec {
   // 0.9, two less above 0.8, three less above 0.6, four less elsewhere
   // (at least 0)
   int band_lmax = 0;
+  // the Const basis of Section 2.2 carried as three coincident ordinates
+  // per patch (mean direction, a third of the area each; see tr.h)
+  bool const_basis = false;
 };
 
 // One nested angular mesh T_l with everything the kernels need.
@@ -55,6 +58,7 @@ struct HostLevel {
 struct HostAngular {
   std::vector<PatchNode> tree;
   std::vector<HostLevel> lv;        // T_0 .. T_L
+  bool const_basis = false;
 };
 
 // Build the tree and levels.  Returns false with a message on bad input.
@@ -68,8 +72,10 @@ void scatter_matrix(const HostAngular &ang, int level, const std::vector<double>
                     std::vector<double> &St, std::vector<double> *Xout = nullptr);
 
 // Accurate integral of psi_m * Y_{n,o} over a patch for n <= order; used
-// for the X integrals.  X is [3][(order+1)^2].
-void patch_x_integrals(const PatchNode &p, int order, std::vector<double> &X);
+// for the X integrals.  X is [3][(order+1)^2].  With const_basis every row
+// is a third of int_q Y_{n,o} (the Const function split over the three
+// coincident ordinates).
+void patch_x_integrals(const PatchNode &p, int order, std::vector<double> &X, bool const_basis = false);
 
 // Lin basis values psi_d(omega) of a patch (barycentric coordinates of the
 // gnomonic projection).

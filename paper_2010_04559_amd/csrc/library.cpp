@@ -452,6 +452,9 @@ void build(tr_handle *h, const tr_problem *p) {
   spec.cone_extra_levels = p->cone_extra_levels;
   spec.closure = p->irregularity_closure != 0;
   spec.band_lmax = p->band_lmax;
+  if (p->angular_basis != TR_BASIS_LIN && p->angular_basis != TR_BASIS_CONST)
+    throw ArgError{"angular_basis must be TR_BASIS_LIN or TR_BASIS_CONST"};
+  spec.const_basis = p->angular_basis == TR_BASIS_CONST;
   if (spec.cone_extra_levels > 0 &&
       !(std::fabs(spec.cone_axis.x) + std::fabs(spec.cone_axis.y) + std::fabs(spec.cone_axis.z) > 0))
     throw ArgError{"cone axis must be nonzero"};
@@ -1950,8 +1953,12 @@ int tr_rhs(tr_handle *h, const double *q_cell, const tr_inflow *in, double *b, t
         tr::lin_basis(pn, d, psi);
         if (psi[0] >= -1e-12 && psi[1] >= -1e-12 && psi[2] >= -1e-12) hits.push_back({q, {psi[0], psi[1], psi[2]}});
       }
+      // Lin: the patch functions' values at the direction; Const: the
+      // constant 1, a third in each of the three coincident ordinates
       for (auto &hq : hits)
-        for (int m = 0; m < 3; ++m) coef[3 * hq.first + m] = in->value * hq.second[m] / (double)hits.size();
+        for (int m = 0; m < 3; ++m)
+          coef[3 * hq.first + m] =
+              in->value * (h->ang.const_basis ? 1.0 / 3.0 : hq.second[m]) / (double)hits.size();
     }
     TmpBuf tcoef(D.A * sizeof(double)), tcells(cells.size() * sizeof(int)), tfint(g.ns * sizeof(double));
     double *dcoef = tcoef.as<double>(), *dfint = tfint.as<double>();

@@ -225,7 +225,9 @@ def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=Tru
     nlev = spec.n_levels
     mg = mg_orders if mg_orders is not None else [order] * nlev
     tag = (f"ang{level}" if angular is None else f"band{spec.band_lmax}" if spec.band_lmax
-           else f"cone{spec.base_level}+{spec.extra_levels}")
+           else f"cone{spec.base_level}+{spec.extra_levels}" if spec.extra_levels else f"ang{spec.base_level}")
+    if spec.basis != "lin":
+        tag += "-" + spec.basis
     return Problem(f"small-{dim}d-{n}-{tag}-L{order}-s{seed}", dim, nn, spec,
                    st, ss, g, order, mg, q, Inflow("iso", 0, 0, value=1.0) if inflow else None,
                    restart=restart)
@@ -234,7 +236,7 @@ def small_problem(dim=2, n=4, level=1, g=0.8, order=4, c=0.9, seed=0, inflow=Tru
 # ------------------------------------------------------ the paper's workloads
 
 def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_lmax=0, restart=20,
-              nr_levels="all", nu_coarse=10):
+              nr_levels="all", nu_coarse=10, basis="lin"):
     """The cube of the paper's Section 5 experiments: 5 x 5 x 5 cm, n^3
     hexahedra (30^3 in the paper), vacuum boundaries, Fokker-Planck-
     equivalent scatter moments of order N with transport cross section 1
@@ -248,12 +250,13 @@ def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_l
     preconditioner level (``nr_levels="all"``, Sections 5.3-5.5) or on the
     coarsest level only with N elsewhere (``"coarsest"``, the Section 5.1
     study); the problem operator keeps order N.  ``nu_coarse`` Gauss-Seidel
-    sweeps on the coarsest level (10 in Sections 5.3-5.5)."""
+    sweeps on the coarsest level (10 in Sections 5.3-5.5).  ``basis``: the
+    angular basis, "lin" or "const" (both studied in Section 5)."""
     nn = (n, n, n)
     C = n ** 3
     sig = 0.5 * N * (N + 1)
     st = np.full(C, sig)
-    spec = AngularSpec(level) if not band_lmax else AngularSpec(0, band_lmax=band_lmax)
+    spec = AngularSpec(level, basis=basis) if not band_lmax else AngularSpec(0, band_lmax=band_lmax, basis=basis)
     nlev = spec.n_levels
     nr = N if nr is None else nr
     if nr_levels == "all":
@@ -262,9 +265,9 @@ def paper_box(N, level=3, nr=None, n=30, nu_pre=1, nu_post=1, beam=False, band_l
         mg = [nr] + [N] * (nlev - 1)
     else:
         raise ValueError("nr_levels is 'all' or 'coarsest'")
-    name = "paper-box-%d^3-N%d-%s-nr%d%s-V%d%d-gs%d" % (n, N, ("band%d" % band_lmax) if band_lmax else ("lev%d" % level),
-                                                      nr, "c" if nr_levels == "coarsest" else "", nu_pre, nu_post,
-                                                      nu_coarse)
+    name = "paper-box-%d^3-N%d-%s-nr%d%s-V%d%d-gs%d-%s" % (
+        n, N, ("band%d" % band_lmax) if band_lmax else ("lev%d" % level), nr, "c" if nr_levels == "coarsest" else "",
+        nu_pre, nu_post, nu_coarse, basis)
     inflow = None
     q = np.ones(C)
     if beam:

@@ -32,6 +32,10 @@ def problem_struct(prob: Problem):
     p.cone_extra_levels = int(a.extra_levels)
     p.irregularity_closure = 1 if a.closure else 0
     p.band_lmax = int(a.band_lmax)
+    bases = {"lin": _lib.TR_BASIS_LIN, "const": _lib.TR_BASIS_CONST}
+    if a.basis not in bases:
+        raise ValueError("angular basis is 'lin' or 'const'")
+    p.angular_basis = bases[a.basis]
     st = np.ascontiguousarray(prob.sigma_t, dtype=np.float64)
     ss = np.ascontiguousarray(prob.sigma_s, dtype=np.float64)
     mom = np.ascontiguousarray(prob.moments(max([prob.order] + list(prob.mg_orders))), dtype=np.float64)

@@ -3,7 +3,8 @@
 // builds the patch tree and levels for a refinement spec, forms the finest
 // level's scatter matrix for HG moments, and writes every table as raw
 // doubles (each array preceded by its length as a double).
-//   setup_dump base cone_x cone_y cone_z half_angle extra closure band_lmax order g out.bin
+//   setup_dump base cone_x cone_y cone_z half_angle extra closure band_lmax order g basis out.bin
+// (basis 0 = Lin, 1 = Const)
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -18,8 +19,8 @@ static void put(FILE *f, const std::vector<double> &v) {
 }
 
 int main(int argc, char **argv) {
-  if (argc != 12) {
-    std::fprintf(stderr, "usage: setup_dump base cx cy cz half extra closure band order g out\n");
+  if (argc != 13) {
+    std::fprintf(stderr, "usage: setup_dump base cx cy cz half extra closure band order g basis out\n");
     return 2;
   }
   tr::RefineSpec spec;
@@ -31,13 +32,14 @@ int main(int argc, char **argv) {
   spec.band_lmax = std::atoi(argv[8]);
   const int order = std::atoi(argv[9]);
   const double g = std::atof(argv[10]);
+  spec.const_basis = std::atoi(argv[11]) != 0;
   tr::HostAngular ang;
   std::string err;
   if (!tr::build_angular(spec, ang, err)) {
     std::fprintf(stderr, "build_angular: %s\n", err.c_str());
     return 1;
   }
-  FILE *f = std::fopen(argv[11], "wb");
+  FILE *f = std::fopen(argv[12], "wb");
   if (!f) return 1;
   put(f, {(double)ang.lv.size()});
   for (const tr::HostLevel &L : ang.lv) {

@@ -110,6 +110,17 @@ def test_setup_rejects_bad_octant_order():
         problem_struct(replace(_small(), octant_order=(0, 1, 2, 3, 4, 5, 6, 6)))
 
 
+def test_setup_rejects_unknown_angular_basis():
+    from paper_2010_04559_amd import _lib
+    from paper_2010_04559_amd.transport import problem_struct
+    L = _lib.load()
+    p, keep = problem_struct(_small())
+    p.angular_basis = 2
+    h = ctypes.c_void_p()
+    assert L.tr_setup(ctypes.byref(p), ctypes.byref(h)) == _lib.TR_ERR_ARG
+    assert b"angular_basis" in L.tr_last_error() and not h.value
+
+
 @pytest.mark.parametrize("orders", [[4, 97], [-1, 4]])
 def test_setup_rejects_mg_order_out_of_range(orders):
     from dataclasses import replace

@@ -100,7 +100,7 @@ def test_band_meshes_match_the_paper_counts(setup_dump):
     rows = [tuple(int(v) for v in line.split()) for line in open(os.path.join(HERE, "golden", "band_mesh_counts.txt"))
             if line.strip() and not line.startswith("#")]
     for lmax, count in rows:
-        levels, _ = _run_dump(setup_dump, (0, 0, 0, 1, 0, 0, 0, lmax, 0, 0.5))
+        levels, _ = _run_dump(setup_dump, (0, 0, 0, 1, 0, 0, 0, lmax, 0, 0.5, 0))
         assert levels[-1]["P"] == count, (lmax, levels[-1]["P"])
         assert len(levels) == lmax + 1
 
@@ -135,7 +135,7 @@ def _run_dump(setup_dump, args):
                                   (1, 0.3, 0.5, 0.81, 25.0, 2, 1, 0, 4, 0.8), (0, 0, 0, 1, 0, 0, 0, 3, 6, 0.9)])
 def test_setup_tables_match_oracle(setup_dump, spec):
     base, cx, cy, cz, half, extra, closure, band, order, g = spec
-    levels, St = _run_dump(setup_dump, spec)
+    levels, St = _run_dump(setup_dump, spec + (0,))
     if band:
         mesh = ang.AngularMesh.band_z(band)
     elif extra:
@@ -166,3 +166,39 @@ def test_setup_tables_match_oracle(setup_dump, spec):
     ref = ang.scatter_matrix(T[-1], ang.hg_moments(g, order))
     A = ref.shape[0]
     assert np.abs(St.reshape(A, A) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("spec", [(1, 0, 0, 1, 0, 0, 1, 0, 6, 0.9), (1, 1, 0, 0, 15.0, 2, 1, 0, 4, 0.85),
+                                  (0, 0, 0, 1, 0, 0, 0, 2, 5, 0.8)])
+def test_const_setup_tables_match_oracle(setup_dump, spec):
+    """The Const basis carried as three coincident ordinates: each patch's
+    ordinates are the oracle's mean direction int_q Omega / |q| with a third
+    of |q| each, its X rows a third of int_q Y (so S~ is the oracle's Const
+    scatter matrix over 9 in every 3x3 block), and a daughter's
+    prolongation block is J / 3 (the parent's value in all three)."""
+    base, cx, cy, cz, half, extra, closure, band, order, g = spec
+    levels, St = _run_dump(setup_dump, spec + (1,))
+    if band:
+        mesh = ang.AngularMesh.band_z(band)
+    elif extra:
+        mesh = ang.AngularMesh.cone((cx, cy, cz), half, base, extra, closure=bool(closure))
+    else:
+        mesh = ang.AngularMesh.uniform(base)
+    T = mesh.levels()
+    for l, (L, patches) in enumerate(zip(levels, T)):
+        rule = ang.PatchRule(patches, basis="const")
+        for q in range(len(patches)):
+            area = rule.mass(q)[0, 0]
+            mean = np.array([rule.jacobian(q, xi)[0, 0] for xi in range(3)]) / area
+            for k in range(3):
+                assert np.abs(L["omega"][3 * q + k] - mean).max() < 1e-14
+                assert abs(L["w"][3 * q + k] - area / 3) < 1e-14 * area
+                assert abs(L["ipsi"][3 * q + k] - area / 3) < 1e-14 * area
+                assert np.abs(L["iom"][3 * q + k] - mean * area / 3).max() < 1e-14
+        if l > 0:
+            for c in range(len(patches)):
+                blk = L["pblk"][c]
+                assert np.allclose(blk, np.full((3, 3), 1 / 3), rtol=0, atol=1e-15) or np.allclose(blk, np.eye(3))
+    ref = ang.scatter_matrix(T[-1], ang.hg_moments(g, order), basis="const")
+    A = 3 * len(T[-1])
+    assert np.abs(St.reshape(A, A) - np.kron(ref, np.ones((3, 3))) / 9).max() < 1e-13 * np.abs(ref).max()
