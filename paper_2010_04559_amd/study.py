@@ -6,7 +6,7 @@ moments of order N, transport cross section 1, no absorption), with either
 the single-grid sweep preconditioner (SG: one transport sweep per
 application) or the angular multigrid V(nu_pre, nu_post) cycle:
 
-* ``table1``: Section 5.1 (Table 1, Lin basis): uniform angular levels
+* ``table1``: Section 5.1 (Table 1, Lin or Const basis): uniform angular levels
   1-3, N = 4, 8, 16, SG and V(1,1) / V(2,1) with the coarse order N_r on
   the coarsest level only and an accurate coarse solve (``--nu-coarse``
   Gauss-Seidel sweeps; the paper solved it to 1e-5);
@@ -60,7 +60,8 @@ def solve_case(prob, mode, tol=1e-8, max_iters=2000, method="bicgstab"):
         return {"case": prob.name, "mode": mode, "method": method, "iters": st["iters"],
                 "converged": bool(st["converged"]), "rel_res": st["rel_res"], "solve_s": round(t_solve, 4),
                 "setup_s": round(t_setup, 3), "patches": tr.patches[-1], "levels": tr.nlev,
-                "dofs": 3 * tr.patches[-1] * prob.cells * 8, "mg_orders": list(prob.mg_orders),
+                "dofs": (3 if prob.angular.basis == "lin" else 1) * tr.patches[-1] * prob.cells * 8,
+                "basis": prob.angular.basis, "mg_orders": list(prob.mg_orders),
                 "nu": [prob.nu_pre, prob.nu_post, prob.nu_coarse]}
     finally:
         tr.close()
@@ -73,41 +74,42 @@ def _emit(rec, out):
     out.append(rec)
 
 
-def table1(n=30, levels=(1, 2, 3), Ns=(4, 8, 16), nrs=(0, 1, 2, 3), nu_coarse=40, out=None):
+def table1(n=30, levels=(1, 2, 3), Ns=(4, 8, 16), nrs=(0, 1, 2, 3), nu_coarse=40, basis="lin", out=None):
     out = [] if out is None else out
     for lev in levels:
         for N in Ns:
-            p = inputs.paper_box(N, level=lev, n=n, nu_coarse=nu_coarse)
+            p = inputs.paper_box(N, level=lev, n=n, nu_coarse=nu_coarse, basis=basis)
             _emit(dict(solve_case(p, "sg"), study="table1", level=lev, N=N, nr=None, cycle="SG"), out)
             for nr in nrs:
                 if nr >= N:
                     continue
                 for pre, post in ((1, 1), (2, 1)):
                     p = inputs.paper_box(N, level=lev, nr=nr, n=n, nu_pre=pre, nu_post=post, nr_levels="coarsest",
-                                         nu_coarse=nu_coarse)
+                                         nu_coarse=nu_coarse, basis=basis)
                     _emit(dict(solve_case(p, "f64"), study="table1", level=lev, N=N, nr=nr,
                                cycle="V(%d,%d)" % (pre, post)), out)
     return out
 
 
 def nr_effect(n=30, level=3, Ns=(4, 8, 12, 16, 20, 24), nu_coarse=10, nrs=(1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24),
-              out=None):
+              basis="lin", out=None):
     out = [] if out is None else out
     for N in Ns:
         for nr in sorted(set(v for v in nrs if v <= N) | {OPTIMAL_NR.get(N, N)}):
             for pre, post in ((1, 0), (1, 1)):
-                p = inputs.paper_box(N, level=level, nr=nr, n=n, nu_pre=pre, nu_post=post, nu_coarse=nu_coarse)
+                p = inputs.paper_box(N, level=level, nr=nr, n=n, nu_pre=pre, nu_post=post, nu_coarse=nu_coarse,
+                                     basis=basis)
                 _emit(dict(solve_case(p, "f64"), study="nr", level=level, N=N, nr=nr,
                            cycle="V(%d,%d)" % (pre, post)), out)
     return out
 
 
 def final(n=30, level=3, Ns=(4, 8, 12, 16, 20, 24), nu_coarse=10, sg_max_N=20, beam=False, lmaxs=(None,),
-          out=None):
+          basis="lin", out=None):
     out = [] if out is None else out
     for lmax in lmaxs:
         for N in Ns:
-            kw = dict(n=n, nu_coarse=nu_coarse, beam=beam, band_lmax=lmax or 0, level=level)
+            kw = dict(n=n, nu_coarse=nu_coarse, beam=beam, band_lmax=lmax or 0, level=level, basis=basis)
             if N <= sg_max_N:
                 p = inputs.paper_box(N, **kw)
                 _emit(dict(solve_case(p, "sg"), study="beam" if beam else "final", level=lmax or level, N=N,
@@ -121,11 +123,11 @@ def final(n=30, level=3, Ns=(4, 8, 12, 16, 20, 24), nu_coarse=10, sg_max_N=20, b
 
 def markdown(recs):
     """One row per (level, N, N_r, cycle): iterations and solve seconds."""
-    lines = ["| study | level | N | N_r | cycle | DoFs | iterations | solve s | converged |",
-             "|---|---|---|---|---|---|---|---|---|"]
+    lines = ["| study | basis | level | N | N_r | cycle | DoFs | iterations | solve s | converged |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
     for r in recs:
-        lines.append("| %s | %s | %d | %s | %s | %.3g | %d | %.3f | %s |" % (
-            r["study"], r["level"], r["N"], "-" if r["nr"] is None else r["nr"], r["cycle"], r["dofs"],
+        lines.append("| %s | %s | %s | %d | %s | %s | %.3g | %d | %.3f | %s |" % (
+            r["study"], r["basis"], r["level"], r["N"], "-" if r["nr"] is None else r["nr"], r["cycle"], r["dofs"],
             r["iters"], r["solve_s"], "yes" if r["converged"] else "no"))
     return "\n".join(lines)
 
@@ -138,19 +140,22 @@ def main(argv=None):
     ap.add_argument("--levels", default=None, help="comma-separated angular levels (table1) or l_max (beam)")
     ap.add_argument("--nu-coarse", type=int, default=None)
     ap.add_argument("--sg-max-N", type=int, default=20, help="largest N with a single-grid solve")
+    ap.add_argument("--basis", default="lin", choices=["lin", "const"], help="angular basis (Section 2.2)")
     a = ap.parse_args(argv)
     ints = lambda s: tuple(int(v) for v in s.split(","))
     if a.study == "table1":
         recs = table1(n=a.n, levels=ints(a.levels) if a.levels else (1, 2, 3), Ns=ints(a.N) if a.N else (4, 8, 16),
-                      nu_coarse=a.nu_coarse or 40)
+                      nu_coarse=a.nu_coarse or 40, basis=a.basis)
     elif a.study == "nr":
-        recs = nr_effect(n=a.n, Ns=ints(a.N) if a.N else (4, 8, 12, 16, 20, 24), nu_coarse=a.nu_coarse or 10)
+        recs = nr_effect(n=a.n, Ns=ints(a.N) if a.N else (4, 8, 12, 16, 20, 24), nu_coarse=a.nu_coarse or 10,
+                         basis=a.basis)
     elif a.study == "final":
         recs = final(n=a.n, Ns=ints(a.N) if a.N else (4, 8, 12, 16, 20, 24), nu_coarse=a.nu_coarse or 10,
-                     sg_max_N=a.sg_max_N)
+                     sg_max_N=a.sg_max_N, basis=a.basis)
     else:
         recs = final(n=a.n, Ns=ints(a.N) if a.N else (4, 8, 12, 16, 20, 24), nu_coarse=a.nu_coarse or 10,
-                     sg_max_N=a.sg_max_N, beam=True, lmaxs=ints(a.levels) if a.levels else (1, 2, 3, 4, 5, 6))
+                     sg_max_N=a.sg_max_N, beam=True, lmaxs=ints(a.levels) if a.levels else (1, 2, 3, 4, 5, 6),
+                     basis=a.basis)
     print(markdown(recs), flush=True)
     return 0
 
