@@ -76,6 +76,10 @@ bool sweep_lds_fits(const Planes &pl, const Grid &g, bool has_s);
 template <typename T>
 bool sweep_pair_fits(const Planes &bpl);
 
+// Workgroups of the brick Gauss-Seidel kernels that stay co-resident on the
+// current device (0 when no device answers).
+int coarse_brick_capacity();
+
 // Fill SweepArgs::sig_pl from the per-cell cross sections.
 void launch_sigma_planes(const double *sig_t, const double *sig_s, const Planes &pl, const Grid &g, double *out,
                          hipStream_t st);

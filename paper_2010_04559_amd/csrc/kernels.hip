@@ -3029,6 +3029,20 @@ void launch_coarse_brick(const double *f, double *u, const double *G, const doub
     throw std::runtime_error("cooperative launch of the Gauss-Seidel solve failed");
 }
 
+int coarse_brick_capacity() {
+  // workgroups of both brick kernels that stay co-resident on the device
+  // (0 without a device)
+  int dev = 0, ncu = 0, a = 0, b = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void *)k_gs_brick<false>, 192, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)k_gs_brick<true>, 192, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return ncu * std::min(a, b);
+}
+
 void launch_coarse_gs(const double *f, double *u, const double *G, const double *sig_t, const double *sig_s,
                       const OrdInfo *ord, const Planes &pl, const Grid &g, const int *step_off, const int *items,
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,

@@ -1067,10 +1067,14 @@ const tr_handle::GsSchedule &gs_schedule(tr_handle *h, int nu, bool adj) {
     int bmx = 0;
     for (auto &st : bsteps) bmx = std::max(bmx, (int)st.size());
     // two slot lists (one workgroup of three waves each) per brick of the
-    // widest step, at most 512 lists, which stay co-resident.  A list works
-    // its slots one after the other, so fewer lists lengthen the solve:
-    // 32^3 problem, 10 sweeps, 5.0 ms with 512 lists, 11.6 ms with 256
-    const int W = 2 * std::max(2, std::min(256, bmx));
+    // widest step, as many as stay co-resident (four per CU on MI355X: 1024;
+    // assumed without a device).  A list works its slots one after the
+    // other, so fewer lists lengthen the solve: 32^3 problem (widest step
+    // 256 bricks), 10 sweeps, 5.0 ms with 512 lists, 11.6 ms with 256; 48^3
+    // (widest step 576) 13.7 ms with 512 lists, 10.1 ms with 1024
+    static const int capacity = tr::coarse_brick_capacity();
+    const int cap = capacity > 0 ? capacity : 1024;
+    const int W = 2 * std::max(2, std::min(cap / 2, bmx));
     std::vector<std::vector<int>> lists(W);
     int next = 0;
     for (auto &st : bsteps)
