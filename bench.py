@@ -305,7 +305,7 @@ def main():
                          "(counter calibration), then the finest-level sweeps and scatter products of the workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU angular sharding is a design "
+        print("bench.py: runs on one GPU only (the multi-GPU angular sharding is a design "
               "note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.oracle_timings:

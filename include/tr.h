@@ -50,7 +50,7 @@ typedef void *tr_stream;
 enum {
   TR_OK = 0,
   TR_ERR_ARG = 1,          /* bad argument or inconsistent sizes            */
-  TR_ERR_UNSUPPORTED = 2,  /* valid request this build does not provide     */
+  TR_ERR_UNSUPPORTED = 2,  /* valid request the library does not provide   */
   TR_ERR_ALLOC = 3,        /* device or host allocation failed              */
   TR_ERR_HIP = 4,          /* a HIP runtime call failed                     */
   TR_ERR_NOCONV = 5        /* solver hit its iteration limit (x is written) */

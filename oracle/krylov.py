@@ -1,7 +1,7 @@
 """Outer Krylov solvers (oracle; test infrastructure).
 
 The paper accelerates its preconditioned iteration with BiCGStab (Section 3);
-this build's default outer solver is GMRES(m): x0 = 0, modified Gram-Schmidt
+the configured workloads' outer solver is GMRES(m): x0 = 0, modified Gram-Schmidt
 Arnoldi on A M^{-1}, Givens rotations, inner exit when the implicit residual
 drops below tol ||b||, x += M^{-1}(V y) at the end of each cycle, and the
 explicit residual ||b - A x|| / ||b|| < tol (the stopping rule of Section
