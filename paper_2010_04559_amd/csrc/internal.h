@@ -127,10 +127,11 @@ void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double
                      const int *n_child, int Pc, const double *sig_s, bool apply_sn, const Grid &g,
                      hipStream_t st, const int *pos = nullptr, const OrdInfo *cord = nullptr);
 
-// Prolongation: uf[c] (+)= P_c uc[owner(c)]
+// Prolongation: uf[c] (+)= P_c uc[p] for the children c of every coarse
+// patch p (first_child[p] .. + n_child[p]), Pc coarse patches
 template <typename Tin, typename Tout>
-void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *owner, int Pf, long long S, bool add,
-                    hipStream_t st);
+void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *first_child, const int *n_child, int Pc,
+                    long long S, bool add, hipStream_t st);
 
 // y = L x - sigma_s N s  (canonical FP64, s = S~ x); adjoint: L^T x - sigma_s N s
 void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,

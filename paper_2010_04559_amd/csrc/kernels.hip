@@ -2088,6 +2088,9 @@ __global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict_
                            const int *__restrict__ n_child, int Pc, const double *__restrict__ sig_s,
                            int apply_sn, Grid g, const int *__restrict__ pos, const OrdInfo *__restrict__ cord) {
   constexpr int NS = 1 << DIM;
+  // children whose loads are issued together (a parent has one or four):
+  // all four in FP32, two at a time in FP64 (registers)
+  constexpr int CH = sizeof(Tin) == 4 ? 4 : 2;
   const long long C = g.C, S = g.S;
   const long long total = (long long)Pc * C;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
@@ -2100,33 +2103,50 @@ __global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict_
 #pragma unroll
       for (int b = 0; b < NS; ++b) out[m][b] = 0.0;
     const int c0 = first_child[p], nc = n_child[p];
-    for (int c = c0; c < c0 + nc; ++c) {
-      double x[3][NS];
+    const double fsn = apply_sn ? sig_s[j] * g.vol : 1.0;
+    for (int cb = 0; cb < nc; cb += CH) {
+      // every load of this group first (children past the last read the
+      // last again and are dropped)
+      Tin xr[CH][3][NS];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const long long off = (3LL * c + m) * S + j * NS;
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          double v = (double)s_new[off + b];
-          if (s_prev) v -= (double)s_prev[off + b];
-          x[m][b] = v;
-        }
-        if (apply_sn) {
-          mass_shape<double, DIM, false>(x[m]);
-          const double f = sig_s[j] * g.vol;
-#pragma unroll
-          for (int b = 0; b < NS; ++b) x[m][b] *= f;
-        }
-      }
-      const double *Rc = R + 9LL * c;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
+      for (int cc = 0; cc < CH; ++cc) {
+        const int c = c0 + min(cb + cc, nc - 1);
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-          const double r = Rc[k * 3 + m];
+          const long long off = (3LL * c + m) * S + j * NS;
 #pragma unroll
-          for (int b = 0; b < NS; ++b) out[k][b] += r * x[m][b];
+          for (int b = 0; b < NS; ++b) {
+            Tin v = s_new[off + b];
+            if (s_prev) v -= s_prev[off + b];
+            xr[cc][m][b] = v;
+          }
         }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        if (cb + cc >= nc) break;
+        const int c = c0 + cb + cc;
+        double x[3][NS];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) x[m][b] = (double)xr[cc][m][b];
+          if (apply_sn) {
+            mass_shape<double, DIM, false>(x[m]);
+#pragma unroll
+            for (int b = 0; b < NS; ++b) x[m][b] *= fsn;
+          }
+        }
+        const double *Rc = R + 9LL * c;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            const double r = Rc[k * 3 + m];
+#pragma unroll
+            for (int b = 0; b < NS; ++b) out[k][b] += r * x[m][b];
+          }
+      }
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -2140,25 +2160,42 @@ __global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict_
   }
 }
 
+// One thread per (coarse patch p, spatial dof s): the parent's three values
+// are read once for all of its children (one, or four when it is refined),
+// whose fine values are then written (added to with add).
 template <typename Tin, typename Tout>
 __global__ void k_prolong(const Tin *__restrict__ uc, Tout *__restrict__ uf, const double *__restrict__ Pb,
-                          const int *__restrict__ owner, int Pf, long long S, int add) {
-  const long long total = (long long)Pf * S;
+                          const int *__restrict__ first_child, const int *__restrict__ n_child, int Pc, long long S,
+                          int add) {
+  const long long total = (long long)Pc * S;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / S);
-    const long long s = t - (long long)c * S;
-    const int p = owner[c];
+    const int p = (int)(t / S);
+    const long long s = t - (long long)p * S;
     double x[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) x[d] = (double)uc[(3LL * p + d) * S + s];
-    const double *B = Pb + 9LL * c;
+    const int c0 = first_child[p], nc = n_child[p];
+    Tout f[4][3];
+    if (add) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      double y = B[k * 3] * x[0] + B[k * 3 + 1] * x[1] + B[k * 3 + 2] * x[2];
-      Tout *dst = uf + (3LL * c + k) * S + s;
-      if (add) y += (double)*dst;
-      *dst = (Tout)y;
+      for (int cc = 0; cc < 4; ++cc) {
+        const int c = c0 + min(cc, nc - 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[cc][k] = uf[(3LL * c + k) * S + s];
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      if (cc >= nc) break;
+      const int c = c0 + cc;
+      const double *B = Pb + 9LL * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double y = B[k * 3] * x[0] + B[k * 3 + 1] * x[1] + B[k * 3 + 2] * x[2];
+        if (add) y += (double)f[cc][k];
+        uf[(3LL * c + k) * S + s] = (Tout)y;
+      }
     }
   }
 }
@@ -3127,14 +3164,14 @@ TR_INST_RESTRICT(float, double)
 TR_INST_RESTRICT(double, float)
 
 template <typename Tin, typename Tout>
-void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *owner, int Pf, long long S, bool add,
-                    hipStream_t st) {
-  hipLaunchKernelGGL((k_prolong<Tin, Tout>), dim3(grid_for((long long)Pf * S)), dim3(kBlock), 0, st, uc, uf, Pblk,
-                     owner, Pf, S, (int)add);
+void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *first_child, const int *n_child, int Pc,
+                    long long S, bool add, hipStream_t st) {
+  hipLaunchKernelGGL((k_prolong<Tin, Tout>), dim3(grid_for((long long)Pc * S)), dim3(kBlock), 0, st, uc, uf, Pblk,
+                     first_child, n_child, Pc, S, (int)add);
 }
-#define TR_INST_PROLONG(TI, TO)                                                                              \
-  template void launch_prolong<TI, TO>(const TI *, TO *, const double *, const int *, int, long long, bool, \
-                                       hipStream_t);
+#define TR_INST_PROLONG(TI, TO)                                                                                    \
+  template void launch_prolong<TI, TO>(const TI *, TO *, const double *, const int *, const int *, int, long long, \
+                                       bool, hipStream_t);
 TR_INST_PROLONG(double, double)
 TR_INST_PROLONG(float, float)
 TR_INST_PROLONG(double, float)

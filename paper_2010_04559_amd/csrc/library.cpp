@@ -1251,9 +1251,10 @@ void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
     mg_level<T>(h, l - 1, adj, st);
   tbegin(h, C_TRANSFER);
   if (l - 1 == 0)
-    tr::launch_prolong<double, T>(Dc.u64, u, adj ? D.Pa : D.Pu, D.owner, D.P, h->g.S, true, st);
+    tr::launch_prolong<double, T>(Dc.u64, u, adj ? D.Pa : D.Pu, D.first_child, D.n_child, Dc.P, h->g.S, true, st);
   else
-    tr::launch_prolong<T, T>(LevelBuf<T>::u(Dc), u, adj ? D.Pa : D.Pu, D.owner, D.P, h->g.S, true, st);
+    tr::launch_prolong<T, T>(LevelBuf<T>::u(Dc), u, adj ? D.Pa : D.Pu, D.first_child, D.n_child, Dc.P, h->g.S, true,
+                             st);
   tend(h);
   for (int it = 0; it < nu_post; ++it) {
     if (!adj) {
@@ -2081,9 +2082,11 @@ int tr_transfer(tr_handle *h, int level, int dir, int prec, const void *in, void
     DevLevel &D = h->lv[level], &Dc = h->lv[level - 1];
     if (dir == TR_PROLONG) {
       if (prec == TR_F64)
-        tr::launch_prolong<double, double>((const double *)in, (double *)out, D.Pc, D.owner, D.P, h->g.S, false, S(st));
+        tr::launch_prolong<double, double>((const double *)in, (double *)out, D.Pc, D.first_child, D.n_child,
+                                           h->lv[level - 1].P, h->g.S, false, S(st));
       else
-        tr::launch_prolong<float, float>((const float *)in, (float *)out, D.Pc, D.owner, D.P, h->g.S, false, S(st));
+        tr::launch_prolong<float, float>((const float *)in, (float *)out, D.Pc, D.first_child, D.n_child,
+                                         h->lv[level - 1].P, h->g.S, false, S(st));
     } else {
       if (prec == TR_F64)
         tr::launch_restrict<double, double>((const double *)in, nullptr, (double *)out, D.Rc, D.first_child,
