@@ -109,10 +109,11 @@ void launch_coarse_gs(const double *f, double *u, const double *G, const double 
                       int nsteps, int max_items, bool adjoint, unsigned *bar_arrive, unsigned *bar_release,
                       int *bar_err, int max_blocks, unsigned gen0, bool coh, hipStream_t st);
 
-// out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * scale * in[3p+m][s]
+// out[a][s] = post[a] * sum_m Psi^{-1}[k(a)][m] * pre[3p+m] * scale * in[3p+m][s];
+// out64 (optional): the same rounded values widened to FP64
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
-                    hipStream_t st, double scale = 1.0);
+                    hipStream_t st, double scale = 1.0, double *out64 = nullptr);
 // The same conversion followed by the inverse cell mass matrix per ordinate:
 // a forward right-hand side in prepared form f~ = N^{-1} f (the form every
 // forward sweep, forward coarse solve and forward restriction works in).

@@ -2022,7 +2022,8 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
 // ------------------------------------------------------------- conversions
 template <typename Tin, typename Tout>
 __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, int P, long long S,
-                          const double *__restrict__ pre, const double *__restrict__ post, double scale) {
+                          const double *__restrict__ pre, const double *__restrict__ post, double scale,
+                          double *__restrict__ out64) {
   const long long total = (long long)P * S;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
@@ -2039,7 +2040,10 @@ __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, in
     for (int k = 0; k < 3; ++k) {
       double y = 2.0 * x[k] - sum * (1.0 / 3.0);   // Psi^{-1} = 2 I - J / 3
       if (post) y *= post[3 * p + k];
-      out[(3LL * p + k) * S + s] = (Tout)y;
+      const Tout yo = (Tout)y;
+      out[(3LL * p + k) * S + s] = yo;
+      // the same values widened (a second copy in FP64, from the rounded ones)
+      if (out64) out64[(3LL * p + k) * S + s] = (double)yo;
     }
   }
 }
@@ -3112,9 +3116,9 @@ void launch_coarse_gs(const double *f, double *u, const double *G, const double 
 
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
-                    hipStream_t st, double scale) {
+                    hipStream_t st, double scale, double *out64) {
   hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for((long long)P * S)), dim3(kBlock), 0, st, in, out, P, S,
-                     pre, post, scale);
+                     pre, post, scale, out64);
 }
 template <typename Tin, typename Tout>
 void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
@@ -3134,13 +3138,13 @@ template void launch_convert_minv<double, float>(const double *, float *, int, c
 template void launch_convert_minv<float, float>(const float *, float *, int, const Grid &, const double *,
                                                 const double *, hipStream_t, const int *, const OrdInfo *, double);
 template void launch_convert<double, double>(const double *, double *, int, long long, const double *,
-                                             const double *, hipStream_t, double);
+                                             const double *, hipStream_t, double, double *);
 template void launch_convert<double, float>(const double *, float *, int, long long, const double *, const double *,
-                                            hipStream_t, double);
+                                            hipStream_t, double, double *);
 template void launch_convert<float, double>(const float *, double *, int, long long, const double *, const double *,
-                                            hipStream_t, double);
+                                            hipStream_t, double, double *);
 template void launch_convert<float, float>(const float *, float *, int, long long, const double *, const double *,
-                                           hipStream_t, double);
+                                           hipStream_t, double, double *);
 
 template <typename Tin, typename Tout>
 void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,

@@ -1320,8 +1320,9 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
     mg_level<float>(h, L, adj, st);
     tbegin(h, C_OTHER);
     if (z32) {
-      tr::launch_convert<float, float>(D.u32, z32, D.P, h->g.S, pre_out, post_out, st, out_scale);
-      tr::launch_cast<float, double>(z32, z, h->vec_len(L), st);
+      // the FP32 vector kept for the flexible update and its FP64 copy for
+      // the operator, in one pass
+      tr::launch_convert<float, float>(D.u32, z32, D.P, h->g.S, pre_out, post_out, st, out_scale, z);
     } else {
       tr::launch_convert<float, double>(D.u32, z, D.P, h->g.S, pre_out, post_out, st, out_scale);
     }
