@@ -462,6 +462,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   __shared__ T As[NBUF][NCHI][BK][BM + PAD];
   __shared__ T Bs[NBUF][NCHI][BK][BN + PAD];
   __shared__ int pos_s[8][BN / 4 + 1];
+  __shared__ unsigned char flip_s[NCHI][BM];  // orientation of each output row (plane layout)
 
   const int b = blockIdx.x;
   const int xcd = b % kXcds, slot = b / kXcds;
@@ -577,12 +578,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     }
   };
   if (pos) {
-    // positions of the tile's cells in every orientation's list (plane
-    // layout output); read after the loop's barriers
+    // positions of the tile's cells in every orientation's list, and the
+    // orientation of every output row (plane layout output); read after the
+    // loop's barriers
     const int ncell = BN / cell;
     for (int t = tid; t < 8 * ncell; t += 256) {
       const int fl = t / ncell, c = t % ncell;
       pos_s[fl][c] = pos[(long long)fl * ncells + min(n0 / cell + c, ncells - 1)];
+    }
+    for (int t = tid; t < NCHI * BM; t += 256) {
+      const int q = t / BM, r = m0 + t % BM;
+      flip_s[q][t % BM] = r < nc ? (unsigned char)rord[oct_row<R>(om, r, q)].flip : 0;
     }
   }
   // DB: two LDS buffers, the next slice stored during the MFMAs, one
@@ -637,7 +643,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         for (int q = 0; q < NCHI; ++q) {
           const long long row = oct_row<R>(om, t, q);
           long long col = gn;
-          if (pos) col = (long long)pos_s[rord[row].flip][(int)((gn - n0) / cell)] * cell + (gn % cell);
+          if (pos) col = (long long)pos_s[flip_s[q][t - m0]][(int)((gn - n0) / cell)] * cell + (gn % cell);
           const long long o = row * N + col;
           T v = y[q];
           if (colscale) v *= cs;
