@@ -207,6 +207,13 @@ def headline(args):
     reps64 = max(1, min(args.steps, args.fp64_steps))
     x64, st64, ms64, acc64 = _timed_solves(tr, b, "f64", reps64, 1, "fp64")
     rel2, relmax = _chunked_rel_diff(xm, x64)
+    del xm
+    torch.cuda.empty_cache()
+    # the same FP32 preconditioner with its scatter products formed from
+    # split-BF16 operands (three BF16 matrix-core products, FP32 accumulate)
+    xb, stb, msb, accb = _timed_solves(tr, b, "mixed_bf16", reps64, 1, "fp32-mg-split-bf16")
+    relb2, relbmax = _chunked_rel_diff(xb, x64)
+    del xb
     free, _ = torch.cuda.mem_get_info()
     print("after solves: %.1f GB free" % (free / 1e9), file=sys.stderr, flush=True)
 
@@ -229,6 +236,7 @@ def headline(args):
     ms_sw64 = tr.time_sweep_kernel(L, "f64", reps=5)
     ms_sw32 = tr.time_sweep_kernel(L, "f32", reps=5)
     ms_g32 = tr.time_scatter_kernel(L, outer=False, prec="f32", reps=5)
+    ms_gb = tr.time_scatter_kernel(L, outer=False, prec="bf16x3", reps=5)
     fl_lv = tr.scatter_flops(L)
     line = {
         "metric": METRIC,
@@ -248,12 +256,17 @@ def headline(args):
                    "step": "one solve to 1e-8: FP64 flexible GMRES(%d) + FP32 angular MG V(1,1), FP64 coarsest "
                            "level (10 Gauss-Seidel sweeps)" % prob.restart,
                    "parallelism": "single GPU"},
-        "time_to_tol_ms": {"fp32_mg": ms_step, "fp64_plain": ms64, "fp64_over_fp32_mg": ms64 / ms_step},
-        "iters": {"fp32_mg": stm["iters"], "fp64_plain": st64["iters"]},
-        "explicit_rel_res": {"fp32_mg": stm["rel_res"], "fp64_plain": st64["rel_res"]},
+        "time_to_tol_ms": {"fp32_mg": ms_step, "fp64_plain": ms64, "fp64_over_fp32_mg": ms64 / ms_step,
+                           "fp32_mg_split_bf16": msb, "fp64_over_fp32_mg_split_bf16": ms64 / msb},
+        "iters": {"fp32_mg": stm["iters"], "fp64_plain": st64["iters"], "fp32_mg_split_bf16": stb["iters"]},
+        "explicit_rel_res": {"fp32_mg": stm["rel_res"], "fp64_plain": st64["rel_res"],
+                             "fp32_mg_split_bf16": stb["rel_res"]},
         "fp32_mg_vs_fp64_solution": {"rel_l2": rel2, "rel_max": relmax},
-        "sweep_dof_updates_per_s": {"fp32_mg": value, "fp64_plain": st64["sweep_dof_updates"] / (ms64 * 1e-3)},
-        "breakdown_ms_per_solve": {"fp32_mg": per_solve(accm, args.steps), "fp64_plain": per_solve(acc64, reps64)},
+        "fp32_mg_split_bf16_vs_fp64_solution": {"rel_l2": relb2, "rel_max": relbmax},
+        "sweep_dof_updates_per_s": {"fp32_mg": value, "fp64_plain": st64["sweep_dof_updates"] / (ms64 * 1e-3),
+                                    "fp32_mg_split_bf16": stb["sweep_dof_updates"] / (msb * 1e-3)},
+        "breakdown_ms_per_solve": {"fp32_mg": per_solve(accm, args.steps), "fp64_plain": per_solve(acc64, reps64),
+                                   "fp32_mg_split_bf16": per_solve(accb, reps64)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": sweep_kernel + " (finest-level FP32 transport sweep)",
@@ -271,12 +284,15 @@ def headline(args):
             "sweep_f32_ms": ms_sw32, "sweep_f32_dof_per_s": dofs / (ms_sw32 * 1e-3),
             "sweep_f32_hbm_frac": dofs * 8 / (ms_sw32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "scatter_f32_finest_ms": ms_g32, "scatter_f32_finest_tflops": fl_lv / (ms_g32 * 1e-3) / 1e12,
-            "scatter_f32_finest_frac": fl_lv / (ms_g32 * 1e-3) / 1e12 / FP32_PEAK_TFS},
+            "scatter_f32_finest_frac": fl_lv / (ms_g32 * 1e-3) / 1e12 / FP32_PEAK_TFS,
+            "scatter_split_bf16_finest_ms": ms_gb,
+            "scatter_split_bf16_finest_tflops": 3 * fl_lv / (ms_gb * 1e-3) / 1e12,
+            "scatter_split_bf16_finest_frac": 3 * fl_lv / (ms_gb * 1e-3) / 1e12 / BF16_PEAK_TFS},
         "scatter_forms": [list(f) for f in tr.scatter_forms],
         "coarse_gs": coarse_gs_line(accm, args.steps),
         "setup_s": t_setup,
     }
-    del xm, x64, b
+    del x64, b
     tr.close()
     torch.cuda.synchronize()
     if not args.no_cpu_baseline:

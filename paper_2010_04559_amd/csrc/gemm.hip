@@ -439,6 +439,74 @@ __device__ __forceinline__ int oct_row(const OctMap &om, int t, int i) {
   return t + off;
 }
 
+// Plane-layout output of the octant-group products: the positions of the
+// tile's cells in every orientation's list and the orientation of every
+// output row, staged in LDS by the whole workgroup.
+template <int R, int BM, int BN>
+__device__ __forceinline__ void oct_out_stage(int (&pos_s)[8][BN / 4 + 1], unsigned char (&flip_s)[1 << R][BM],
+                                              const OctMap &om, const int *pos, const OrdInfo *rord, int nc, int m0,
+                                              long long n0, int cell, long long ncells) {
+  const int ncell = BN / cell;
+  for (int t = threadIdx.x; t < 8 * ncell; t += blockDim.x) {
+    const int fl = t / ncell, c = t % ncell;
+    pos_s[fl][c] = pos[(long long)fl * ncells + min(n0 / cell + c, ncells - 1)];
+  }
+  for (int t = threadIdx.x; t < (1 << R) * BM; t += blockDim.x) {
+    const int q = t / BM, r = m0 + t % BM;
+    flip_s[q][t % BM] = r < nc ? (unsigned char)rord[oct_row<R>(om, r, q)].flip : 0;
+  }
+}
+
+// Output stage of the octant-group products: for each accumulator position
+// (transformed row t, column) the 2^R values of the sign patterns chi are
+// transformed back in registers and stored with the epilogue of k_gemm.
+// Accumulator element r of lane (lrow, lk) of MFMA tile (i, jn) is row
+// wm0 + 16 i + Mma<T>::row(lk, r), column wn0 + 16 jn + lrow of the tile.
+template <typename T, int R, int BM, int BN, int TM, int TN>
+__device__ __forceinline__ void oct_store(const typename Mma<T>::acc_t (&acc)[1 << R][TM][TN], T *__restrict__ C,
+                                          const OctMap &om, int nc, int N, int m0, long long n0, int wm0, int wn0,
+                                          int lrow, int lk, const T *__restrict__ bias,
+                                          const double *__restrict__ colscale, int cell, const int *pos,
+                                          const int (&pos_s)[8][BN / 4 + 1],
+                                          const unsigned char (&flip_s)[1 << R][BM]) {
+  constexpr int NCHI = 1 << R;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int jn = 0; jn < TN; ++jn) {
+      const long long gn = n0 + wn0 + jn * 16 + lrow;
+      const T cs = (colscale && gn < N) ? T(colscale[gn / cell]) : T(1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
+        if (t >= nc || gn >= N) continue;
+        T y[NCHI];
+#pragma unroll
+        for (int j = 0; j < NCHI; ++j) y[j] = acc[j][i][jn][r];
+#pragma unroll
+        for (int hh = 1; hh < NCHI; hh <<= 1)
+#pragma unroll
+          for (int q = 0; q < NCHI; ++q)
+            if (!(q & hh)) {
+              const T a = y[q], c = y[q + hh];
+              y[q] = a + c;
+              y[q + hh] = a - c;
+            }
+#pragma unroll
+        for (int q = 0; q < NCHI; ++q) {
+          const long long row = oct_row<R>(om, t, q);
+          long long col = gn;
+          if (pos) col = (long long)pos_s[flip_s[q][t - m0]][(int)((gn - n0) / cell)] * cell + (gn % cell);
+          const long long o = row * N + col;
+          T v = y[q];
+          if (colscale) v *= cs;
+          if (bias) v += bias[o];
+          C[o] = v;
+        }
+      }
+    }
+}
+
 template <typename T, int R, int BM, int BN, int BK, int WPE, bool DB, bool ALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_oct(
     const T *__restrict__ Bh, int ldb, const T *__restrict__ U, T *__restrict__ C, OctMap om, int nc, int N,
@@ -577,20 +645,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       }
     }
   };
-  if (pos) {
-    // positions of the tile's cells in every orientation's list, and the
-    // orientation of every output row (plane layout output); read after the
-    // loop's barriers
-    const int ncell = BN / cell;
-    for (int t = tid; t < 8 * ncell; t += 256) {
-      const int fl = t / ncell, c = t % ncell;
-      pos_s[fl][c] = pos[(long long)fl * ncells + min(n0 / cell + c, ncells - 1)];
-    }
-    for (int t = tid; t < NCHI * BM; t += 256) {
-      const int q = t / BM, r = m0 + t % BM;
-      flip_s[q][t % BM] = r < nc ? (unsigned char)rord[oct_row<R>(om, r, q)].flip : 0;
-    }
-  }
+  if (pos) oct_out_stage<R, BM, BN>(pos_s, flip_s, om, pos, rord, nc, m0, n0, cell, ncells);  // read after the loop's barriers
   // DB: two LDS buffers, the next slice stored during the MFMAs, one
   // barrier per slice; else one buffer, the next slice's loads in flight
   // during the MFMAs, two barriers per slice
@@ -616,42 +671,151 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       __syncthreads();
     }
   }
-  // inverse transform and store
+  oct_store<T, R, BM, BN, TM, TN>(acc, C, om, nc, N, m0, n0, wm0, wn0, lrow, lk, bias, colscale, cell, pos, pos_s,
+                                  flip_s);
+}
+
+// Split-BF16 form of the octant-group product (FP32 operands: the
+// preconditioner's scatter when its accuracy suffices).  The blocks B^[chi]
+// are split once by k_split_rows ([hi | lo][2^R nc][kp]) and their MFMA
+// operands read straight from global memory (L2-resident), one sign pattern
+// ahead; per k-slice of 32 every thread loads, for one column and 8
+// transformed rows k, the 2^R canonical rows of each k, transforms them over
+// the sign patterns in FP32, splits each value x = bf16(x) + bf16(x -
+// bf16(x)) and stores both parts in LDS column-major ([chi][column][k]), as
+// 16-byte chunks of 8 k whose chunk index is XOR-swizzled with bits 1-2 of
+// the column: the 16-byte reads and writes of 8 consecutive columns then
+// cover all banks.  Each product is three v_mfma_f32_16x16x32_bf16 (lo hi,
+// hi lo, hi hi), FP32 accumulate, the relative error of k_gemm_bf16x3.
+// Tile BM x 64 for every chi, 2 x 2 waves; the output stage of k_gemm_oct.
+template <int R, int BM, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_gemm_oct_bf16x3(
+    const __bf16 *__restrict__ Bs, int kp, const float *__restrict__ U, float *__restrict__ C, OctMap om, int nc,
+    int N, int mblocks, int nblocks, const float *__restrict__ bias, const double *__restrict__ colscale, int cell,
+    const int *__restrict__ pos, const OrdInfo *__restrict__ rord, long long ncells) {
+  constexpr int NCHI = 1 << R;
+  constexpr int BN = 64, BK = 32, KG = 8;  // KG: k values per thread (64 columns x 4 groups)
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert(BM % 32 == 0 && 256 / BN * KG == BK, "tile shape");
+  __shared__ __attribute__((aligned(16))) __bf16 Bhi[NCHI][BN][BK], Blo[NCHI][BN][BK];
+  __shared__ int pos_s[8][BN / 4 + 1];
+  __shared__ unsigned char flip_s[NCHI][BM];
+
+  const int b = blockIdx.x;
+  const int xcd = b % kXcds, slot = b / kXcds;
+  const int mb = slot % mblocks;
+  const int nb = xcd + kXcds * (slot / mblocks);
+  if (nb >= nblocks) return;
+  const int m0 = mb * BM;
+  const long long n0 = (long long)nb * BN;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const __bf16 *Bl = Bs + (long long)NCHI * nc * kp;
+
+  f4 acc[NCHI][TM][TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < NCHI; ++j)
 #pragma unroll
-    for (int jn = 0; jn < TN; ++jn) {
-      const long long gn = n0 + wn0 + jn * 16 + lrow;
-      const T cs = (colscale && gn < N) ? T(colscale[gn / cell]) : T(1);
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int t = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
-        if (t >= nc || gn >= N) continue;
-        T y[NCHI];
+      for (int jn = 0; jn < TN; ++jn) acc[j][i][jn] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // staging: column c, transformed rows k0 + KG g .. + KG - 1
+  const int c = tid % BN, g = tid / BN;
+  const long long gn = n0 + c;
+  const bool col_ok = gn < N;
+  float rx[KG][NCHI];
+  auto load = [&](int k0) {
 #pragma unroll
-        for (int j = 0; j < NCHI; ++j) y[j] = acc[j][i][jn][r];
+    for (int kk = 0; kk < KG; ++kk) {
+      const int k = k0 + KG * g + kk;
 #pragma unroll
-        for (int hh = 1; hh < NCHI; hh <<= 1)
-#pragma unroll
-          for (int q = 0; q < NCHI; ++q)
-            if (!(q & hh)) {
-              const T a = y[q], c = y[q + hh];
-              y[q] = a + c;
-              y[q + hh] = a - c;
-            }
-#pragma unroll
-        for (int q = 0; q < NCHI; ++q) {
-          const long long row = oct_row<R>(om, t, q);
-          long long col = gn;
-          if (pos) col = (long long)pos_s[flip_s[q][t - m0]][(int)((gn - n0) / cell)] * cell + (gn % cell);
-          const long long o = row * N + col;
-          T v = y[q];
-          if (colscale) v *= cs;
-          if (bias) v += bias[o];
-          C[o] = v;
-        }
-      }
+      for (int i = 0; i < NCHI; ++i)
+        rx[kk][i] = (k < nc && col_ok) ? U[(long long)oct_row<R>(om, k, i) * N + gn] : 0.f;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+      for (int hh = 1; hh < NCHI; hh <<= 1)
+#pragma unroll
+        for (int i = 0; i < NCHI; ++i)
+          if (!(i & hh)) {
+            const float a = rx[kk][i], d = rx[kk][i + hh];
+            rx[kk][i] = a + d;
+            rx[kk][i + hh] = a - d;
+          }
+    const int ch = g ^ ((c >> 1) & 3);
+#pragma unroll
+    for (int j = 0; j < NCHI; ++j) {
+      unsigned hw[KG / 2], lw[KG / 2];
+#pragma unroll
+      for (int e = 0; e < KG / 2; ++e) {
+        __bf16 h0, l0, h1, l1;
+        split_bf16(rx[2 * e][j], h0, l0);
+        split_bf16(rx[2 * e + 1][j], h1, l1);
+        hw[e] = pack_bf16(h0, h1);
+        lw[e] = pack_bf16(l0, l1);
+      }
+      *reinterpret_cast<uint4 *>(&Bhi[j][c][8 * ch]) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      *reinterpret_cast<uint4 *>(&Blo[j][c][8 * ch]) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+  };
+  // A operand rows of this lane (rows past nc read row nc - 1 of the same
+  // block: their products land in rows that are not stored)
+  long long arow[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) arow[i] = (long long)min(m0 + wm0 + 16 * i + lrow, nc - 1) * kp + 8 * lk;
+  auto mma = [&](int k0) {
+    bf8 ah[2][TM], al[2][TM];
+    auto load_a = [&](int j, int sl) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const long long o = (long long)j * nc * kp + arow[i] + k0;
+        ah[sl][i] = *reinterpret_cast<const bf8 *>(Bs + o);
+        al[sl][i] = *reinterpret_cast<const bf8 *>(Bl + o);
+      }
+    };
+    load_a(0, 0);
+#pragma unroll
+    for (int j = 0; j < NCHI; ++j) {
+      if (j + 1 < NCHI) load_a(j + 1, (j + 1) & 1);
+      bf8 bh[TN], bl[TN];
+#pragma unroll
+      for (int jn = 0; jn < TN; ++jn) {
+        const int col = wn0 + 16 * jn + lrow;
+        const int chk = lk ^ ((col >> 1) & 3);
+        bh[jn] = *reinterpret_cast<const bf8 *>(&Bhi[j][col][8 * chk]);
+        bl[jn] = *reinterpret_cast<const bf8 *>(&Blo[j][col][8 * chk]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int jn = 0; jn < TN; ++jn) {
+          f4 a = acc[j][i][jn];
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[j & 1][i], bh[jn], a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[j & 1][i], bl[jn], a, 0, 0, 0);
+          acc[j][i][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[j & 1][i], bh[jn], a, 0, 0, 0);
+        }
+    }
+  };
+  if (pos) oct_out_stage<R, BM, BN>(pos_s, flip_s, om, pos, rord, nc, m0, n0, cell, ncells);  // read after the loop's barriers
+  // one LDS buffer: the next slice's loads in flight during the MFMAs, two
+  // barriers per slice
+  load(0);
+  for (int k0 = 0; k0 < nc; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < nc) load(k0 + BK);
+    mma(k0);
+    __syncthreads();
+  }
+  oct_store<float, R, BM, BN, TM, TN>(acc, C, om, nc, N, m0, n0, wm0, wn0, lrow, lk, bias, colscale, cell, pos,
+                                      pos_s, flip_s);
 }
 
 }  // namespace
@@ -743,6 +907,38 @@ void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int
   hipLaunchKernelGGL(k_gemm_bf16x3, dim3((unsigned)(mblocks * nb_pad)), dim3(256), 0, st,
                      reinterpret_cast<const __bf16 *>(Asplit), split_rows_kp(K), B, C, M, N, K, mblocks, nblocks,
                      bias, colscale, cell, pos, rord);
+}
+
+template <int R, int BM, int WPE>
+static void launch_oct_bf16_shape(const __bf16 *Bs, int kp, const float *U, float *C, const OctMap &om, int N,
+                                  hipStream_t st, const float *bias, const double *colscale, int cell, const int *pos,
+                                  const OrdInfo *rord) {
+  const int nc = om.nc;
+  const int mblocks = (nc + BM - 1) / BM;
+  const int nblocks = (int)(((long long)N + 63) / 64);
+  const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL((k_gemm_oct_bf16x3<R, BM, WPE>), dim3((unsigned)(mblocks * nb_pad)), dim3(256), 0, st, Bs, kp, U,
+                     C, om, nc, N, mblocks, nblocks, bias, colscale, cell, pos, rord, (long long)(N / cell));
+}
+
+void launch_gemm_oct_bf16x3(const void *Bsplit, int kp, const float *U, float *C, const OctMap &om, int N,
+                            hipStream_t st, const float *bias, const double *colscale, int cell, const int *pos,
+                            const OrdInfo *rord) {
+  if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
+  if (kp % 32 != 0 || kp < om.nc) throw std::runtime_error("octant-group GEMM: bad split block stride");
+  const __bf16 *Bs = reinterpret_cast<const __bf16 *>(Bsplit);
+  // tile 32 x 64 x 32, two waves per SIMD: measured on MI355X (three axes,
+  // N = 884736) 9.1 ms at nc = 192 and 1.55 ms at nc = 48, the times of the
+  // FP32 product (9.3 and 1.3-1.6 ms): both are bound by the latency of the
+  // operand loads, not by the matrix cores (64 x 64 tiles at one wave per
+  // SIMD: 13 and 2.7 ms; the A operands of a slice loaded ahead of the next
+  // slice's U loads: no change)
+  switch (om.R) {
+    case 1: launch_oct_bf16_shape<1, 32, 2>(Bs, kp, U, C, om, N, st, bias, colscale, cell, pos, rord); break;
+    case 2: launch_oct_bf16_shape<2, 32, 2>(Bs, kp, U, C, om, N, st, bias, colscale, cell, pos, rord); break;
+    case 3: launch_oct_bf16_shape<3, 32, 2>(Bs, kp, U, C, om, N, st, bias, colscale, cell, pos, rord); break;
+    default: throw std::runtime_error("octant-group GEMM: 1 to 3 reflected axes");
+  }
 }
 
 template void launch_gemm<double>(const double *, const double *, double *, int, int, int, hipStream_t,

@@ -208,5 +208,11 @@ void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st);
 void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int N, int K, hipStream_t st,
                         const float *bias = nullptr, const double *colscale = nullptr, int cell = 8,
                         const int *pos = nullptr, const OrdInfo *rord = nullptr);
+// Octant-group product (as launch_gemm_oct) with split-BF16 operands: Bsplit
+// holds the blocks Bh ([2^R nc][ldb], FP32) split by launch_split_rows with
+// K = ldb, row stride kp = split_rows_kp(ldb).
+void launch_gemm_oct_bf16x3(const void *Bsplit, int kp, const float *U, float *C, const OctMap &om, int N,
+                            hipStream_t st, const float *bias = nullptr, const double *colscale = nullptr,
+                            int cell = 8, const int *pos = nullptr, const OrdInfo *rord = nullptr);
 
 }  // namespace tr

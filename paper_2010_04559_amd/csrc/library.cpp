@@ -911,6 +911,11 @@ const void *split_of(tr_handle *h, const float *A, int M, int K, hipStream_t st)
   return p;
 }
 
+// The split-BF16 form of a level's octant-group blocks Bh ([2^R nc][ldb]).
+const void *split_blocks(tr_handle *h, const DevLevel &D, const float *Bh, hipStream_t st) {
+  return split_of(h, Bh, (1 << D.symR) * D.sym_nc, D.sym_ldb, st);
+}
+
 // C = A B on the level GEMM path: FP64 and FP32 on the matrix cores in
 // their own precision, FP32 from split-BF16 operands when the handle's
 // preconditioner mode asks for it.
@@ -1177,10 +1182,20 @@ void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t 
   DevLevel &D = h->lv[l];
   const OrdInfo *rord = plane_out ? D.ord : nullptr;
   if (D.symR) {
-    // octant-group blocks (split-BF16 products are not used on these levels)
+    // octant-group blocks
     tbegin(h, C_SCATTER);
-    tr::launch_gemm_oct<T>(LevelBuf<T>::Bh(D, adj), D.sym_ldb, u, y, D.om, (int)h->g.S, st, bias,
-                           scale_sn ? h->sig_s : nullptr, h->g.ns, rord ? h->pos_pl : nullptr, rord);
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value) {
+      if (h->split32) {
+        tr::launch_gemm_oct_bf16x3(split_blocks(h, D, LevelBuf<T>::Bh(D, adj), st), tr::split_rows_kp(D.sym_ldb), u,
+                                   y, D.om, (int)h->g.S, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns,
+                                   rord ? h->pos_pl : nullptr, rord);
+        done = true;
+      }
+    }
+    if (!done)
+      tr::launch_gemm_oct<T>(LevelBuf<T>::Bh(D, adj), D.sym_ldb, u, y, D.om, (int)h->g.S, st, bias,
+                             scale_sn ? h->sig_s : nullptr, h->g.ns, rord ? h->pos_pl : nullptr, rord);
     tend(h);
     return;
   }
@@ -1883,8 +1898,9 @@ int tr_workspace_bytes(const tr_problem *prob, const tr_solve_opts *o, size_t *b
       if (o->prec_mode == TR_PREC_MIXED_BF16 && mixed)
         for (int l = 1; l <= h->top(); ++l) {
           DevLevel &D = h->lv[l];
-          if (D.symR) continue;  // octant-block levels take no split products
-          if (D.Kf) {
+          if (D.symR) {
+            split_blocks(h.get(), D, D.Bh32, nullptr);
+          } else if (D.Kf) {
             split_of(h.get(), D.Rt32, D.Kf, D.A, nullptr);
             split_of(h.get(), D.L32, D.A, D.Kf, nullptr);
           } else {
@@ -2051,7 +2067,10 @@ int tr_scatter(tr_handle *h, int level, int outer, int prec, const void *phi, vo
       tr::launch_scale_sn<double>(t, (double *)s, h->sig_s, D.A, h->g, S(st));
     } else {
       float *t = reinterpret_cast<float *>(D.sa64);  // the level's FP64 work buffer holds n floats
-      if (prec == TR_F32_SPLIT)
+      if (prec == TR_F32_SPLIT && D.symR)
+        tr::launch_gemm_oct_bf16x3(split_blocks(h, D, D.Bc32, S(st)), tr::split_rows_kp(D.sym_ldb),
+                                   (const float *)phi, t, D.om, Sn, S(st));
+      else if (prec == TR_F32_SPLIT)
         tr::launch_gemm_bf16x3(split_of(h, D.St32, D.A, D.A, S(st)), (const float *)phi, t, D.A, Sn, D.A, S(st));
       else if (D.symR)
         tr::launch_gemm_oct<float>(D.Bc32, D.sym_ldb, (const float *)phi, t, D.om, Sn, S(st));
@@ -2284,13 +2303,13 @@ int tr_time_scatter_kernel(tr_handle *h, int level, int outer, int prec, int rep
     if (prec == TR_F32 || prec == TR_F32_SPLIT) {
       if (level == 0) throw ArgError{"FP32 runs on levels >= 1"};
       ensure_mixed(h);
-      // the level's scatter as the V-cycle runs it (TR_F32_SPLIT: the dense
-      // split-BF16 product)
+      // the level's scatter as the V-cycle runs it (TR_F32_SPLIT: with
+      // split-BF16 products)
       auto run = [&]() {
-        if (prec == TR_F32_SPLIT)
-          tr::launch_gemm_bf16x3(split_of(h, D.G32, D.A, D.A, S(st)), D.u32, D.sa32, D.A, (int)h->g.S, D.A, S(st));
-        else
-          level_scatter<float>(h, level, false, D.u32, D.sa32, S(st));
+        const bool keep = h->split32;
+        h->split32 = prec == TR_F32_SPLIT;
+        level_scatter<float>(h, level, false, D.u32, D.sa32, S(st));
+        h->split32 = keep;
       };
       run();
       HIPCHK(hipEventRecord(e0, S(st)));

@@ -87,6 +87,22 @@ def test_cfg3_sweep_blocks(cfg3, prec):
         assert worst < tol, (q, worst)
 
 
+_ROWS = {}
+
+
+def _rows(prob, leaves, level, order, q):
+    """Rows of patch q of S~ (order ``order``) on a level, by the addition
+    theorem, kept for the module's other tests."""
+    key = (level, order, q)
+    if key not in _ROWS:
+        _ROWS[key] = ang.scatter_rows_addition(leaves, prob.moments(order), q)
+    return _ROWS[key]
+
+
+def _top_patches(qs):
+    return [qs[0], qs[len(qs) // 2]]
+
+
 def test_cfg3_scatter_outer_and_level2(cfg3):
     """Octant-block products against S~ rows by the addition theorem
     (convention-free), on sampled patches and cells."""
@@ -104,14 +120,47 @@ def test_cfg3_scatter_outer_and_level2(cfg3):
         xs = x.view(A, grid.S)[:, cols].cpu().numpy().reshape(A, len(cells), grid.ns)
         ss = s.view(A, grid.S)[:, cols].cpu().numpy().reshape(A, len(cells), grid.ns)
         del x, s
-        mom = prob.moments(order)
         # addition-theorem rows cost tens of seconds each at order 32
-        for q in ([qs[0], qs[len(qs) // 2]] if outer else qs[:4]):
+        for q in (_top_patches(qs) if outer else qs[:4]):
             qq = q % len(leaves)
-            rows = ang.scatter_rows_addition(leaves, mom, qq)
+            rows = _rows(prob, leaves, level, order, qq)
             for k, j in enumerate(cells):
                 ref = prob.sigma_s[j] * (rows @ xs[:, k, :]) @ grid.N.T
                 assert rel(ss[3 * qq:3 * qq + 3, k, :], ref) < 1e-10, (level, qq, j)
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_cfg3_scatter_fp32_finest_level(cfg3, split):
+    """The finest multigrid level's FP32 octant-block product (order 32,
+    A = 1536, the preconditioner's largest scatter), plain FP32 and from
+    split-BF16 operands, against S~ rows by the addition theorem on sampled
+    patches and cells (tolerances of the small-size parity tests: 1e-5 and
+    2e-4 relative)."""
+    prob, tr, grid, mesh, qs, cells = cfg3
+    torch = torch_mod()
+    level = tr.nlev - 1
+    leaves = mesh.levels()[level]
+    A = 3 * len(leaves)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17)
+    x = torch.randn(A * grid.S, dtype=torch.float32, device="cuda", generator=gen)
+    s = tr.scatter(level, x, split_bf16=split)
+    cols = torch.tensor([j * grid.ns + i for j in cells for i in range(grid.ns)], device="cuda")
+    xs = x.view(A, grid.S)[:, cols].double().cpu().numpy().reshape(A, len(cells), grid.ns)
+    ss = s.view(A, grid.S)[:, cols].double().cpu().numpy().reshape(A, len(cells), grid.ns)
+    del x, s
+    assert prob.mg_orders[level] == prob.order
+    got, ref = [], []
+    for q in _top_patches(qs):
+        rows = _rows(prob, leaves, level, prob.order, q)
+        for k, j in enumerate(cells):
+            ref.append(prob.sigma_s[j] * (rows @ xs[:, k, :]) @ grid.N.T)
+            got.append(ss[3 * q:3 * q + 3, k, :])
+    err = rel(np.array(got), np.array(ref))
+    print("finest-level FP32 scatter, split %s: rel %.2e" % (split, err), flush=True)
+    assert err < (2e-4 if split else 1e-5), err
+    if split:
+        assert err > 1e-8  # really the split product
 
 
 def test_cfg3_solves(cfg3):
@@ -123,12 +172,20 @@ def test_cfg3_solves(cfg3):
     x, st = tr.solve(b)
     assert st["converged"] == 1 and st["iters"] <= 11
     # |xm - x| in chunks (no full-size temporary next to the solver's workspace)
-    d2 = 0.0
-    for i in range(0, x.numel(), 1 << 27):
-        t = xm[i:i + (1 << 27)] - x[i:i + (1 << 27)]
-        d2 += float(torch.dot(t, t))
-    assert d2 ** 0.5 / float(torch.linalg.norm(x)) < 1e-7
+    def rel_diff(xa):
+        d2 = 0.0
+        for i in range(0, x.numel(), 1 << 27):
+            t = xa[i:i + (1 << 27)] - x[i:i + (1 << 27)]
+            d2 += float(torch.dot(t, t))
+        return d2 ** 0.5 / float(torch.linalg.norm(x))
+    assert rel_diff(xm) < 1e-7
     del xm
+    # the FP32 preconditioner with split-BF16 scatter products
+    xb, stb = tr.solve(b, mode="mixed_bf16")
+    print("iterations: fp64 %d, fp32 %d, split-bf16 %d" % (st["iters"], stm["iters"], stb["iters"]), flush=True)
+    assert stb["converged"] == 1 and stb["iters"] <= 11
+    assert rel_diff(xb) < 1e-7
+    del xb
     y = tr.apply(x)
     y -= b
     assert float(torch.linalg.norm(y) / torch.linalg.norm(b)) < 1e-8
