@@ -2225,209 +2225,154 @@ __device__ __forceinline__ void axis_apply(double *v, int d, double m00, double 
 // Adjoint:  L^T = Psi L^T_ord W Psi: mu = W Psi x, r_k = A_loc^T mu_k -
 //           downwind coupling, y = Psi r (S is symmetric, so S^T x = S x).
 template <int DIM, bool ADJ>
-__global__ void k_apply(const double *__restrict__ x, const double *__restrict__ s, double *__restrict__ y,
-                        const double *__restrict__ sig_t, const double *__restrict__ sig_s,
-                        const OrdInfo *__restrict__ ord, const double *__restrict__ w, int P, Grid g) {
-  constexpr int NS = 1 << DIM;
-  const long long C = g.C, S = g.S;
-  const long long total = (long long)P * C;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int q = (int)(t / C);
-    const long long j = t - (long long)q * C;
-    int ix[3] = {(int)(j % g.n[0]), (int)((j / g.n[0]) % g.n[1]), (int)(j / ((long long)g.n[0] * g.n[1]))};
-    double xv[3][NS];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) load_node_vec<double, NS>(x + (3LL * q + m) * S + j * NS, xv[m]);
-    double yk[3][NS];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const OrdInfo o = ord[3 * q + k];
-      const int flip = o.flip;
-      const double wk = ADJ ? w[3 * q + k] : 1.0;
-      double u[NS];
-#pragma unroll
-      for (int b = 0; b < NS; ++b) u[b] = wk * (xv[0][b] + xv[1][b] + xv[2][b] + 3.0 * xv[k][b]) * (1.0 / 6.0);
-      // removal
-      double r[NS];
-#pragma unroll
-      for (int b = 0; b < NS; ++b) r[b] = u[b];
-      mass_shape<double, DIM, false>(r);
-#pragma unroll
-      for (int b = 0; b < NS; ++b) r[b] *= sig_t[j] * g.vol;
-      // streaming |Omega_d| T1_d (x) N on the other axes (T1 = [[1,1],[-1,1]]/2
-      // oriented along the flow; its transpose is the flipped matrix),
-      // minus the coupling to the upwind (adjoint: downwind) neighbour
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const int fl = (flip >> d) & 1;
-        double tv[NS];
-#pragma unroll
-        for (int b = 0; b < NS; ++b) tv[b] = u[b];
-        if (fl != (ADJ ? 1 : 0))
-          axis_apply<DIM>(tv, d, 0.5, -0.5, 0.5, 0.5);
-        else
-          axis_apply<DIM>(tv, d, 0.5, 0.5, -0.5, 0.5);
-        double hs = 1.0;
-#pragma unroll
-        for (int e = 0; e < DIM; ++e)
-          if (e != d) {
-            axis_apply<DIM>(tv, e, 2.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 2.0 / 6.0);
-            hs *= g.h[e];
-          }
-#pragma unroll
-        for (int b = 0; b < NS; ++b) r[b] += o.a[d] * hs * tv[b];
-        // forward: neighbour upstream (fl ? +1 : -1); adjoint: downstream
-        const int step = (fl ? 1 : -1) * (ADJ ? -1 : 1);
-        const int ok = step > 0 ? (ix[d] < g.n[d] - 1) : (ix[d] > 0);
-        if (ok) {
-          int nx[3] = {ix[0], ix[1], ix[2]};
-          nx[d] += step;
-          const long long jn = nx[0] + (long long)g.n[0] * (nx[1] + (long long)g.n[1] * nx[2]);
-          // forward: neighbour's outflow face into own inflow face;
-          // adjoint: neighbour's inflow face into own outflow face
-          const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
-          const int own = 1 - nbit;
-          double tr[NS / 2];
-#pragma unroll
-          for (int tt = 0; tt < NS / 2; ++tt) {
-            const int b = insert_bit(tt, d, nbit);
-            const double x0 = x[(3LL * q + 0) * S + jn * NS + b];
-            const double x1 = x[(3LL * q + 1) * S + jn * NS + b];
-            const double x2 = x[(3LL * q + 2) * S + jn * NS + b];
-            const double xk = k == 0 ? x0 : (k == 1 ? x1 : x2);
-            tr[tt] = wk * (x0 + x1 + x2 + 3.0 * xk) * (1.0 / 6.0);
-          }
-          mass_shape<double, DIM - 1, false>(tr);
-#pragma unroll
-          for (int tt = 0; tt < NS / 2; ++tt) r[insert_bit(tt, d, own)] -= o.a[d] * hs * tr[tt];
-        }
-      }
-      const double wo = ADJ ? 1.0 : w[3 * q + k];
-#pragma unroll
-      for (int b = 0; b < NS; ++b) yk[k][b] = wo * r[b];
-    }
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      double sv[NS];
-      load_node_vec<double, NS>(s + (3LL * q + m) * S + j * NS, sv);
-      mass_shape<double, DIM, false>(sv);
-      double out[NS];
-#pragma unroll
-      for (int b = 0; b < NS; ++b)
-        out[b] = (yk[0][b] + yk[1][b] + yk[2][b] + 3.0 * yk[m][b]) * (1.0 / 6.0) - sig_s[j] * g.vol * sv[b];
-      store_node_vec<double, NS>(y + (3LL * q + m) * S + j * NS, out);
-    }
-  }
-}
-
-// Same operator with one lane per Q1 node: the 2^dim lanes of a cell group
-// hold the cell's node values, so every global access of a wave covers
-// whole cells (x, s, y and the neighbours' faces are read and written
-// 64 / 2^dim cells at a time), and the per-axis 2 x 2 operators are lane
-// exchanges along the node bits.
-template <int DIM>
-__device__ __forceinline__ double lane_axis(double v, int b, int d, double m00, double m01, double m10,
-                                            double m11) {
-  const double p = shx(v, 1 << d);
-  return ((b >> d) & 1) ? m10 * p + m11 * v : m00 * v + m01 * p;
-}
-
-template <int DIM, bool ADJ>
-__global__ __launch_bounds__(kBlock) void k_apply_lanes(const double *__restrict__ x, const double *__restrict__ s,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_apply_cells(const double *__restrict__ x, const double *__restrict__ s,
                                                         double *__restrict__ y, const double *__restrict__ sig_t,
                                                         const double *__restrict__ sig_s,
                                                         const OrdInfo *__restrict__ ord, const double *__restrict__ w,
-                                                        int P, Grid g) {
+                                                        int P, Grid g, int per_xcd) {
   constexpr int NS = 1 << DIM;
-  constexpr double m6 = 1.0 / 6.0, m3 = 1.0 / 3.0;
+  constexpr double m6 = 1.0 / 6.0;
+  // one (patch, cell) per thread; the workgroups of one XCD (dispatched
+  // round-robin over the 8) take one contiguous run of cells, so the
+  // neighbour cells one row or plane back are read from the same L2
+  const long long lb = (long long)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const long long t = lb * kBlock + threadIdx.x;
   const long long C = g.C, S = g.S;
-  const int b = threadIdx.x & (NS - 1);
-  const long long groups = (long long)P * C;
-  const long long gstride = (long long)gridDim.x * (kBlock / NS);
-  // whole waves iterate together (the exchanges need every lane); lanes of
-  // a group past the end work on group 0 and store nothing
-  const long long gbase = blockIdx.x * (long long)(kBlock / NS) + threadIdx.x / NS;
-  const long long wave_first = gbase - (threadIdx.x & 63) / NS;
-  for (long long t0 = wave_first; t0 < groups; t0 += gstride) {
-    const long long t = t0 + (threadIdx.x & 63) / NS;
-    const bool active = t < groups;
-    // 32-bit index arithmetic (patches x cells < 2^31, checked at launch):
-    // 64-bit divisions would dominate the kernel's instruction count
-    const unsigned tt = active ? (unsigned)t : 0u;
-    const unsigned q = tt / (unsigned)C;
-    const unsigned ju = tt - q * (unsigned)C;
-    const unsigned r0 = ju / (unsigned)g.n[0];
-    const int ix[3] = {(int)(ju - r0 * (unsigned)g.n[0]), (int)(r0 % (unsigned)g.n[1]), (int)(r0 / (unsigned)g.n[1])};
-    const long long j = ju;
-    const double st = sig_t[j], ss = sig_s[j];
-    double xv[3];
+  if (t >= (long long)P * C) return;
+  // 32-bit index arithmetic (patches x cells < 2^31, checked at launch)
+  const unsigned tt = (unsigned)t;
+  const unsigned q = tt / (unsigned)C;
+  const unsigned ju = tt - q * (unsigned)C;
+  const unsigned r0 = ju / (unsigned)g.n[0];
+  const int ix[3] = {(int)(ju - r0 * (unsigned)g.n[0]), (int)(r0 % (unsigned)g.n[1]), (int)(r0 / (unsigned)g.n[1])};
+  const long long j = ju;
+  const int fl0 = ord[3 * q].flip;  // the three ordinates of a patch share the octant
+  auto vec_load = [&](const double *p, double *v) {
 #pragma unroll
-    for (int m = 0; m < 3; ++m) xv[m] = x[(3LL * q + m) * S + j * NS + b];
-    // neighbour node values of the three patch dofs, one face per axis
-    double xn[DIM][3];
-    bool has[DIM];
-    int flip[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) flip[k] = ord[3 * q + k].flip;
-    const int fl0 = flip[0];  // the three ordinates of a patch share the octant
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const int fl = (fl0 >> d) & 1;
-      const int step = (fl ? 1 : -1) * (ADJ ? -1 : 1);
-      has[d] = step > 0 ? (ix[d] < g.n[d] - 1) : (ix[d] > 0);
-      int nx[3] = {ix[0], ix[1], ix[2]};
-      if (has[d]) nx[d] += step;
-      const long long jn = nx[0] + (long long)g.n[0] * (nx[1] + (long long)g.n[1] * nx[2]);
-      const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
-      const int bn = (b & ~(1 << d)) | (nbit << d);
-#pragma unroll
-      for (int m = 0; m < 3; ++m) xn[d][m] = x[(3LL * q + m) * S + jn * NS + bn];
+    for (int b = 0; b < NS; b += 2) {
+      const double2 u = *reinterpret_cast<const double2 *>(p + b);
+      v[b] = u.x;
+      v[b + 1] = u.y;
     }
-    double yk[3];
+  };
+  double xv[3][NS];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) vec_load(x + (3LL * q + m) * S + j * NS, xv[m]);
+  double hs[3];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    hs[d] = 1.0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e)
+      if (e != d) hs[d] *= g.h[e];
+  }
+  // T1 along d oriented with the flow (its transpose for the adjoint)
+  auto stream_axis = [&](double *v, int d) {
+    if (((fl0 >> d) & 1) != (ADJ ? 1 : 0))
+      axis_apply<DIM>(v, d, 0.5, -0.5, 0.5, 0.5);
+    else
+      axis_apply<DIM>(v, d, 0.5, 0.5, -0.5, 0.5);
+  };
+  auto mass_axis = [&](double *v, int d) { axis_apply<DIM>(v, d, 2.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 2.0 / 6.0); };
+  // volume terms of every ordinate: r_k = sigma_t vol N u_k + sum_d c_kd
+  // T1_d (x) N on the other axes u_k, the axis products shared between
+  // the terms (3-D: 7 axis products instead of 12, 2-D: 5 instead of 6)
+  const double stv = sig_t[j] * g.vol;
+  double yk[3][NS];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const OrdInfo &o = ord[3 * q + k];
+    const double wk = ADJ ? w[3 * q + k] : 1.0;
+    const double wo = ADJ ? 1.0 : w[3 * q + k];
+    double c[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) c[d] = o.a[d] * hs[d];
+    double u[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) u[b] = wk * (xv[0][b] + xv[1][b] + xv[2][b] + 3.0 * xv[k][b]) * m6;
+    // e, c and u are overwritten in place (three arrays live)
+    double e[NS], c1[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) e[b] = u[b];
+    if constexpr (DIM == 3) {
+      stream_axis(e, 2);
+      mass_axis(e, 1);  // e = N_y T_z u
+      mass_axis(u, 2);  // u = N_z u
+#pragma unroll
+      for (int b = 0; b < NS; ++b) c1[b] = u[b];
+      stream_axis(c1, 1);  // c1 = T_y N_z u
+      mass_axis(u, 1);     // u = N_y N_z u
+#pragma unroll
+      for (int b = 0; b < NS; ++b) c1[b] = stv * u[b] + c[1] * c1[b] + c[2] * e[b];
+      mass_axis(c1, 0);    // N_x (sigma_t vol N_y N_z u + c_y T_y N_z u + c_z N_y T_z u)
+      stream_axis(u, 0);   // u = T_x N_y N_z u
+    } else {
+      mass_axis(e, 0);
+      stream_axis(e, 1);  // e = T_y N_x u
+      mass_axis(u, 1);    // u = N_y u
+#pragma unroll
+      for (int b = 0; b < NS; ++b) c1[b] = u[b];
+      mass_axis(c1, 0);  // c1 = N_x N_y u
+#pragma unroll
+      for (int b = 0; b < NS; ++b) c1[b] = stv * c1[b] + c[1] * e[b];
+      stream_axis(u, 0);  // u = T_x N_y u
+    }
+    double r[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) r[b] = c1[b] + c[0] * u[b];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) yk[k][b] = wo * r[b];
+  }
+  // minus the coupling to the upwind (adjoint: downwind) neighbour along
+  // each axis: the neighbour's opposite face, applied on the own face
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int fl = (fl0 >> d) & 1;
+    const int step = (fl ? 1 : -1) * (ADJ ? -1 : 1);
+    const bool has = step > 0 ? (ix[d] < g.n[d] - 1) : (ix[d] > 0);
+    if (!has) continue;
+    const long long jn = j + (d == 0 ? step : d == 1 ? step * (long long)g.n[0] : step * (long long)g.n[0] * g.n[1]);
+    const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
+    const int own = 1 - nbit;
+    double xf[3][NS / 2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double *pn = x + (3LL * q + m) * S + jn * NS;
+#pragma unroll
+      for (int u = 0; u < NS / 2; ++u) xf[m][u] = pn[insert_bit(u, d, nbit)];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const OrdInfo &o = ord[3 * q + k];
       const double wk = ADJ ? w[3 * q + k] : 1.0;
-      const double u = wk * (xv[0] + xv[1] + xv[2] + 3.0 * xv[k]) * m6;
-      // removal sigma_t N u
-      double r = u;
+      const double wo = ADJ ? 1.0 : w[3 * q + k];
+      double tr[NS / 2];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) r = lane_axis<DIM>(r, b, d, m3, m6, m6, m3);
-      r *= st * g.vol;
+      for (int u = 0; u < NS / 2; ++u) tr[u] = wk * (xf[0][u] + xf[1][u] + xf[2][u] + 3.0 * xf[k][u]) * m6;
+      mass_shape<double, DIM - 1, false>(tr);
+      const double cn = wo * o.a[d] * hs[d];
+      // node b takes face value b without bit d, on the own face only
+      // (compile-time register indices: a selected factor, not a select of
+      // the register)
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const int fl = (fl0 >> d) & 1;
-        // streaming |Omega_d| T1_d (x) N on the other axes
-        double tv = (fl != (ADJ ? 1 : 0)) ? lane_axis<DIM>(u, b, d, 0.5, -0.5, 0.5, 0.5)
-                                          : lane_axis<DIM>(u, b, d, 0.5, 0.5, -0.5, 0.5);
-        double hs = 1.0;
-#pragma unroll
-        for (int e = 0; e < DIM; ++e)
-          if (e != d) {
-            tv = lane_axis<DIM>(tv, b, e, m3, m6, m6, m3);
-            hs *= g.h[e];
-          }
-        r += o.a[d] * hs * tv;
-        // minus the coupling to the upwind (adjoint: downwind) neighbour's
-        // face, applied on the own face
-        double tr = has[d] ? wk * (xn[d][0] + xn[d][1] + xn[d][2] + 3.0 * xn[d][k]) * m6 : 0.0;
-#pragma unroll
-        for (int e = 0; e < DIM; ++e)
-          if (e != d) tr = lane_axis<DIM>(tr, b, e, m3, m6, m6, m3);
-        const int nbit = (fl ? 0 : 1) ^ (ADJ ? 1 : 0);
-        if (((b >> d) & 1) == 1 - nbit) r -= o.a[d] * hs * tr;
+      for (int b = 0; b < NS; ++b) {
+        const int u = (b & ((1 << d) - 1)) | ((b >> (d + 1)) << d);
+        yk[k][b] -= (((b >> d) & 1) == own ? cn : 0.0) * tr[u];
       }
-      yk[k] = (ADJ ? 1.0 : w[3 * q + k]) * r;
     }
+  }
+  const double ssv = sig_s[j] * g.vol;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      double sv = s[(3LL * q + m) * S + j * NS + b];
+  for (int m = 0; m < 3; ++m) {
+    double sv[NS];
+    vec_load(s + (3LL * q + m) * S + j * NS, sv);
+    mass_shape<double, DIM, false>(sv);
+    double out[NS];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) sv = lane_axis<DIM>(sv, b, d, m3, m6, m6, m3);
-      const double out = (yk[0] + yk[1] + yk[2] + 3.0 * yk[m]) * m6 - ss * g.vol * sv;
-      if (active) y[(3LL * q + m) * S + j * NS + b] = out;
-    }
+    for (int b = 0; b < NS; ++b) out[b] = (yk[0][b] + yk[1][b] + yk[2][b] + 3.0 * yk[m][b]) * m6 - ssv * sv[b];
+    double *po = y + (3LL * q + m) * S + j * NS;
+#pragma unroll
+    for (int b = 0; b < NS; b += 2) *reinterpret_cast<double2 *>(po + b) = make_double2(out[b], out[b + 1]);
   }
 }
 
@@ -3183,22 +3128,25 @@ TR_INST_PROLONG(float, double)
 
 void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
                   const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
-  // one lane per node, kBlock / 2^dim cells per workgroup
+  // one (patch, cell) per thread; the grid a multiple of the 8 XCDs
   const long long cells = (long long)P * g.C;
   if (cells >= (1LL << 31)) throw std::runtime_error("operator apply: patches x cells must be below 2^31");
-  const int grid = (int)std::max(1LL, std::min((cells * g.ns + kBlock - 1) / kBlock, 16384LL));
+  const int per_xcd = (int)((cells + 8LL * kBlock - 1) / (8LL * kBlock));
+  const dim3 grid(8 * per_xcd);
   if (g.dim == 3) {
     if (adjoint)
-      hipLaunchKernelGGL((k_apply_lanes<3, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+      hipLaunchKernelGGL((k_apply_cells<3, true>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
+                         per_xcd);
     else
-      hipLaunchKernelGGL((k_apply_lanes<3, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P,
-                         g);
+      hipLaunchKernelGGL((k_apply_cells<3, false>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
+                         per_xcd);
   } else {
     if (adjoint)
-      hipLaunchKernelGGL((k_apply_lanes<2, true>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g);
+      hipLaunchKernelGGL((k_apply_cells<2, true>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
+                         per_xcd);
     else
-      hipLaunchKernelGGL((k_apply_lanes<2, false>), dim3(grid), dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P,
-                         g);
+      hipLaunchKernelGGL((k_apply_cells<2, false>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
+                         per_xcd);
   }
 }
 
