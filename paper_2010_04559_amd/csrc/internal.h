@@ -172,8 +172,6 @@ void launch_axpby(long long n, double a, const double *x, double b, const double
 template <typename T>
 void launch_fill(T *x, long long n, T v, hipStream_t st);
 void launch_fill_u32(unsigned *x, long long n, hipStream_t st);  // x[0..n) = 0
-template <typename Tin, typename Tout>
-void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st);
 
 // C[M][N] = A[M][K] * B[K][N]   (row-major; ld of B and C is N)
 // C[M][N] = A[M][K] B[K][N] on the matrix cores; with bias / colscale:

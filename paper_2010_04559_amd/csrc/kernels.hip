@@ -2021,14 +2021,16 @@ __global__ __launch_bounds__(192) void k_gs_brick(const double *__restrict__ f, 
 
 // ------------------------------------------------------------- conversions
 template <typename Tin, typename Tout>
-__global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, int P, long long S,
-                          const double *__restrict__ pre, const double *__restrict__ post, double scale,
-                          double *__restrict__ out64) {
-  const long long total = (long long)P * S;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int p = (int)(t / S);
-    const long long s = t - (long long)p * S;
+__global__ __launch_bounds__(kBlock) void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, int P,
+                                                    long long S, const double *__restrict__ pre,
+                                                    const double *__restrict__ post, double scale,
+                                                    double *__restrict__ out64) {
+  // one thread per (patch, spatial dof), 32-bit indices (below 2^32,
+  // checked at launch)
+  const unsigned t = blockIdx.x * (unsigned)kBlock + threadIdx.x;
+  if (t < (unsigned)P * (unsigned)S) {
+    const unsigned p = t / (unsigned)S;
+    const long long s = t - p * (unsigned)S;
     double x[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -2050,132 +2052,106 @@ __global__ void k_convert(const Tin *__restrict__ in, Tout *__restrict__ out, in
 
 // Conversion of a forward right-hand side into prepared ordinate form:
 // the ordinate conversion above, then the inverse cell mass matrix applied
-// per ordinate (f~ = N^{-1} f).  One thread per (patch, cell).
+// per ordinate (f~ = N^{-1} f).  One lane per (patch, spatial dof): the
+// 2^dim lanes of a cell are one aligned group and the inverse mass shape is
+// a lane exchange inside it; reads and writes of consecutive lanes are
+// consecutive (plane layout: whole cells at their list positions).
 template <typename Tin, typename Tout, int DIM>
-__global__ void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ out, int P, Grid g,
-                               const double *__restrict__ pre, const double *__restrict__ post,
-                               const int *__restrict__ pos, const OrdInfo *__restrict__ ord, double scale) {
+__global__ __launch_bounds__(kBlock) void k_convert_minv(const Tin *__restrict__ in, Tout *__restrict__ out, int P,
+                                                         Grid g, const double *__restrict__ pre,
+                                                         const double *__restrict__ post,
+                                                         const int *__restrict__ pos,
+                                                         const OrdInfo *__restrict__ ord, double scale) {
   constexpr int NS = 1 << DIM;
-  const long long C = g.C, S = g.S;
-  const long long total = (long long)P * C;
+  const unsigned S = (unsigned)g.S;
+  const unsigned t = blockIdx.x * (unsigned)kBlock + threadIdx.x;
+  if (t >= (unsigned)P * S) return;  // whole cell groups
+  const unsigned p = t / S;
+  const unsigned rem = t - p * S;
+  const unsigned j = rem >> DIM;
   const double iv = 1.0 / g.vol;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int p = (int)(t / C);
-    const long long j = t - (long long)p * C;
-    double x[3][NS];
+  double x[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const double sc = (pre ? pre[3 * p + m] : 1.0) * scale;
+  for (int m = 0; m < 3; ++m) x[m] = (double)in[(3LL * p + m) * S + rem] * ((pre ? pre[3 * p + m] : 1.0) * scale);
+  // plane layout (the three ordinates of a patch share the orientation)
+  const unsigned jo = pos ? (unsigned)pos[(long long)ord[3 * p].flip * g.C + j] : j;
+  const long long ro = ((long long)jo << DIM) + (rem & (NS - 1));
 #pragma unroll
-      for (int b = 0; b < NS; ++b) x[m][b] = (double)in[(3LL * p + m) * S + j * NS + b] * sc;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double sc = post ? post[3 * p + k] : 1.0;
-      double y[NS];
-#pragma unroll
-      for (int b = 0; b < NS; ++b) y[b] = (2.0 * x[k][b] - (x[0][b] + x[1][b] + x[2][b]) * (1.0 / 3.0)) * sc;
-      mass_shape<double, DIM, true>(y);
-      // plane layout (the three ordinates of a patch share the orientation)
-      const long long jo = pos ? (long long)pos[(long long)ord[3 * p].flip * C + j] : j;
-#pragma unroll
-      for (int b = 0; b < NS; ++b) out[(3LL * p + k) * S + jo * NS + b] = (Tout)(y[b] * iv);
-    }
+  for (int k = 0; k < 3; ++k) {
+    const double y = (2.0 * x[k] - (x[0] + x[1] + x[2]) * (1.0 / 3.0)) * (post ? post[3 * p + k] : 1.0);
+    out[(3LL * p + k) * S + ro] = (Tout)(lane_mass<DIM>(y, NS - 1, true) * iv);
   }
 }
 
 // ------------------------------------------------------------- transfers
 template <typename Tin, typename Tout, int DIM>
-__global__ void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict__ s_prev, Tout *__restrict__ fc,
-                           const double *__restrict__ R, const int *__restrict__ first_child,
-                           const int *__restrict__ n_child, int Pc, const double *__restrict__ sig_s,
-                           int apply_sn, Grid g, const int *__restrict__ pos, const OrdInfo *__restrict__ cord) {
+__global__ __launch_bounds__(kBlock) void k_restrict(const Tin *__restrict__ s_new, const Tin *__restrict__ s_prev,
+                                                     Tout *__restrict__ fc, const double *__restrict__ R,
+                                                     const int *__restrict__ first_child,
+                                                     const int *__restrict__ n_child, int Pc,
+                                                     const double *__restrict__ sig_s, int apply_sn, Grid g,
+                                                     const int *__restrict__ pos, const OrdInfo *__restrict__ cord) {
+  // one lane per (coarse patch, spatial dof): consecutive lanes read and
+  // write consecutive values, the 2^dim lanes of a cell are one aligned
+  // group (the mass shape of the adjoint is a lane exchange inside it)
   constexpr int NS = 1 << DIM;
-  // children whose loads are issued together (a parent has one or four):
-  // all four in FP32, two at a time in FP64 (registers)
-  constexpr int CH = sizeof(Tin) == 4 ? 4 : 2;
-  const long long C = g.C, S = g.S;
-  const long long total = (long long)Pc * C;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int p = (int)(t / C);
-    const long long j = t - (long long)p * C;
-    double out[3][NS];
+  const unsigned S = (unsigned)g.S;
+  const unsigned t = blockIdx.x * (unsigned)kBlock + threadIdx.x;
+  if (t >= (unsigned)Pc * S) return;  // whole cell groups (S is a multiple of 2^dim)
+  const unsigned p = t / S;
+  const unsigned rem = t - p * S;
+  const unsigned j = rem >> DIM;
+  const int c0 = first_child[p], nc = n_child[p];
+  const double fsn = apply_sn ? sig_s[j] * g.vol : 1.0;
+  double out[3] = {0.0, 0.0, 0.0};
+  for (int cb = 0; cb < nc; cb += 4) {
+    // the loads of up to four children first (a parent has one or four)
+    Tin xr[4][3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
+    for (int cc = 0; cc < 4; ++cc) {
+      const unsigned c = (unsigned)(c0 + min(cb + cc, nc - 1));
 #pragma unroll
-      for (int b = 0; b < NS; ++b) out[m][b] = 0.0;
-    const int c0 = first_child[p], nc = n_child[p];
-    const double fsn = apply_sn ? sig_s[j] * g.vol : 1.0;
-    for (int cb = 0; cb < nc; cb += CH) {
-      // every load of this group first (children past the last read the
-      // last again and are dropped)
-      Tin xr[CH][3][NS];
-#pragma unroll
-      for (int cc = 0; cc < CH; ++cc) {
-        const int c = c0 + min(cb + cc, nc - 1);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const long long off = (3LL * c + m) * S + j * NS;
-#pragma unroll
-          for (int b = 0; b < NS; ++b) {
-            Tin v = s_new[off + b];
-            if (s_prev) v -= s_prev[off + b];
-            xr[cc][m][b] = v;
-          }
-        }
-      }
-#pragma unroll
-      for (int cc = 0; cc < CH; ++cc) {
-        if (cb + cc >= nc) break;
-        const int c = c0 + cb + cc;
-        double x[3][NS];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-#pragma unroll
-          for (int b = 0; b < NS; ++b) x[m][b] = (double)xr[cc][m][b];
-          if (apply_sn) {
-            mass_shape<double, DIM, false>(x[m]);
-#pragma unroll
-            for (int b = 0; b < NS; ++b) x[m][b] *= fsn;
-          }
-        }
-        const double *Rc = R + 9LL * c;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const double r = Rc[k * 3 + m];
-#pragma unroll
-            for (int b = 0; b < NS; ++b) out[k][b] += r * x[m][b];
-          }
+      for (int m = 0; m < 3; ++m) {
+        const long long off = (3LL * c + m) * S + rem;
+        Tin v = s_new[off];
+        if (s_prev) v -= s_prev[off];
+        xr[cc][m] = v;
       }
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      // plane layout: the cell's position in its ordinate's sweep list (the
-      // three ordinates of a patch share the orientation)
-      const long long jo = pos ? (long long)pos[(long long)cord[3 * p].flip * C + j] : j;
-      const long long off = (3LL * p + k) * S + jo * NS;
+    for (int cc = 0; cc < 4; ++cc) {
+      if (cb + cc >= nc) break;
+      const double *Rc = R + 9LL * (c0 + cb + cc);
+      double x[3];
 #pragma unroll
-      for (int b = 0; b < NS; ++b) fc[off + b] = (Tout)out[k][b];
+      for (int m = 0; m < 3; ++m) {
+        x[m] = (double)xr[cc][m];
+        if (apply_sn) x[m] = fsn * lane_mass<DIM>(x[m], NS - 1, false);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) out[k] += Rc[k * 3] * x[0] + Rc[k * 3 + 1] * x[1] + Rc[k * 3 + 2] * x[2];
     }
   }
+  // plane layout: the cell's position in its ordinate's sweep list (the
+  // three ordinates of a patch share the orientation)
+  const unsigned jo = pos ? (unsigned)pos[(long long)cord[3 * p].flip * g.C + j] : j;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) fc[(3LL * p + k) * S + ((long long)jo << DIM) + (rem & (NS - 1))] = (Tout)out[k];
 }
 
 // One thread per (coarse patch p, spatial dof s): the parent's three values
 // are read once for all of its children (one, or four when it is refined),
 // whose fine values are then written (added to with add).
 template <typename Tin, typename Tout>
-__global__ void k_prolong(const Tin *__restrict__ uc, Tout *__restrict__ uf, const double *__restrict__ Pb,
-                          const int *__restrict__ first_child, const int *__restrict__ n_child, int Pc, long long S,
-                          int add) {
-  const long long total = (long long)Pc * S;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int p = (int)(t / S);
-    const long long s = t - (long long)p * S;
+__global__ __launch_bounds__(kBlock) void k_prolong(const Tin *__restrict__ uc, Tout *__restrict__ uf,
+                                                    const double *__restrict__ Pb,
+                                                    const int *__restrict__ first_child,
+                                                    const int *__restrict__ n_child, int Pc, long long S, int add) {
+  // 32-bit indices (patches x spatial dofs < 2^32, checked at launch)
+  const unsigned t = blockIdx.x * (unsigned)kBlock + threadIdx.x;
+  if (t < (unsigned)Pc * (unsigned)S) {
+    const unsigned p = t / (unsigned)S;
+    const long long s = t - p * (unsigned)S;
     double x[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) x[d] = (double)uc[(3LL * p + d) * S + s];
@@ -2740,12 +2716,6 @@ __global__ void k_fill(T *x, long long n, T v) {
     x[i] = v;
 }
 
-template <typename Tin, typename Tout>
-__global__ void k_cast(const Tin *__restrict__ in, Tout *__restrict__ out, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    out[i] = (Tout)in[i];
-}
-
 int grid_for(long long n, int block = kBlock) {
   long long g = (n + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -3062,19 +3032,23 @@ void launch_coarse_gs(const double *f, double *u, const double *G, const double 
 template <typename Tin, typename Tout>
 void launch_convert(const Tin *in, Tout *out, int P, long long S, const double *pre, const double *post,
                     hipStream_t st, double scale, double *out64) {
-  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for((long long)P * S)), dim3(kBlock), 0, st, in, out, P, S,
-                     pre, post, scale, out64);
+  const long long n = (long long)P * S;
+  if (n >= (1LL << 32) - kBlock) throw std::runtime_error("conversion: patches x spatial dofs must be below 2^32");
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, in, out,
+                     P, S, pre, post, scale, out64);
 }
 template <typename Tin, typename Tout>
 void launch_convert_minv(const Tin *in, Tout *out, int P, const Grid &g, const double *pre, const double *post,
                          hipStream_t st, const int *pos, const OrdInfo *ord, double scale) {
-  const int grid = grid_for((long long)P * g.C);
+  const long long n = (long long)P * g.S;
+  if (n >= (1LL << 32) - kBlock) throw std::runtime_error("conversion: patches x spatial dofs must be below 2^32");
+  const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post, pos,
-                       ord, scale);
+    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 3>), grid, dim3(kBlock), 0, st, in, out, P, g, pre, post, pos, ord,
+                       scale);
   else
-    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, P, g, pre, post, pos,
-                       ord, scale);
+    hipLaunchKernelGGL((k_convert_minv<Tin, Tout, 2>), grid, dim3(kBlock), 0, st, in, out, P, g, pre, post, pos, ord,
+                       scale);
 }
 template void launch_convert_minv<double, double>(const double *, double *, int, const Grid &, const double *,
                                                   const double *, hipStream_t, const int *, const OrdInfo *, double);
@@ -3095,13 +3069,16 @@ template <typename Tin, typename Tout>
 void launch_restrict(const Tin *s_new, const Tin *s_prev, Tout *fc, const double *R, const int *first_child,
                      const int *n_child, int Pc, const double *sig_s, bool apply_sn, const Grid &g,
                      hipStream_t st, const int *pos, const OrdInfo *cord) {
-  const int grid = grid_for((long long)Pc * g.C);
+  // one lane per (coarse patch, spatial dof), 32-bit indices
+  const long long n = (long long)Pc * g.S;
+  if (n >= (1LL << 32) - kBlock) throw std::runtime_error("restriction: coarse patches x spatial dofs must be below 2^32");
+  const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_restrict<Tin, Tout, 3>), dim3(grid), dim3(kBlock), 0, st, s_new, s_prev, fc, R,
-                       first_child, n_child, Pc, sig_s, (int)apply_sn, g, pos, cord);
+    hipLaunchKernelGGL((k_restrict<Tin, Tout, 3>), grid, dim3(kBlock), 0, st, s_new, s_prev, fc, R, first_child,
+                       n_child, Pc, sig_s, (int)apply_sn, g, pos, cord);
   else
-    hipLaunchKernelGGL((k_restrict<Tin, Tout, 2>), dim3(grid), dim3(kBlock), 0, st, s_new, s_prev, fc, R,
-                       first_child, n_child, Pc, sig_s, (int)apply_sn, g, pos, cord);
+    hipLaunchKernelGGL((k_restrict<Tin, Tout, 2>), grid, dim3(kBlock), 0, st, s_new, s_prev, fc, R, first_child,
+                       n_child, Pc, sig_s, (int)apply_sn, g, pos, cord);
 }
 #define TR_INST_RESTRICT(TI, TO)                                                                               \
   template void launch_restrict<TI, TO>(const TI *, const TI *, TO *, const double *, const int *, const int *, \
@@ -3115,8 +3092,10 @@ TR_INST_RESTRICT(double, float)
 template <typename Tin, typename Tout>
 void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *first_child, const int *n_child, int Pc,
                     long long S, bool add, hipStream_t st) {
-  hipLaunchKernelGGL((k_prolong<Tin, Tout>), dim3(grid_for((long long)Pc * S)), dim3(kBlock), 0, st, uc, uf, Pblk,
-                     first_child, n_child, Pc, S, (int)add);
+  const long long n = (long long)Pc * S;
+  if (n >= (1LL << 32) - kBlock) throw std::runtime_error("prolongation: coarse patches x spatial dofs must be below 2^32");
+  hipLaunchKernelGGL((k_prolong<Tin, Tout>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, uc, uf,
+                     Pblk, first_child, n_child, Pc, S, (int)add);
 }
 #define TR_INST_PROLONG(TI, TO)                                                                                    \
   template void launch_prolong<TI, TO>(const TI *, TO *, const double *, const int *, const int *, int, long long, \
@@ -3292,11 +3271,5 @@ void launch_fill_u32(unsigned *x, long long n, hipStream_t st) {
 }
 template void launch_fill<double>(double *, long long, double, hipStream_t);
 template void launch_fill<float>(float *, long long, float, hipStream_t);
-template <typename Tin, typename Tout>
-void launch_cast(const Tin *in, Tout *out, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(kBlock), 0, st, in, out, n);
-}
-template void launch_cast<double, float>(const double *, float *, long long, hipStream_t);
-template void launch_cast<float, double>(const float *, double *, long long, hipStream_t);
 
 }  // namespace tr
