@@ -860,27 +860,29 @@ void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, i
                      const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
   if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
   const int nc = om.nc;
-#define TR_OCT(BM, BN, BK, DB, ALL)                                                                              \
+#define TR_OCT(BM, BN, BK, WPE, DB, ALL)                                                                              \
   switch (om.R) {                                                                                                 \
     case 1:                                                                                                       \
-      launch_oct_shape<T, 1, BM, BN, BK, 2, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+      launch_oct_shape<T, 1, BM, BN, BK, WPE, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
       break;                                                                                                      \
     case 2:                                                                                                       \
-      launch_oct_shape<T, 2, BM, BN, BK, 2, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+      launch_oct_shape<T, 2, BM, BN, BK, WPE, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
       break;                                                                                                      \
     case 3:                                                                                                       \
-      launch_oct_shape<T, 3, BM, BN, BK, 2, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
+      launch_oct_shape<T, 3, BM, BN, BK, WPE, DB, ALL>(Bh, ldb, U, C, om, nc, N, st, bias, colscale, cell, pos, rord); \
       break;                                                                                                      \
     default: throw std::runtime_error("octant-group GEMM: 1 to 3 reflected axes");                                \
   }
   // shapes measured on MI355X (three axes, N = 884736): FP64 32 x 64 x 8
-  // with one LDS buffer and every thread loading, 14.5 ms at nc = 192 (36
-  // TF/s) and 1.9 ms at nc = 48; FP32 32 x 64 x 8 double-buffered, 9.0 and
-  // 1.2 ms
+  // with one LDS buffer and every thread loading, two waves per SIMD, 15.2
+  // ms at nc = 192 (34 TF/s) and 2.0 ms at nc = 48 (32 x 32 x 8 and 16: 19
+  // and 17 ms); FP32 32 x 64 x 16 with one LDS buffer, every thread
+  // loading, three waves per SIMD, 8.2 and 1.16 ms (32 x 64 x 8 double
+  // buffered: 9.1 and 1.3 ms; 64 x 64 x 16: 8.3 and 1.5 ms)
   if constexpr (sizeof(T) == 8) {
-    TR_OCT(32, 64, 8, false, true)
+    TR_OCT(32, 64, 8, 2, false, true)
   } else {
-    TR_OCT(32, 64, 8, true, false)
+    TR_OCT(32, 64, 16, 3, false, true)
   }
 #undef TR_OCT
 }
