@@ -134,8 +134,11 @@ template <typename Tin, typename Tout>
 void launch_prolong(const Tin *uc, Tout *uf, const double *Pblk, const int *first_child, const int *n_child, int Pc,
                     long long S, bool add, hipStream_t st);
 
-// y = L x - sigma_s N s  (canonical FP64, s = S~ x); adjoint: L^T x - sigma_s N s
+// y = L x - sigma_s N s  (canonical FP64, s = S~ x); adjoint: L^T x - sigma_s N s.
+// The float form reads an FP32 x (its values widened exactly to FP64).
 void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
+                  const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st);
+void launch_apply(const float *x, const double *s, double *y, const double *sig_t, const double *sig_s,
                   const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st);
 
 // out[a][j][i] = sigma_s[j] vol Nshape(in[a][j][.])[i]

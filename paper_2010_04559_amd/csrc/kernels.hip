@@ -2200,8 +2200,8 @@ __device__ __forceinline__ void axis_apply(double *v, int d, double m00, double 
 //           coupling, y = Psi W r.
 // Adjoint:  L^T = Psi L^T_ord W Psi: mu = W Psi x, r_k = A_loc^T mu_k -
 //           downwind coupling, y = Psi r (S is symmetric, so S^T x = S x).
-template <int DIM, bool ADJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_apply_cells(const double *__restrict__ x, const double *__restrict__ s,
+template <int DIM, bool ADJ, typename TX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_apply_cells(const TX *__restrict__ x, const double *__restrict__ s,
                                                         double *__restrict__ y, const double *__restrict__ sig_t,
                                                         const double *__restrict__ sig_s,
                                                         const OrdInfo *__restrict__ ord, const double *__restrict__ w,
@@ -2231,9 +2231,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       v[b + 1] = u.y;
     }
   };
+  // x in FP64, or FP32 widened exactly
+  auto x_load = [&](const TX *p, double *v) {
+    if constexpr (sizeof(TX) == 8) {
+      vec_load(reinterpret_cast<const double *>(p), v);
+    } else {
+#pragma unroll
+      for (int b = 0; b < NS; b += 4) {
+        const float4 u = *reinterpret_cast<const float4 *>(p + b);
+        v[b] = u.x;
+        v[b + 1] = u.y;
+        v[b + 2] = u.z;
+        v[b + 3] = u.w;
+      }
+    }
+  };
   double xv[3][NS];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) vec_load(x + (3LL * q + m) * S + j * NS, xv[m]);
+  for (int m = 0; m < 3; ++m) x_load(x + (3LL * q + m) * S + j * NS, xv[m]);
   double hs[3];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -2313,9 +2328,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     double xf[3][NS / 2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const double *pn = x + (3LL * q + m) * S + jn * NS;
+      const TX *pn = x + (3LL * q + m) * S + jn * NS;
 #pragma unroll
-      for (int u = 0; u < NS / 2; ++u) xf[m][u] = pn[insert_bit(u, d, nbit)];
+      for (int u = 0; u < NS / 2; ++u) xf[m][u] = (double)pn[insert_bit(u, d, nbit)];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -3105,8 +3120,9 @@ TR_INST_PROLONG(float, float)
 TR_INST_PROLONG(double, float)
 TR_INST_PROLONG(float, double)
 
-void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
-                  const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
+template <typename TX>
+static void launch_apply_t(const TX *x, const double *s, double *y, const double *sig_t, const double *sig_s,
+                           const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
   // one (patch, cell) per thread; the grid a multiple of the 8 XCDs
   const long long cells = (long long)P * g.C;
   if (cells >= (1LL << 31)) throw std::runtime_error("operator apply: patches x cells must be below 2^31");
@@ -3114,19 +3130,27 @@ void launch_apply(const double *x, const double *s, double *y, const double *sig
   const dim3 grid(8 * per_xcd);
   if (g.dim == 3) {
     if (adjoint)
-      hipLaunchKernelGGL((k_apply_cells<3, true>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
+      hipLaunchKernelGGL((k_apply_cells<3, true, TX>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
                          per_xcd);
     else
-      hipLaunchKernelGGL((k_apply_cells<3, false>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
-                         per_xcd);
+      hipLaunchKernelGGL((k_apply_cells<3, false, TX>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P,
+                         g, per_xcd);
   } else {
     if (adjoint)
-      hipLaunchKernelGGL((k_apply_cells<2, true>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
+      hipLaunchKernelGGL((k_apply_cells<2, true, TX>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
                          per_xcd);
     else
-      hipLaunchKernelGGL((k_apply_cells<2, false>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P, g,
-                         per_xcd);
+      hipLaunchKernelGGL((k_apply_cells<2, false, TX>), grid, dim3(kBlock), 0, st, x, s, y, sig_t, sig_s, ord, w, P,
+                         g, per_xcd);
   }
+}
+void launch_apply(const double *x, const double *s, double *y, const double *sig_t, const double *sig_s,
+                  const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
+  launch_apply_t(x, s, y, sig_t, sig_s, ord, w, P, g, adjoint, st);
+}
+void launch_apply(const float *x, const double *s, double *y, const double *sig_t, const double *sig_s,
+                  const OrdInfo *ord, const double *w, int P, const Grid &g, bool adjoint, hipStream_t st) {
+  launch_apply_t(x, s, y, sig_t, sig_s, ord, w, P, g, adjoint, st);
 }
 
 template <typename T>

@@ -1299,8 +1299,9 @@ void convert_in(tr_handle *h, int level, bool adj, const Tin *r, Tout *f, hipStr
 // z = out_scale M^{-1} (in_scale r).  The scales keep the FP32 V-cycle's
 // input at unit size whatever the scale of r (GMRES passes its unnormalised
 // basis vectors with the normalising factor).  With z32 (FP32 preconditioner
-// modes only) the result is also left in FP32 in z32 and z is its exact
-// FP64 image, so the flexible GMRES update can use the stored FP32 vectors.
+// modes only) the result is also left in FP32 in z32 and z, if not null,
+// is its exact FP64 image, so the flexible GMRES update can use the stored
+// FP32 vectors.
 void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, hipStream_t st,
                   double in_scale = 1.0, double out_scale = 1.0, float *z32 = nullptr) {
   const int L = h->top();
@@ -1309,6 +1310,7 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
   const double *pre_out = adj ? D.winv : nullptr, *post_out = nullptr;
   const bool mixed = (mode == TR_PREC_MIXED || mode == TR_PREC_MIXED_BF16) && L > 0;
   if (z32 && !mixed) throw std::runtime_error("internal: FP32 preconditioned vectors need an FP32 V-cycle");
+  if (!z && !z32) throw std::runtime_error("internal: preconditioner without an output");
   if (mode == TR_PREC_SG || L == 0) {
     tbegin(h, C_OTHER);
     convert_in<double, double>(h, L, adj, r, D.f64, st, in_scale);
@@ -1335,8 +1337,8 @@ void precondition(tr_handle *h, int mode, bool adj, const double *r, double *z, 
     mg_level<float>(h, L, adj, st);
     tbegin(h, C_OTHER);
     if (z32) {
-      // the FP32 vector kept for the flexible update and its FP64 copy for
-      // the operator, in one pass
+      // the FP32 vector kept for the flexible update and (z) its FP64 copy
+      // for the operator, in one pass
       tr::launch_convert<float, float>(D.u32, z32, D.P, h->g.S, pre_out, post_out, st, out_scale, z);
     } else {
       tr::launch_convert<float, double>(D.u32, z, D.P, h->g.S, pre_out, post_out, st, out_scale);
@@ -1370,6 +1372,19 @@ void apply_A(tr_handle *h, bool adj, const double *x, double *y, hipStream_t st)
   tend(h);
   tbegin(h, C_APPLY);
   tr::launch_apply(x, h->tmp, y, h->sig_t, h->sig_s, D.ord, D.w, D.P, h->g, adj, st);
+  tend(h);
+}
+
+// y = A x for x held twice, in FP64 (x) and as the FP32 values it widens
+// exactly (x32): the scatter product reads x, the transport stencil the
+// half-size x32
+void apply_A_pair(tr_handle *h, bool adj, const double *x, const float *x32, double *y, hipStream_t st) {
+  DevLevel &D = h->lv[h->top()];
+  tbegin(h, C_SCATTER_OUTER);
+  outer_scatter(h, x, h->tmp, st);
+  tend(h);
+  tbegin(h, C_APPLY);
+  tr::launch_apply(x32, h->tmp, y, h->sig_t, h->sig_s, D.ord, D.w, D.P, h->g, adj, st);
   tend(h);
 }
 
@@ -1520,7 +1535,10 @@ int gmres(tr_handle *h, bool adj, const double *b, double *x, const tr_solve_opt
       double *zj = zkind == 64 ? h->Z[j] : h->tmp2;
       double *W = h->kw;
       precondition(h, o->prec_mode, adj, h->V[j], zj, st, vs[j], 1.0, zkind == 32 ? h->Z32[j] : nullptr);
-      apply_A(h, adj, zj, W, st);
+      if (zkind == 32)
+        apply_A_pair(h, adj, zj, h->Z32[j], W, st);  // the stencil reads the FP32 copy
+      else
+        apply_A(h, adj, zj, W, st);
       stats->iters++;
       // modified Gram-Schmidt (two passes over the basis, see arnoldi_orth)
       tbegin(h, C_ORTH);
