@@ -632,6 +632,12 @@ void build(tr_handle *h, const tr_problem *p) {
       if (!(H.w[a] > 0)) throw ArgError{"internal: nonpositive quadrature weight"};
       winv[a] = 1.0 / H.w[a];
     }
+    // the three ordinates of a patch sweep in one orientation (the operator
+    // apply, the plane-layout transfers and the coarse solve rely on it;
+    // octant-contained patches guarantee it)
+    for (int a = 0; a + 2 < H.A; a += 3)
+      if (ord[a].flip != ord[a + 1].flip || ord[a].flip != ord[a + 2].flip)
+        throw std::runtime_error("internal: ordinates of one patch in different orientations");
     D.ord = h->upload(ord);
     // forward sweep inputs in plane layout on the V-cycle's smoothing levels
     // when their sweeps run in the LDS kernel (one pre-smoothing sweep: the
