@@ -121,7 +121,7 @@ def test_autograd_detector_response_matches_oracle():
     st = torch.tensor(prob.sigma_t, dtype=torch.float64, device="cuda", requires_grad=True)
     ss = torch.tensor(prob.sigma_s, dtype=torch.float64, device="cuda", requires_grad=True)
     R = detector_response(pr.tr, st, ss, to_dev(b_np), to_dev(w_np), "f64", 1e-12)
-    assert abs(float(R) - R_ref) < 1e-10 * abs(R_ref)
+    assert abs(float(R.detach()) - R_ref) < 1e-10 * abs(R_ref)
     (3.0 * R).backward()
     assert rel(to_np(st.grad), 3.0 * gt_ref) < 1e-9
     assert rel(to_np(ss.grad), 3.0 * gs_ref) < 1e-9
