@@ -189,3 +189,37 @@ def test_cfg3_solves(cfg3):
     y = tr.apply(x)
     y -= b
     assert float(torch.linalg.norm(y) / torch.linalg.norm(b)) < 1e-8
+
+
+def test_cfg3_bench_cycle(cfg3):
+    """The benchmark's V-cycle on the same problem (inputs.CFG3_CYCLE):
+    FP32-MG and FP64 solves converge in at most 6 iterations, agree to 1e-7,
+    and the FP64 solution's explicit residual is below 1e-8.  Runs last: it
+    releases the module's handle for a handle of its own."""
+    prob, tr, grid, mesh, qs, cells = cfg3
+    torch = torch_mod()
+    from paper_2010_04559_amd.transport import Transport
+    tr.close()
+    torch.cuda.empty_cache()
+    pb = inputs.config3()
+    pb.nu_pre, pb.nu_post, pb.nu_coarse = inputs.CFG3_CYCLE
+    tb = Transport(pb)
+    try:
+        b = tb.rhs()
+        xm, stm = tb.solve(b, mode="mixed")
+        assert stm["converged"] == 1 and stm["flexible"] == 32 and stm["iters"] <= 6
+        x, st = tb.solve(b)
+        assert st["converged"] == 1 and st["iters"] <= 6
+        print("bench cycle V(%d,%d)/%d: iterations fp32 %d, fp64 %d" % (pb.nu_pre, pb.nu_post, pb.nu_coarse,
+                                                                       stm["iters"], st["iters"]), flush=True)
+        d2 = 0.0
+        for i in range(0, x.numel(), 1 << 27):
+            t = xm[i:i + (1 << 27)] - x[i:i + (1 << 27)]
+            d2 += float(torch.dot(t, t))
+        assert d2 ** 0.5 / float(torch.linalg.norm(x)) < 1e-7
+        del xm
+        y = tb.apply(x)
+        y -= b
+        assert float(torch.linalg.norm(y) / torch.linalg.norm(b)) < 1e-8
+    finally:
+        tb.close()
