@@ -63,6 +63,10 @@ struct Vec16 {
 
 constexpr int kXcds = 8;
 
+// Spatial dofs per cell (4 or 8, checked at launch) as a shift: the
+// epilogues' column -> cell arithmetic without integer division.
+__device__ __forceinline__ int cell_shift(int cell) { return cell == 8 ? 3 : 2; }
+
 // Plane-layout output (a sweep input): column gn of row gm goes to the
 // cell's position in row gm's orientation list, keeping the node index; the
 // bias is read at the same place.  The workgroup stages the orientation of
@@ -94,8 +98,8 @@ template <int BM, int BN>
 __device__ __forceinline__ long long out_col(const OutMap<BM, BN> &om, long long gn, int gm, int m0, long long n0,
                                              int cell, const int *pos) {
   if (!pos) return gn;
-  const int c = (int)((gn - n0) / cell);
-  return (long long)om.pos[om.flip[gm - m0]][c] * cell + (gn % cell);
+  const int c = (int)(gn - n0) >> cell_shift(cell);
+  return (long long)om.pos[om.flip[gm - m0]][c] * cell + (gn & (cell - 1));
 }
 
 // C = G * U, optionally C = bias + diag-per-column(colscale) * (G * U) where
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
     for (int jn = 0; jn < TN; ++jn) {
       const long long gn = n0 + wn0 + jn * 16 + lrow;
-      const T cs = (colscale && gn < N) ? T(colscale[gn / cell]) : T(1);
+      const T cs = (colscale && gn < N) ? T(colscale[gn >> cell_shift(cell)]) : T(1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long gn = n0 + wn0 + 16 * j + lr;
-      const float cs = (colscale && gn < N) ? (float)colscale[gn / cell] : 1.f;
+      const float cs = (colscale && gn < N) ? (float)colscale[gn >> cell_shift(cell)] : 1.f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm0 + 16 * i + 4 * lk + r;
@@ -475,7 +479,8 @@ __device__ __forceinline__ void oct_store(const typename Mma<T>::acc_t (&acc)[1 
 #pragma unroll
     for (int jn = 0; jn < TN; ++jn) {
       const long long gn = n0 + wn0 + jn * 16 + lrow;
-      const T cs = (colscale && gn < N) ? T(colscale[gn / cell]) : T(1);
+      const T cs = (colscale && gn < N) ? T(colscale[gn >> cell_shift(cell)]) : T(1);
+      const int cl = (int)(gn - n0) >> cell_shift(cell), within = (int)(gn & (cell - 1));
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int t = m0 + wm0 + i * 16 + Mma<T>::row(lk, r);
@@ -496,7 +501,7 @@ __device__ __forceinline__ void oct_store(const typename Mma<T>::acc_t (&acc)[1 
         for (int q = 0; q < NCHI; ++q) {
           const long long row = oct_row<R>(om, t, q);
           long long col = gn;
-          if (pos) col = (long long)pos_s[flip_s[q][t - m0]][(int)((gn - n0) / cell)] * cell + (gn % cell);
+          if (pos) col = (long long)pos_s[flip_s[q][t - m0]][cl] * cell + within;
           const long long o = row * N + col;
           T v = y[q];
           if (colscale) v *= cs;
@@ -838,6 +843,7 @@ static void launch_shape(const T *A, const T *B, T *C, int M, int N, int K, hipS
 template <typename T>
 void launch_gemm(const T *A, const T *B, T *C, int M, int N, int K, hipStream_t st, const T *bias,
                  const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
+  if ((cell != 4 && cell != 8) || (pos && !rord)) throw std::runtime_error("GEMM: bad epilogue arguments");
   if (sizeof(T) == 8)
     launch_shape<T, 64, 128, 8, true, 4>(A, B, C, M, N, K, st, bias, colscale, cell, pos, rord);
   else
@@ -858,7 +864,7 @@ static void launch_oct_shape(const T *Bh, int ldb, const T *U, T *C, const OctMa
 template <typename T>
 void launch_gemm_oct(const T *Bh, int ldb, const T *U, T *C, const OctMap &om, int N, hipStream_t st, const T *bias,
                      const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
-  if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
+  if ((cell != 4 && cell != 8) || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
   const int nc = om.nc;
 #define TR_OCT(BM, BN, BK, WPE, DB, ALL)                                                                              \
   switch (om.R) {                                                                                                 \
@@ -903,6 +909,7 @@ void launch_split_rows(const float *A, int M, int K, void *out, hipStream_t st) 
 
 void launch_gemm_bf16x3(const void *Asplit, const float *B, float *C, int M, int N, int K, hipStream_t st,
                         const float *bias, const double *colscale, int cell, const int *pos, const OrdInfo *rord) {
+  if ((cell != 4 && cell != 8) || (pos && !rord)) throw std::runtime_error("GEMM: bad epilogue arguments");
   const int mblocks = (M + 127) / 128;
   const int nblocks = (int)(((long long)N + 127) / 128);
   const long long nb_pad = ((long long)nblocks + kXcds - 1) / kXcds * kXcds;
@@ -926,7 +933,7 @@ static void launch_oct_bf16_shape(const __bf16 *Bs, int kp, const float *U, floa
 void launch_gemm_oct_bf16x3(const void *Bsplit, int kp, const float *U, float *C, const OctMap &om, int N,
                             hipStream_t st, const float *bias, const double *colscale, int cell, const int *pos,
                             const OrdInfo *rord) {
-  if (cell < 4 || cell > 8 || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
+  if ((cell != 4 && cell != 8) || (pos && !rord)) throw std::runtime_error("octant-group GEMM: bad epilogue arguments");
   if (kp % 32 != 0 || kp < om.nc) throw std::runtime_error("octant-group GEMM: bad split block stride");
   const __bf16 *Bs = reinterpret_cast<const __bf16 *>(Bsplit);
   // tile 32 x 64 x 32, two waves per SIMD: measured on MI355X (three axes,
