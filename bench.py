@@ -10,8 +10,9 @@ levels at orders (8, 8, 8, 32), checkerboard of 8^3-cell blocks (sigma_t
 
 One step = one solve with the FP32 angular-multigrid preconditioner (FP32
 sweeps, scatter products and transfers on levels >= 1, FP64 coarsest
-level; V(1,4) cycle with 5 coarsest-level sweeps on the 48^3 problem,
---cycle to change it) inside FP64 flexible GMRES: every transport sweep, scatter product,
+level; V(1,6) cycle with one post-smoothing sweep on the levels between
+and 5 coarsest-level sweeps on the 48^3 problem, --cycle to change it)
+inside FP64 flexible GMRES: every transport sweep, scatter product,
 transfer, coarse Gauss-Seidel sweep, precision cast and Krylov update of
 the solve runs inside the timed region.  value = sweep DoF-updates per
 second of the whole solve (sum over all transport sweeps of ordinates x
@@ -192,9 +193,11 @@ def headline(args):
     # the V-cycle of the timed solves (FP32-MG and FP64 alike)
     if args.cycle != "problem":
         cyc = inputs.CFG3_CYCLE if args.cycle == "auto" and args.workload == "cfg3" else (
-            (prob.nu_pre, prob.nu_post, prob.nu_coarse) if args.cycle == "auto" else
+            (prob.nu_pre, prob.nu_post, prob.nu_coarse, prob.nu_post_coarse) if args.cycle == "auto" else
             tuple(int(v) for v in args.cycle.split(",")))
-        prob.nu_pre, prob.nu_post, prob.nu_coarse = cyc
+        if len(cyc) == 3:
+            cyc = cyc + (0,)
+        prob.nu_pre, prob.nu_post, prob.nu_coarse, prob.nu_post_coarse = cyc
     t_setup = time.perf_counter()
     tr = Transport(prob)
     b = tr.rhs()
@@ -260,9 +263,10 @@ def headline(args):
         "data": "synthetic",
         "config": {"workload": prob.name + ": " + (make.__doc__ or "").strip().replace("\n", " "),
                    "cells": tr.C, "spatial_dofs": tr.S, "angular_dofs": A, "dofs": dofs,
-                   "step": "one solve to 1e-8: FP64 flexible GMRES(%d) + FP32 angular MG V(%d,%d), FP64 coarsest "
-                           "level (%d Gauss-Seidel sweeps)" % (prob.restart, prob.nu_pre, prob.nu_post,
-                                                               prob.nu_coarse),
+                   "step": "one solve to 1e-8: FP64 flexible GMRES(%d) + FP32 angular MG V(%d,%d) (post-smoothing %d "
+                           "on the levels between), FP64 coarsest level (%d Gauss-Seidel sweeps)"
+                           % (prob.restart, prob.nu_pre, prob.nu_post, prob.nu_post_coarse or prob.nu_post,
+                              prob.nu_coarse),
                    "parallelism": "single GPU"},
         "time_to_tol_ms": {"fp32_mg": ms_step, "fp64_plain": ms64, "fp64_over_fp32_mg": ms64 / ms_step,
                            "fp32_mg_split_bf16": msb, "fp64_over_fp32_mg_split_bf16": ms64 / msb},
@@ -322,8 +326,9 @@ def main():
                          "the others a measurement line of their own (2-D square, 32^3 beam gradient, cone mesh)")
     ap.add_argument("--fd-cells", type=int, default=6, help="finite-difference cells for cfg4/cfg5")
     ap.add_argument("--cycle", default="auto",
-                    help="V-cycle of the timed solves as PRE,POST,COARSE sweeps; 'auto': the measured choice for "
-                         "cfg3 (inputs.CFG3_CYCLE), the problem's own otherwise; 'problem': the problem's own")
+                    help="V-cycle of the timed solves as PRE,POST,COARSE[,POST_BETWEEN] sweeps; 'auto': the "
+                         "measured choice for cfg3 (inputs.CFG3_CYCLE), the problem's own otherwise; 'problem': "
+                         "the problem's own")
     ap.add_argument("--oracle-timings", action="store_true",
                     help="only time the oracle on the host (sweep, scatter and V-cycle of the 2-D and 32^3 "
                          "problems, full solve of the 2-D problem)")

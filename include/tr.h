@@ -97,6 +97,8 @@ typedef struct {
   int nu_coarse;                /* Gauss-Seidel sweeps on T_0 (Section 5.2)      */
   int octant_order[8];          /* Gauss-Seidel octant order (a permutation)     */
   int angular_basis;            /* TR_BASIS_LIN or TR_BASIS_CONST (Section 2.2)  */
+  int nu_post_coarse;           /* post-smoothing sweeps on the levels below the  */
+                                /* finest (>= 0; 0: nu_post on every level)       */
 } tr_problem;
 
 /* Angular basis (Section 2.2).  LIN: the three nodal functions of a patch.

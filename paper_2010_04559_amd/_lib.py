@@ -30,7 +30,8 @@ class TrProblem(ctypes.Structure):
                 ("irregularity_closure", ctypes.c_int), ("band_lmax", ctypes.c_int), ("sigma_t", _dp), ("sigma_s", _dp),
                 ("order", ctypes.c_int), ("moments", _dp), ("n_levels", ctypes.c_int),
                 ("mg_order", _ip), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
-                ("nu_coarse", ctypes.c_int), ("octant_order", ctypes.c_int * 8), ("angular_basis", ctypes.c_int)]
+                ("nu_coarse", ctypes.c_int), ("octant_order", ctypes.c_int * 8), ("angular_basis", ctypes.c_int),
+                ("nu_post_coarse", ctypes.c_int)]
 
 
 class TrInfo(ctypes.Structure):

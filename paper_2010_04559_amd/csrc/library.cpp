@@ -415,7 +415,8 @@ void build(tr_handle *h, const tr_problem *p) {
   }
   if (p->order < 0 || p->order > 96) throw ArgError{"order out of range 0..96"};
   if (!p->moments || !p->sigma_t || !p->sigma_s || !p->mg_order) throw ArgError{"null array in problem"};
-  if (p->nu_pre < 1 || p->nu_post < 0 || p->nu_coarse < 1) throw ArgError{"need nu_pre >= 1, nu_post >= 0, nu_coarse >= 1"};
+  if (p->nu_pre < 1 || p->nu_post < 0 || p->nu_coarse < 1 || p->nu_post_coarse < 0)
+    throw ArgError{"need nu_pre >= 1, nu_post >= 0, nu_coarse >= 1, nu_post_coarse >= 0"};
   {
     int seen[8] = {0};
     for (int i = 0; i < 8; ++i) {
@@ -1229,7 +1230,8 @@ struct Coarse;
 template <typename T>
 void mg_level(tr_handle *h, int l, bool adj, hipStream_t st) {
   DevLevel &D = h->lv[l];
-  const int nu_pre = h->prob.nu_pre, nu_post = h->prob.nu_post;
+  const int nu_pre = h->prob.nu_pre;
+  const int nu_post = l < h->top() && h->prob.nu_post_coarse > 0 ? h->prob.nu_post_coarse : h->prob.nu_post;
   T *f = LevelBuf<T>::f(D), *u = LevelBuf<T>::u(D);
   T *sa = LevelBuf<T>::sa(D), *sb = LevelBuf<T>::sb(D);
   DevLevel &Dc = h->lv[l - 1];

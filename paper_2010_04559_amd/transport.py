@@ -47,6 +47,7 @@ def problem_struct(prob: Problem):
     p.n_levels = len(prob.mg_orders)
     p.mg_order = order.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     p.nu_pre, p.nu_post, p.nu_coarse = prob.nu_pre, prob.nu_post, prob.nu_coarse
+    p.nu_post_coarse = prob.nu_post_coarse
     if sorted(prob.octant_order) != list(range(8)):
         raise ValueError("octant_order must be a permutation of 0..7")
     for i in range(8):

@@ -139,7 +139,7 @@ def test_setup_rejects_level_count_mismatch():
 def test_setup_rejects_bad_smoothing_counts():
     from dataclasses import replace
     from paper_2010_04559_amd import _lib
-    for kw in ({"nu_pre": 0}, {"nu_post": -1}, {"nu_coarse": 0}):
+    for kw in ({"nu_pre": 0}, {"nu_post": -1}, {"nu_coarse": 0}, {"nu_post_coarse": -1}):
         rc, msg = _setup_rc(replace(_small(), **kw))
         assert rc == _lib.TR_ERR_ARG and "nu_" in msg
 

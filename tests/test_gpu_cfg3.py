@@ -202,7 +202,7 @@ def test_cfg3_bench_cycle(cfg3):
     tr.close()
     torch.cuda.empty_cache()
     pb = inputs.config3()
-    pb.nu_pre, pb.nu_post, pb.nu_coarse = inputs.CFG3_CYCLE
+    pb.nu_pre, pb.nu_post, pb.nu_coarse, pb.nu_post_coarse = inputs.CFG3_CYCLE
     tb = Transport(pb)
     try:
         b = tb.rhs()
@@ -210,8 +210,8 @@ def test_cfg3_bench_cycle(cfg3):
         assert stm["converged"] == 1 and stm["flexible"] == 32 and stm["iters"] <= 6
         x, st = tb.solve(b)
         assert st["converged"] == 1 and st["iters"] <= 6
-        print("bench cycle V(%d,%d)/%d: iterations fp32 %d, fp64 %d" % (pb.nu_pre, pb.nu_post, pb.nu_coarse,
-                                                                       stm["iters"], st["iters"]), flush=True)
+        print("bench cycle %s: iterations fp32 %d, fp64 %d" % (inputs.CFG3_CYCLE, stm["iters"], st["iters"]),
+              flush=True)
         d2 = 0.0
         for i in range(0, x.numel(), 1 << 27):
             t = xm[i:i + (1 << 27)] - x[i:i + (1 << 27)]
