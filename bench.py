@@ -240,6 +240,11 @@ def headline(args):
     sweep_kernel = tr.sweep_kernel_name(L, "f32")
     traffic = measured_traffic(args.workload, sweep_kernel, digest)
     ms_outer = accm["ms_scatter_outer"] / accm["n_scatter_outer"]
+    # the finest multigrid level's FP32 scatter products (the solve's
+    # largest kernel time with the benchmark cycle)
+    ms_mg = accm["ms_scatter_finest"] / max(1, accm["n_scatter_finest"])
+    fl_mg = tr.scatter_flops(L)
+    tf_mg = fl_mg / (ms_mg * 1e-3) / 1e12 if accm["n_scatter_finest"] else 0.0
     fl_outer = tr.scatter_flops(L, outer=True)
     tf_outer = fl_outer / (ms_outer * 1e-3) / 1e12
     # back-to-back launches of single kernels (the same kernels, outside a solve)
@@ -290,6 +295,13 @@ def headline(args):
                              "ms_per_launch": ms_outer, "launches": accm["n_scatter_outer"],
                              "flop_per_launch": fl_outer,
                              "dense_equivalent_tflops": 2.0 * A * A * tr.S / (ms_outer * 1e-3) / 1e12},
+        "roofline_scatter_mg": {"bound": "mfma", "achieved": tf_mg, "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
+                                "frac": tf_mg / FP32_PEAK_TFS,
+                                "kernel": "finest multigrid level's scatter, FP32 %s form"
+                                          % ("octant-block" if tr.scatter_forms[L][0] == "octant"
+                                             else tr.scatter_forms[L][0]),
+                                "ms_per_launch": ms_mg, "launches": accm["n_scatter_finest"],
+                                "flop_per_launch": fl_mg},
         "kernels_back_to_back": {
             "sweep_f64_ms": ms_sw64, "sweep_f64_dof_per_s": dofs / (ms_sw64 * 1e-3),
             "sweep_f64_hbm_frac": dofs * 16 / (ms_sw64 * 1e-3) / 1e9 / HBM_PEAK_GBS,

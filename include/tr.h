@@ -167,6 +167,8 @@ typedef struct {
   int flexible;                 /* preconditioned vectors kept: 64 / 32 (bits), 0 recomputed */
   double ms_scatter_outer;      /* time in the problem operator's scatter products */
   int n_scatter_outer;          /* (included in ms_scatter / n_scatter)            */
+  double ms_scatter_finest;     /* time in the finest multigrid level's scatter    */
+  int n_scatter_finest;         /* products (included in ms_scatter / n_scatter)   */
 } tr_solve_stats;
 
 /* Build the angular mesh, quadrature, level operators, prolongations and

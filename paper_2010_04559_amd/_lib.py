@@ -62,7 +62,8 @@ class TrSolveStats(ctypes.Structure):
                 ("n_coarse", ctypes.c_int), ("ms_sweep_finest", ctypes.c_double),
                 ("n_sweep_finest", ctypes.c_int), ("n_precond", ctypes.c_int),
                 ("sweep_dof_updates", ctypes.c_double), ("coarse_steps", ctypes.c_int),
-                ("flexible", ctypes.c_int), ("ms_scatter_outer", ctypes.c_double), ("n_scatter_outer", ctypes.c_int)]
+                ("flexible", ctypes.c_int), ("ms_scatter_outer", ctypes.c_double), ("n_scatter_outer", ctypes.c_int),
+                ("ms_scatter_finest", ctypes.c_double), ("n_scatter_finest", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

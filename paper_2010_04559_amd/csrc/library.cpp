@@ -153,7 +153,8 @@ struct TmpBuf {
   T *as() { return static_cast<T *>(p); }
 };
 
-enum { C_SWEEP = 0, C_SCATTER, C_TRANSFER, C_COARSE, C_APPLY, C_ORTH, C_OTHER, C_SWEEP_FINE, C_SCATTER_OUTER, C_N };
+enum { C_SWEEP = 0, C_SCATTER, C_TRANSFER, C_COARSE, C_APPLY, C_ORTH, C_OTHER, C_SWEEP_FINE, C_SCATTER_OUTER,
+       C_SCATTER_FINE, C_N };
 
 }  // namespace
 
@@ -943,8 +944,8 @@ void gemm(tr_handle *h, const T *A, const T *B, T *C, int M, int N, int K, hipSt
 // result (and the bias) are in plane layout for the level's ordinates.
 template <typename T>
 void do_gemm(tr_handle *h, const T *G, const T *x, T *y, int A, hipStream_t st, bool scale_sn = false,
-             const T *bias = nullptr, const OrdInfo *rord = nullptr) {
-  tbegin(h, C_SCATTER);
+             const T *bias = nullptr, const OrdInfo *rord = nullptr, int comp = C_SCATTER) {
+  tbegin(h, comp);
   gemm<T>(h, G, x, y, A, (int)h->g.S, A, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns,
           rord ? h->pos_pl : nullptr, rord);
   tend(h);
@@ -1188,9 +1189,10 @@ void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t 
                    const T *bias = nullptr, bool plane_out = false) {
   DevLevel &D = h->lv[l];
   const OrdInfo *rord = plane_out ? D.ord : nullptr;
+  const int comp = l == h->top() ? C_SCATTER_FINE : C_SCATTER;  // timer component
   if (D.symR) {
     // octant-group blocks
-    tbegin(h, C_SCATTER);
+    tbegin(h, comp);
     bool done = false;
     if constexpr (std::is_same<T, float>::value) {
       if (h->split32) {
@@ -1207,12 +1209,12 @@ void level_scatter(tr_handle *h, int l, bool adj, const T *u, T *y, hipStream_t 
     return;
   }
   if (!D.Kf) {
-    do_gemm<T>(h, LevelBuf<T>::G(D, adj), u, y, D.A, st, scale_sn, bias, rord);
+    do_gemm<T>(h, LevelBuf<T>::G(D, adj), u, y, D.A, st, scale_sn, bias, rord, comp);
     return;
   }
   T *tmp = LevelBuf<T>::fact(h);
   const int S = (int)h->g.S;
-  tbegin(h, C_SCATTER);
+  tbegin(h, comp);
   gemm<T>(h, LevelBuf<T>::Lf(D, adj), u, tmp, D.Kf, S, D.A, st);
   gemm<T>(h, LevelBuf<T>::Rf(D, adj), tmp, y, D.A, S, D.Kf, st, bias, scale_sn ? h->sig_s : nullptr, h->g.ns,
           rord ? h->pos_pl : nullptr, rord);
@@ -1729,6 +1731,8 @@ void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
   s->n_sweep_finest = 0;
   s->ms_scatter_outer = 0;
   s->n_scatter_outer = 0;
+  s->ms_scatter_finest = 0;
+  s->n_scatter_finest = 0;
   if (!h->timer) return;
   for (auto &r : h->timer->recs) {
     float ms = 0;
@@ -1739,6 +1743,9 @@ void fill_stats(tr_handle *h, tr_solve_stats *s, double ms_total) {
       case C_SCATTER: s->ms_scatter += ms; s->n_scatter++; break;
       case C_SCATTER_OUTER:
         s->ms_scatter += ms; s->n_scatter++; s->ms_scatter_outer += ms; s->n_scatter_outer++;
+        break;
+      case C_SCATTER_FINE:
+        s->ms_scatter += ms; s->n_scatter++; s->ms_scatter_finest += ms; s->n_scatter_finest++;
         break;
       case C_TRANSFER: s->ms_transfer += ms; break;
       case C_COARSE: s->ms_coarse += ms; s->n_coarse++; break;
